@@ -1,0 +1,175 @@
+/*
+ * mhd.h -- C ABI of the MI355X (gfx950) ideal-MHD update step.
+ *
+ * The library advances the ideal-MHD equations (1)-(5) of Pang, Pen &
+ * Perrone, "Magnetohydrodynamics on Heterogeneous architectures: a
+ * performance comparison" (arXiv:1004.1680), section II, on a periodic 3D
+ * grid with the scheme of section II.B: dimensionally split relaxing-TVD
+ * fluid sweeps (first-order upwind half step, van-Leer-limited full step)
+ * and constrained-transport advection of the face-centred field, applied in
+ * the order x, y, z, z, y, x.  Every step of the computation runs in HIP
+ * kernels on the device; the host only validates and enqueues.
+ *
+ * State layout.  8 fields, structure of arrays, field-major [f][k][j][i]
+ * with x fastest (section III: one array per component):
+ *   0 rho, 1 m_x, 2 m_y, 3 m_z, 4 e   at cell centres (e = total energy
+ *   density p/(gamma-1) + rho v^2/2 + b^2/2, section II.A),
+ *   5 b_x, 6 b_y, 7 b_z               b_d[c] = field through the LOW d-face
+ *                                     of cell c (b normalised by sqrt(4 pi)).
+ * The grid spacing is h = 1/nx on every axis.  Dimensions must be >= 8 and
+ * multiples of 4 (section III.B, aligned DMA); gamma > 1.
+ *
+ * Precision.  MHD_F32 keeps the state and the sweeps in float; MHD_F64 in
+ * double.  The CFL reduction, the diagnostics sums and the time are FP64 in
+ * both tiers.
+ *
+ * Relaxation speed.  The fluid sweeps use one relaxation (freezing) speed
+ * per step: the largest signal speed max_d |v_d| + c_fast found by the CFL
+ * function (section II.B, Jin & Xin relaxation; section IV.A, one CFL call
+ * per step).  mhd_cfl_dt sets it; mhd_set_relaxation_speed sets it
+ * explicitly; mhd_set_state invalidates it.
+ *
+ * Errors.  Functions returning int give MHD_OK (0) or a negative code;
+ * mhd_last_error() returns a thread-local message for the last failure.
+ * A HIP runtime error makes the handle sticky-failed: every later call on it
+ * returns MHD_ESTATE.  Kernels are asynchronous on the handle's stream;
+ * their faults surface at the next synchronising call.  A handle is not
+ * thread-safe; use one handle per thread or serialise the calls.
+ *
+ * Ownership.  The library owns the handle and its device buffers.  Host
+ * arrays passed in are read or written synchronously and stay the caller's.
+ * Device pointers passed in (mhd_*_device) stay the caller's and must be
+ * valid device memory on the handle's device.
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mhd_ctx mhd_ctx;
+
+enum {
+    MHD_OK = 0,
+    MHD_EINVAL = -1,     /* bad argument (sizes, dims, gamma, dt, null) */
+    MHD_ENOMEM = -2,     /* device allocation failed */
+    MHD_EDEVICE = -3,    /* HIP runtime error (handle becomes sticky-failed) */
+    MHD_ENONPHYS = -4,   /* rho <= 0, p < 0 or a non-finite value found */
+    MHD_ESTATE = -5      /* handle failed earlier, or relaxation speed unset */
+};
+
+enum { MHD_F32 = 0, MHD_F64 = 1 };
+
+/* Create a solver for an nx x ny x nz periodic grid (section II; grid of
+ * section III), FP32 tier, on the default stream.  Returns NULL on failure
+ * (message in mhd_last_error()).  The state is zero until mhd_set_state. */
+mhd_ctx *mhd_create(int nx, int ny, int nz, double gamma);
+
+/* As mhd_create, with precision tier prec (MHD_F32 / MHD_F64) and a HIP
+ * stream (hipStream_t passed as void*, NULL = default stream) on which every
+ * kernel of the handle is enqueued.  The stream must outlive the handle. */
+mhd_ctx *mhd_create_ex(int nx, int ny, int nz, double gamma, int prec,
+                       void *hip_stream);
+
+/* Free the handle and its device memory (synchronises its stream). */
+void mhd_destroy(mhd_ctx *h);
+
+/* Grid and tier of the handle: dims[3], precision; MHD_EINVAL on NULL. */
+int mhd_info(const mhd_ctx *h, int dims[3], int *prec);
+
+/* Copy a state in from host memory: n == 8*nx*ny*nz doubles in the layout
+ * above, converted to the handle's precision.  Synchronous.  Resets the
+ * time to 0 and invalidates the relaxation speed. */
+int mhd_set_state(mhd_ctx *h, const double *host, size_t n);
+
+/* Copy the state out to host memory as doubles (same layout).  Synchronous. */
+int mhd_get_state(mhd_ctx *h, double *host, size_t n);
+
+/* Device-to-device variants: src/dst hold n == 8*nx*ny*nz values of type
+ * float (prec MHD_F32) or double (MHD_F64) in the layout above, in device
+ * memory of the handle's device.  Enqueued on the handle's stream (no host
+ * synchronisation).  set resets time and relaxation speed like
+ * mhd_set_state. */
+int mhd_set_state_device(mhd_ctx *h, const void *src, size_t n, int prec);
+int mhd_get_state_device(mhd_ctx *h, void *dst, size_t n, int prec);
+
+/* CFL condition (section II.B; the CFL function of section IV.A):
+ * vmax = max over cells of max_d |v_d| + sqrt((gamma p + |Bbar|^2)/rho),
+ * Bbar the cell-centred mean of the two face values, p = (gamma-1)(e -
+ * m.m/(2 rho) - |Bbar|^2/2); dt = cfl * h / vmax (h = 1/nx).  FP64 on the
+ * device; synchronous.  Sets the relaxation speed to vmax.  Returns
+ * MHD_ENONPHYS (dt = 0) if any cell has rho <= 0, p < 0 or a non-finite
+ * value; MHD_EINVAL if cfl <= 0 or vmax == 0. */
+int mhd_cfl_dt(mhd_ctx *h, double cfl, double *dt_out);
+
+/* Set / read the relaxation speed c of the fluid sweeps (c > 0). */
+int mhd_set_relaxation_speed(mhd_ctx *h, double c);
+int mhd_get_relaxation_speed(const mhd_ctx *h, double *c);
+
+/* The two operators of a sweep along axis dim (0 x, 1 y, 2 z), each over a
+ * time dt > 0 (section II.B): the relaxing-TVD fluid update of rho, m, e with
+ * b frozen (equations (1)-(3), (6)), and the constrained-transport
+ * advection-constraint update of b with v frozen (equation (4)).
+ * Asynchronous.  The fluid operator needs a relaxation speed (MHD_ESTATE
+ * if none is set). */
+int mhd_fluid(mhd_ctx *h, int dim, double dt);
+int mhd_magnetic(mhd_ctx *h, int dim, double dt);
+
+/* One sweep (section II.B): dim 0,1,2 = fluid then magnetic along x, y, z;
+ * dim 3,4,5 = magnetic then fluid along x, y, z.  Asynchronous. */
+int mhd_sweep(mhd_ctx *h, int dim, double dt);
+
+/* Full step of 2*dt (section II.B; section IV.A): sweeps x, y, z, then
+ * z, y, x, i.e. F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x, every
+ * operator over dt.  Advances the time by 2*dt.  Asynchronous. */
+int mhd_step(mhd_ctx *h, double dt);
+
+/* CFL and full step with dt = cfl h / vmax kept on the device (no host
+ * synchronisation; the form a HIP graph can capture).  A non-physical state
+ * is recorded on the device and reported by the next mhd_status call (the
+ * step then leaves the state unchanged). */
+int mhd_step_auto(mhd_ctx *h, double cfl);
+
+/* Synchronise the handle's stream; report a non-physical state recorded by
+ * mhd_step_auto (MHD_ENONPHYS), then clear that record.  If steps_out is not
+ * NULL it receives the number of mhd_step_auto steps that ran. */
+int mhd_status(mhd_ctx *h, long long *steps_out);
+
+/* Simulated time (sum of 2*dt over all steps, FP64).  Synchronous. */
+int mhd_time(mhd_ctx *h, double *t);
+
+/* Diagnostics, FP64 on the device, synchronous: out[0..7] = h^3 * sum over
+ * cells of each field (conserved totals, section II.B), out[8] =
+ * max_c |sum_d (b_d[c+d] - b_d[c])| / max |b| (= max |div b| h / max |b|,
+ * equation (5)). */
+int mhd_diag(mhd_ctx *h, double out[9]);
+
+/* Restriction of a fine state onto a coarse grid whose sizes divide the fine
+ * ones by one integer factor r (8 for a 1024^3 -> 128^3 coarsening): coarse
+ * rho, m, e = mean over the r^3 fine cells; coarse b_d on a low d-face =
+ * mean of the r^2 fine face values tiling it.  Totals are kept and the
+ * coarse div b is the block mean of the fine one.  Both handles must be of
+ * the same precision and device; enqueued on the coarse handle's stream
+ * after the fine handle's stream is synchronised.  Resets the coarse time
+ * and relaxation speed. */
+int mhd_restrict(mhd_ctx *fine, mhd_ctx *coarse);
+
+/* Launch shape of the y and z sweep kernels: each lane walks one pencil
+ * along the sweep axis in chunks of `value` cells (value must divide the
+ * axis length and be >= 8; 0 restores the built-in choice).  key: MHD_TUNE_
+ * CHUNK_Y or MHD_TUNE_CHUNK_Z.  Results do not depend on the shape.  A
+ * launch-shape parameter, not part of the method. */
+enum { MHD_TUNE_CHUNK_Y = 1, MHD_TUNE_CHUNK_Z = 2 };
+int mhd_set_launch(mhd_ctx *h, int key, int value);
+int mhd_get_launch(const mhd_ctx *h, int key, int *value);
+
+/* Thread-local message describing the last error (never NULL). */
+const char *mhd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHD_H */

@@ -1,0 +1,395 @@
+// Reductions and data-movement kernels of the MHD library for gfx950:
+//  * the CFL condition (section II.B; the CFL function of section IV.A) as
+//    an FP64 max-reduction of the signal speed with wave64 shuffles;
+//  * conserved totals and the divergence diagnostic (FP64, fixed order, so
+//    the result is the same on every run);
+//  * host <-> device precision conversion, the restriction operator and the
+//    small scalar kernels that keep dt on the device.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mhd_kernels.h"
+
+namespace mhd {
+
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// CFL
+// ---------------------------------------------------------------------------
+
+int cfl_blocks(size_t ncell)
+{
+    size_t b = (ncell + RED_THREADS * 8 - 1) / (RED_THREADS * 8);
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// Signal speed max_d |v_d| + sqrt((gamma p + |Bbar|^2)/rho) of every cell in
+// FP64; per-block maximum and non-physical flag.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) cfl_partial_kernel(
+    const T* __restrict__ rho_, const T* __restrict__ mx_, const T* __restrict__ my_,
+    const T* __restrict__ mz_, const T* __restrict__ e_, const T* __restrict__ bx_,
+    const T* __restrict__ by_, const T* __restrict__ bz_, int nx, int ny, int nz, double gamma,
+    double* partial, int* partial_bad)
+{
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t sy = nx, sz = (size_t)nx * ny;
+    double vmax = 0.0;
+    int bad = 0;
+    for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < N;
+         c += (size_t)gridDim.x * RED_THREADS) {
+        const int i = (int)(c % nx);
+        const int j = (int)((c / sy) % ny);
+        const int k = (int)(c / sz);
+        const size_t cx = i + 1 == nx ? c - (nx - 1) : c + 1;
+        const size_t cy = j + 1 == ny ? c - (ny - 1) * sy : c + sy;
+        const size_t cz = k + 1 == nz ? c - (size_t)(nz - 1) * sz : c + sz;
+        const double rho = (double)rho_[c];
+        const double mx = (double)mx_[c], my = (double)my_[c], mz = (double)mz_[c];
+        const double e = (double)e_[c];
+        const double bx = 0.5 * ((double)bx_[c] + (double)bx_[cx]);
+        const double by = 0.5 * ((double)by_[c] + (double)by_[cy]);
+        const double bz = 0.5 * ((double)bz_[c] + (double)bz_[cz]);
+        const double b2 = bx * bx + by * by + bz * bz;
+        const double mm = mx * mx + my * my + mz * mz;
+        const double p = (gamma - 1.0) * (e - 0.5 * mm / rho - 0.5 * b2);
+        const double vx = fabs(mx / rho), vy = fabs(my / rho), vz = fabs(mz / rho);
+        double vm = vx > vy ? vx : vy;
+        vm = vm > vz ? vm : vz;
+        const double sp = vm + sqrt((gamma * p + b2) / rho);
+        if (!(rho > 0.0) || !(p >= 0.0) || !isfinite(sp) || !isfinite(e) || !isfinite(mm) ||
+            !isfinite(b2))
+            bad = 1;
+        else if (sp > vmax)
+            vmax = sp;
+    }
+    __shared__ double smax[RED_THREADS / 64];
+    __shared__ int sbad[RED_THREADS / 64];
+    vmax = wave_max(vmax);
+    bad = wave_or(bad);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { smax[w] = vmax; sbad[w] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = smax[0];
+        int b = sbad[0];
+        for (int q = 1; q < RED_THREADS / 64; ++q) { m = fmax(m, smax[q]); b |= sbad[q]; }
+        partial[blockIdx.x] = m;
+        partial_bad[blockIdx.x] = b;
+    }
+}
+
+// One block: final maximum; dt = cfl h / vmax.  A non-physical state
+// raises *flag (never cleared here) and writes dt = 0 without touching the
+// relaxation speed.
+__global__ void __launch_bounds__(RED_THREADS) cfl_final_kernel(
+    const double* partial, const int* partial_bad, int nblocks, int nx, double cfl, double* scal,
+    int* flag)
+{
+    double m = 0.0;
+    int bad = 0;
+    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS) {
+        m = fmax(m, partial[b]);
+        bad |= partial_bad[b];
+    }
+    __shared__ double smax[RED_THREADS / 64];
+    __shared__ int sbad[RED_THREADS / 64];
+    m = wave_max(m);
+    bad = wave_or(bad);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { smax[w] = m; sbad[w] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double vmax = smax[0];
+        int b = sbad[0];
+        for (int q = 1; q < RED_THREADS / 64; ++q) { vmax = fmax(vmax, smax[q]); b |= sbad[q]; }
+        if (b || !(vmax > 0.0)) {
+            scal[SCAL_DT] = 0.0;
+            scal[SCAL_VMAX] = 0.0;
+            flag[0] = b ? 1 : 2;
+        } else {
+            scal[SCAL_DT] = cfl * (1.0 / (double)nx) / vmax;
+            scal[SCAL_VMAX] = vmax;
+            scal[SCAL_C] = vmax;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_cfl(const T* const f[8], int nx, int ny, int nz, double gamma, double cfl,
+                      double* partial, int* partial_bad, int nblocks, double* scal, int* flag,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(cfl_partial_kernel<T>, dim3(nblocks), dim3(RED_THREADS), 0, s, f[0], f[1],
+                       f[2], f[3], f[4], f[5], f[6], f[7], nx, ny, nz, gamma, partial, partial_bad);
+    hipLaunchKernelGGL(cfl_final_kernel, dim3(1), dim3(RED_THREADS), 0, s, partial, partial_bad,
+                       nblocks, nx, cfl, scal, flag);
+    return hipGetLastError();
+}
+
+template hipError_t launch_cfl<float>(const float* const[8], int, int, int, double, double,
+                                      double*, int*, int, double*, int*, hipStream_t);
+template hipError_t launch_cfl<double>(const double* const[8], int, int, int, double, double,
+                                       double*, int*, int, double*, int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Diagnostics
+// ---------------------------------------------------------------------------
+
+int diag_blocks(size_t ncell)
+{
+    size_t b = (ncell + RED_THREADS * 16 - 1) / (RED_THREADS * 16);
+    if (b > 2048) b = 2048;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// partial[10 * block + q]: q < 8 field sums, 8 max |div b| (times h),
+// 9 max |b|.  Fixed assignment of cells to threads and a fixed tree: the
+// result does not depend on timing.
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) diag_partial_kernel(
+    const T* __restrict__ f0, const T* __restrict__ f1, const T* __restrict__ f2,
+    const T* __restrict__ f3, const T* __restrict__ f4, const T* __restrict__ bx_,
+    const T* __restrict__ by_, const T* __restrict__ bz_, int nx, int ny, int nz, double* partial)
+{
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t sy = nx, sz = (size_t)nx * ny;
+    double acc[8] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    double dmax = 0.0, bmax = 0.0;
+    for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < N;
+         c += (size_t)gridDim.x * RED_THREADS) {
+        const int i = (int)(c % nx);
+        const int j = (int)((c / sy) % ny);
+        const int k = (int)(c / sz);
+        const size_t cx = i + 1 == nx ? c - (nx - 1) : c + 1;
+        const size_t cy = j + 1 == ny ? c - (ny - 1) * sy : c + sy;
+        const size_t cz = k + 1 == nz ? c - (size_t)(nz - 1) * sz : c + sz;
+        const double bx = (double)bx_[c], by = (double)by_[c], bz = (double)bz_[c];
+        acc[0] += (double)f0[c];
+        acc[1] += (double)f1[c];
+        acc[2] += (double)f2[c];
+        acc[3] += (double)f3[c];
+        acc[4] += (double)f4[c];
+        acc[5] += bx;
+        acc[6] += by;
+        acc[7] += bz;
+        const double dv = ((double)bx_[cx] - bx) + ((double)by_[cy] - by) + ((double)bz_[cz] - bz);
+        dmax = fmax(dmax, fabs(dv));
+        bmax = fmax(bmax, fmax(fabs(bx), fmax(fabs(by), fabs(bz))));
+    }
+    __shared__ double red[10][RED_THREADS / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) red[q][w] = v;
+    }
+    dmax = wave_max(dmax);
+    bmax = wave_max(bmax);
+    if (lane == 0) { red[8][w] = dmax; red[9][w] = bmax; }
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const int q = threadIdx.x;
+        double v = red[q][0];
+        for (int ww = 1; ww < RED_THREADS / 64; ++ww)
+            v = q < 8 ? v + red[q][ww] : fmax(v, red[q][ww]);
+        partial[10 * blockIdx.x + q] = v;
+    }
+}
+
+__global__ void diag_final_kernel(const double* partial, int nblocks, double h3, double* out9)
+{
+    const int q = threadIdx.x;
+    if (q >= 10) return;
+    double v = partial[q];
+    for (int b = 1; b < nblocks; ++b) v = q < 8 ? v + partial[10 * b + q] : fmax(v, partial[10 * b + q]);
+    __shared__ double r[10];
+    r[q] = v;
+    __syncthreads();
+    if (q < 8) out9[q] = r[q] * h3;
+    if (q == 8) out9[8] = r[9] > 0.0 ? r[8] / r[9] : 0.0;
+}
+
+template <typename T>
+hipError_t launch_diag(const T* const f[8], int nx, int ny, int nz, double* partial, int nblocks,
+                       double* out9, hipStream_t s)
+{
+    const double h = 1.0 / (double)nx;
+    hipLaunchKernelGGL(diag_partial_kernel<T>, dim3(nblocks), dim3(RED_THREADS), 0, s, f[0], f[1],
+                       f[2], f[3], f[4], f[5], f[6], f[7], nx, ny, nz, partial);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partial, nblocks, h * h * h, out9);
+    return hipGetLastError();
+}
+template hipError_t launch_diag<float>(const float* const[8], int, int, int, double*, int, double*,
+                                       hipStream_t);
+template hipError_t launch_diag<double>(const double* const[8], int, int, int, double*, int,
+                                        double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Conversions
+// ---------------------------------------------------------------------------
+
+template <typename S, typename T>
+__global__ void cast_kernel(const S* __restrict__ src, T* __restrict__ dst, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = (T)src[i];
+}
+
+template <typename S, typename T>
+hipError_t launch_cast(const S* src, T* dst, size_t n, hipStream_t s)
+{
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((cast_kernel<S, T>), dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+template hipError_t launch_cast<double, float>(const double*, float*, size_t, hipStream_t);
+template hipError_t launch_cast<float, double>(const float*, double*, size_t, hipStream_t);
+template hipError_t launch_cast<float, float>(const float*, float*, size_t, hipStream_t);
+template hipError_t launch_cast<double, double>(const double*, double*, size_t, hipStream_t);
+
+template <typename T>
+hipError_t launch_convert_in(const double* src, T* dst, size_t n, hipStream_t s)
+{
+    return launch_cast<double, T>(src, dst, n, s);
+}
+template <typename T>
+hipError_t launch_convert_out(const T* src, double* dst, size_t n, hipStream_t s)
+{
+    return launch_cast<T, double>(src, dst, n, s);
+}
+template hipError_t launch_convert_in<float>(const double*, float*, size_t, hipStream_t);
+template hipError_t launch_convert_in<double>(const double*, double*, size_t, hipStream_t);
+template hipError_t launch_convert_out<float>(const float*, double*, size_t, hipStream_t);
+template hipError_t launch_convert_out<double>(const double*, double*, size_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Restriction
+// ---------------------------------------------------------------------------
+// One thread per coarse cell; consecutive threads take consecutive coarse x,
+// so the r consecutive fine values each thread reads per fine row join into
+// one contiguous run across the wave.  FP64 accumulation in a fixed order
+// (fine z, then y, then x; faces: first transverse, then second).
+
+template <typename T>
+__global__ void __launch_bounds__(256) restrict_kernel(
+    const T* f0, const T* f1, const T* f2, const T* f3, const T* f4, const T* g0, const T* g1,
+    const T* g2, T* o0, T* o1, T* o2, T* o3, T* o4, T* p0, T* p1, T* p2, int nx, int ny, int nz,
+    int r)
+{
+    const int cx = nx / r, cy = ny / r, cz = nz / r;
+    const size_t Nc = (size_t)cx * cy * cz;
+    const size_t C = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (C >= Nc) return;
+    const int I = (int)(C % cx), J = (int)((C / cx) % cy), K = (int)(C / ((size_t)cx * cy));
+    const T* fin[5] = { f0, f1, f2, f3, f4 };
+    T* fout[5] = { o0, o1, o2, o3, o4 };
+    const double rrr = (double)r * r * r;
+    for (int f = 0; f < 5; ++f) {
+        double acc = 0.0;
+        for (int k = 0; k < r; ++k)
+            for (int j = 0; j < r; ++j) {
+                const T* row = fin[f] + (size_t)r * I +
+                               (size_t)nx * ((size_t)(r * J + j) + (size_t)ny * (size_t)(r * K + k));
+                for (int i = 0; i < r; ++i) acc += (double)row[i];
+            }
+        fout[f][C] = (T)(acc / rrr);
+    }
+    const T* gin[3] = { g0, g1, g2 };
+    T* gout[3] = { p0, p1, p2 };
+    const double rr = (double)r * r;
+    for (int d = 0; d < 3; ++d) {
+        const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+        double acc = 0.0;
+        for (int u = 0; u < r; ++u)
+            for (int w = 0; w < r; ++w) {
+                int pp[3] = { r * I, r * J, r * K };
+                pp[t1] += u;
+                pp[t2] += w;
+                acc += (double)gin[d][(size_t)pp[0] + (size_t)nx * ((size_t)pp[1] + (size_t)ny * pp[2])];
+            }
+        gout[d][C] = (T)(acc / rr);
+    }
+}
+
+template <typename T>
+hipError_t launch_restrict(const T* const fine[8], T* const coarse[8], int nx, int ny, int nz,
+                           int r, hipStream_t s)
+{
+    const size_t Nc = (size_t)(nx / r) * (ny / r) * (nz / r);
+    const unsigned blocks = (unsigned)((Nc + 255) / 256);
+    hipLaunchKernelGGL(restrict_kernel<T>, dim3(blocks), dim3(256), 0, s, fine[0], fine[1], fine[2],
+                       fine[3], fine[4], fine[5], fine[6], fine[7], coarse[0], coarse[1], coarse[2],
+                       coarse[3], coarse[4], coarse[5], coarse[6], coarse[7], nx, ny, nz, r);
+    return hipGetLastError();
+}
+template hipError_t launch_restrict<float>(const float* const[8], float* const[8], int, int, int,
+                                           int, hipStream_t);
+template hipError_t launch_restrict<double>(const double* const[8], double* const[8], int, int,
+                                            int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Scalars
+// ---------------------------------------------------------------------------
+
+__global__ void set_scalars_kernel(double* scal, double dt, double c, int* flag, int clear_flag)
+{
+    if (threadIdx.x == 0) {
+        scal[SCAL_DT] = dt;
+        if (c > 0.0) scal[SCAL_C] = c;    // c <= 0: keep the device value
+        if (clear_flag) flag[0] = 0;
+    }
+}
+
+hipError_t launch_set_scalars(double* scal, double dt, double c, int* flag, int clear_flag,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(set_scalars_kernel, dim3(1), dim3(64), 0, s, scal, dt, c, flag, clear_flag);
+    return hipGetLastError();
+}
+
+// Time advance of one full step (2 dt) unless a non-physical state was
+// recorded (nonphys may be null); counts the steps that ran (steps may be
+// null).
+__global__ void advance_time_kernel(double* scal, const int* nonphys, int* steps)
+{
+    if (threadIdx.x == 0 && (nonphys == nullptr || *nonphys == 0)) {
+        scal[SCAL_TIME] += 2.0 * scal[SCAL_DT];
+        if (steps) *steps += 1;
+    }
+}
+
+hipError_t launch_advance_time(double* scal, const int* nonphys, int* steps, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_time_kernel, dim3(1), dim3(64), 0, s, scal, nonphys, steps);
+    return hipGetLastError();
+}
+
+}  // namespace mhd

@@ -1,0 +1,681 @@
+// Sweep kernels of the MHD update step for gfx950 (section II.B of Pang, Pen
+// & Perrone, arXiv:1004.1680): the relaxing-TVD fluid operator F_d and the
+// constrained-transport magnetic operator M_d along each axis d.
+//
+// Memory is structure of arrays with x fastest.  Two thread mappings keep
+// every global access coalesced without a global transpose:
+//  * x sweeps ("row" kernels): a row of the grid is contiguous; each thread
+//    owns 4 consecutive cells of a row and loads them with one vector load
+//    per field; stencil neighbours across threads go through LDS.  A
+//    workgroup holds whole rows, so the periodic wrap stays inside it.
+//  * y and z sweeps ("march" kernels): each lane owns one pencil along d;
+//    the 64 lanes of a wave sit on consecutive x, so every load and store of
+//    a wave is one contiguous run.  The lane walks along d keeping the
+//    stencil in a register window (the two-stage scheme needs 3 cells of
+//    look-ahead), so each input value is read once from memory.  A pencil
+//    may be cut into chunks along d; each chunk re-reads a 6-cell warm-up.
+// Neighbour pencils needed by the transverse field averages and by the
+// edge velocities of constrained transport are read directly; they are the
+// own data of adjacent lanes or adjacent workgroups and are served by the
+// L1/L2 caches.  Workgroup indices are remapped so that consecutive tiles
+// land on the same XCD (the hardware deals workgroups round-robin over the
+// 8 XCDs, each with its own L2).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mhd_device.h"
+#include "mhd_kernels.h"
+
+namespace mhd {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+// Remap the hardware workgroup id so that XCD k (which receives ids
+// k, k+8, k+16, ...) works on one contiguous range of logical tiles.
+__device__ __forceinline__ int xcd_tile(int nblocks)
+{
+    const int b = blockIdx.x;
+    const int per = nblocks >> 3;       // full rounds of 8
+    if (b >= (per << 3)) return b;      // tail: identity
+    return (b & 7) * per + (b >> 3);
+}
+
+template <typename T> struct vec4;
+template <> struct vec4<float> {
+    static __device__ __forceinline__ void load(const float* p, float o[4])
+    {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+    }
+    static __device__ __forceinline__ void store(float* p, const float o[4])
+    {
+        *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+    }
+};
+template <> struct vec4<double> {
+    static __device__ __forceinline__ void load(const double* p, double o[4])
+    {
+        const double2 a = reinterpret_cast<const double2*>(p)[0];
+        const double2 b = reinterpret_cast<const double2*>(p)[1];
+        o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+    }
+    static __device__ __forceinline__ void store(double* p, const double o[4])
+    {
+        reinterpret_cast<double2*>(p)[0] = make_double2(o[0], o[1]);
+        reinterpret_cast<double2*>(p)[1] = make_double2(o[2], o[3]);
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void step_scalars(const SweepParams<T>& P, T& tau, T& halftau, T& c)
+{
+    const double dt = P.scal[SCAL_DT];
+    tau = T(dt * (double)P.nx);          // dt / h with h = 1/nx
+    halftau = T(0.5) * tau;
+    c = T(P.scal[SCAL_C]);
+}
+
+// ---------------------------------------------------------------------------
+// x sweeps: row kernels
+// ---------------------------------------------------------------------------
+// Launch: blockDim = rows_per_wg * tpr threads (tpr = nx/4 threads per row),
+// grid = ceil(ny*nz / rows_per_wg) workgroups; dynamic LDS = 25 * blockDim
+// values of T (fluid) or 16 * blockDim (magnetic).
+
+template <typename T>
+__global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* const A = reinterpret_cast<T*>(smem_raw);          // 20 values / thread
+    T* const B = A + 20 * blockDim.x;                       // 5 values / thread
+    const int nt = blockDim.x;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int t = threadIdx.x;
+    const int rloc = t / tpr, tr = t - rloc * tpr;
+    const int row = xcd_tile(gridDim.x) * rows_per_wg + rloc;
+    const bool active = row < ny * nz;
+    const int y = active ? row % ny : 0, z = active ? row / ny : 0;
+    const int tprev = rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1);
+    const int tnext = rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1);
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t base = (size_t)nx * ((size_t)y + (size_t)ny * z);
+    const size_t base_yp = (size_t)nx * ((size_t)(y + 1 == ny ? 0 : y + 1) + (size_t)ny * z);
+    const size_t base_zp = (size_t)nx * ((size_t)y + (size_t)ny * (z + 1 == nz ? 0 : z + 1));
+    const int i0 = 4 * tr;
+
+    if (P.flag && *P.flag) {      // non-physical state recorded: keep the state
+        if (active)
+            for (int f = 0; f < 5; ++f) {
+                T v[4];
+                vec4<T>::load(P.in[f] + base + i0, v);
+                vec4<T>::store(P.out[f] + base + i0, v);
+            }
+        return;
+    }
+
+    T tau, halftau, c;
+    step_scalars(P, tau, halftau, c);
+    const T gamma = P.gamma;
+
+    T u[4][5], bb[4][3];
+    {
+        T tmp[4], tmp2[4];
+        for (int q = 0; q < 5; ++q) {
+            if (active) vec4<T>::load(P.in[q] + base + i0, tmp);
+            else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u[k][q] = tmp[k];
+        }
+        // Bbar_x: faces i and i+1 along the row
+        T bxn = T(0);
+        if (active) {
+            vec4<T>::load(P.in[BX] + base + i0, tmp);
+            bxn = P.in[BX][base + (i0 + 4 == nx ? 0 : i0 + 4)];
+        } else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bb[k][0] = T(0.5) * (tmp[k] + (k < 3 ? tmp[k + 1] : bxn));
+        // Bbar_y: faces at y and y+1; Bbar_z: faces at z and z+1
+        if (active) { vec4<T>::load(P.in[BY] + base + i0, tmp); vec4<T>::load(P.in[BY] + base_yp + i0, tmp2); }
+        else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bb[k][1] = T(0.5) * (tmp[k] + tmp2[k]);
+        if (active) { vec4<T>::load(P.in[BZ] + base + i0, tmp); vec4<T>::load(P.in[BZ] + base_zp + i0, tmp2); }
+        else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bb[k][2] = T(0.5) * (tmp[k] + tmp2[k]);
+    }
+
+    // stage 1: relaxed split and first-order upwind interface fluxes
+    T fr[4][5], fl[4][5];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) relax_split(u[k], bb[k], gamma, c, fr[k], fl[k]);
+    // LDS regions alternate A, B, A, B between the four exchanges: a region
+    // is rewritten only after the barrier that follows its last read.
+    // exchange 1: F^L of the first cell goes to the previous thread
+#pragma unroll
+    for (int q = 0; q < 5; ++q) A[q * nt + t] = fl[0][q];
+    __syncthreads();
+    T f1[4][5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T flnext = A[q * nt + tnext];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f1[k][q] = fr[k][q] - (k < 3 ? fl[k + 1][q] : flnext);
+    }
+    // exchange 2: interface flux of the last cell goes to the next thread
+#pragma unroll
+    for (int q = 0; q < 5; ++q) B[q * nt + t] = f1[3][q];
+    __syncthreads();
+    T uh[4][5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T f1prev = B[q * nt + tprev];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            uh[k][q] = u[k][q] - halftau * (f1[k][q] - (k > 0 ? f1[k - 1][q] : f1prev));
+    }
+
+    // stage 2: fluxes of the half-step state, van Leer limited
+#pragma unroll
+    for (int k = 0; k < 4; ++k) relax_split(uh[k], bb[k], gamma, c, fr[k], fl[k]);
+    // exchange 3: edge values of the stage-2 parts
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        A[(0 + q) * nt + t] = fr[3][q];     // last F^R -> next thread
+        A[(5 + q) * nt + t] = fr[0][q];     // first F^R -> previous thread
+        A[(10 + q) * nt + t] = fl[0][q];    // first two F^L -> previous thread
+        A[(15 + q) * nt + t] = fl[1][q];
+    }
+    __syncthreads();
+    T phi[4][5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T frprev = A[(0 + q) * nt + tprev];
+        const T frnext = A[(5 + q) * nt + tnext];
+        const T flnext0 = A[(10 + q) * nt + tnext];
+        const T flnext1 = A[(15 + q) * nt + tnext];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T rm = k > 0 ? fr[k - 1][q] : frprev;
+            const T rp = k < 3 ? fr[k + 1][q] : frnext;
+            const T lp = k < 3 ? fl[k + 1][q] : flnext0;
+            const T lpp = k < 2 ? fl[k + 2][q] : (k == 2 ? flnext0 : flnext1);
+            phi[k][q] = limited_right(rm, fr[k][q], rp) - limited_left(fl[k][q], lp, lpp);
+        }
+    }
+    // exchange 4: net flux of the last interface goes to the next thread
+#pragma unroll
+    for (int q = 0; q < 5; ++q) B[q * nt + t] = phi[3][q];
+    __syncthreads();
+    if (!active) return;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T phiprev = B[q * nt + tprev];
+        T o[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = u[k][q] - tau * (phi[k][q] - (k > 0 ? phi[k - 1][q] : phiprev));
+        vec4<T>::store(P.out[q] + base + i0, o);
+    }
+}
+
+// Magnetic sweep along x: e = y then z.  For each e two edge-flux chains
+// are evaluated: "own" (edges of this row, velocity from rows P and P-e)
+// and "plus" (edges of row P+e, velocity from rows P+e and P), the latter
+// for the constraint update of b_x.
+template <typename T>
+__global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* const A = reinterpret_cast<T*>(smem_raw);          // 12 values / thread
+    T* const B = A + 12 * blockDim.x;                       // 4 values / thread
+    const int nt = blockDim.x;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int t = threadIdx.x;
+    const int rloc = t / tpr, tr = t - rloc * tpr;
+    const int row = xcd_tile(gridDim.x) * rows_per_wg + rloc;
+    const bool active = row < ny * nz;
+    const int y = active ? row % ny : 0, z = active ? row / ny : 0;
+    const int tprev = rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1);
+    const int tnext = rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1);
+    const int i0 = 4 * tr;
+    const int inext = (i0 + 4 == nx) ? 0 : i0 + 4;
+    auto rbase = [&](int yy, int zz) -> size_t {
+        yy = wrapi(yy, ny); zz = wrapi(zz, nz);
+        return (size_t)nx * ((size_t)yy + (size_t)ny * zz);
+    };
+    const size_t b0 = rbase(y, z);
+
+    if (P.flag && *P.flag) {
+        if (active)
+            for (int f = BX; f <= BZ; ++f) {
+                T v[4];
+                vec4<T>::load(P.in[f] + b0 + i0, v);
+                vec4<T>::store(P.out[f] + b0 + i0, v);
+            }
+        return;
+    }
+    T tau, halftau, cdummy;
+    step_scalars(P, tau, halftau, cdummy);
+
+    // velocity v_x at 5 positions (i0..i0+4) of the rows P, P-y, P+y, P-z, P+z
+    // rows index: 0 P, 1 P-y, 2 P+y, 3 P-z, 4 P+z
+    T v[5][5];
+    {
+        const size_t rb[5] = { b0, rbase(y - 1, z), rbase(y + 1, z), rbase(y, z - 1), rbase(y, z + 1) };
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            T rho[4], m[4];
+            T rhon = T(1), mn = T(0);
+            if (active) {
+                vec4<T>::load(P.in[RHO] + rb[r] + i0, rho);
+                vec4<T>::load(P.in[MX] + rb[r] + i0, m);
+                rhon = P.in[RHO][rb[r] + inext];
+                mn = P.in[MX][rb[r] + inext];
+            } else {
+                rho[0] = rho[1] = rho[2] = rho[3] = T(1);
+                m[0] = m[1] = m[2] = m[3] = T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[r][k] = m[k] / rho[k];
+            v[r][4] = mn / rhon;
+        }
+    }
+    // chains: 0 own-y, 1 plus-y, 2 own-z, 3 plus-z
+    // velocity rows of each chain: (pencil, pencil - e)
+    const int vr0[4] = { 0, 2, 0, 4 };
+    const int vr1[4] = { 1, 0, 3, 0 };
+    T q[4][5];
+    {
+        const size_t qb[4] = { b0, rbase(y + 1, z), b0, rbase(y, z + 1) };
+        const int qf[4] = { BY, BY, BZ, BZ };
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            T tmp[4];
+            if (active) {
+                vec4<T>::load(P.in[qf[ch]] + qb[ch] + i0, tmp);
+                q[ch][4] = P.in[qf[ch]][qb[ch] + inext];
+            } else {
+                tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(0);
+                q[ch][4] = T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) q[ch][k] = tmp[k];
+        }
+    }
+    T a[4][4], g[4][4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        T w[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) w[k] = face_avg(v[vr0[ch]][k], v[vr1[ch]][k]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[ch][k] = edge_avg(w[k], w[k + 1]);
+            g[ch][k] = upwind_flux1(a[ch][k], q[ch][k], q[ch][k + 1]);
+        }
+    }
+    // exchange 1: last first-order flux -> next thread
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) B[ch * nt + t] = g[ch][3];
+    __syncthreads();
+    T qh[4][4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        const T gprev = B[ch * nt + tprev];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            qh[ch][k] = q[ch][k] - halftau * (g[ch][k] - (k > 0 ? g[ch][k - 1] : gprev));
+    }
+    // exchange 2: half-step values at the thread edges
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        A[(0 + ch) * nt + t] = qh[ch][3];
+        A[(4 + ch) * nt + t] = qh[ch][0];
+        A[(8 + ch) * nt + t] = qh[ch][1];
+    }
+    __syncthreads();
+    T f[4][4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        const T qm1 = A[(0 + ch) * nt + tprev];
+        const T qp0 = A[(4 + ch) * nt + tnext];
+        const T qp1 = A[(8 + ch) * nt + tnext];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T qm = k > 0 ? qh[ch][k - 1] : qm1;
+            const T q1 = k < 3 ? qh[ch][k + 1] : qp0;
+            const T q2 = k < 2 ? qh[ch][k + 2] : (k == 2 ? qp0 : qp1);
+            f[ch][k] = upwind_flux2(a[ch][k], qm, qh[ch][k], q1, q2);
+        }
+    }
+    // exchange 3: last edge flux -> next thread (region B was last read
+    // before the previous barrier)
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) B[ch * nt + t] = f[ch][3];
+    __syncthreads();
+    if (!active) return;
+    T fprev[4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) fprev[ch] = B[ch * nt + tprev];
+    T bx[4];
+    vec4<T>::load(P.in[BX] + b0 + i0, bx);
+    T oy[4], oz[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const T fo_y = k > 0 ? f[0][k - 1] : fprev[0];
+        const T fp_y = k > 0 ? f[1][k - 1] : fprev[1];
+        const T fo_z = k > 0 ? f[2][k - 1] : fprev[2];
+        const T fp_z = k > 0 ? f[3][k - 1] : fprev[3];
+        oy[k] = q[0][k] - tau * (f[0][k] - fo_y);
+        oz[k] = q[2][k] - tau * (f[2][k] - fo_z);
+        T b = bx[k] + tau * (fp_y - fo_y);
+        bx[k] = b + tau * (fp_z - fo_z);
+    }
+    vec4<T>::store(P.out[BY] + b0 + i0, oy);
+    vec4<T>::store(P.out[BZ] + b0 + i0, oz);
+    vec4<T>::store(P.out[BX] + b0 + i0, bx);
+}
+
+// ---------------------------------------------------------------------------
+// y and z sweeps: march kernels
+// ---------------------------------------------------------------------------
+// Lane -> pencil: p = x + nx * w over the transverse plane (w = z for a y
+// sweep, w = y for a z sweep); global lane id = chunk * npencil + p.
+// Launch: 256 threads, grid = ceil(npencil * nchunks / 256).
+
+template <int D> struct MarchGeom {
+    // axis strides and transverse neighbour offsets of the pencil at p
+    int nd;           // pencil length
+    size_t sd;        // stride along d
+    size_t base;      // offset of (pencil, 0)
+    size_t b_t1p, b_t2p, b_t1m, b_t2m;   // bases of pencils P+t1, P+t2, P-t1, P-t2
+    __device__ MarchGeom(int nx, int ny, int nz, int p)
+    {
+        const int x = p % nx, w = p / nx;
+        const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
+        if (D == 1) {           // n = y, t1 = z, t2 = x; w = z
+            const size_t sz = (size_t)nx * ny;
+            const int zp = w + 1 == nz ? 0 : w + 1, zm = w == 0 ? nz - 1 : w - 1;
+            nd = ny; sd = nx;
+            base = x + sz * w;
+            b_t1p = x + sz * zp;  b_t1m = x + sz * zm;
+            b_t2p = xp + sz * w;  b_t2m = xm + sz * w;
+        } else {                // n = z, t1 = x, t2 = y; w = y
+            const int yp = w + 1 == ny ? 0 : w + 1, ym = w == 0 ? ny - 1 : w - 1;
+            nd = nz; sd = (size_t)nx * ny;
+            base = x + (size_t)nx * w;
+            b_t1p = xp + (size_t)nx * w;  b_t1m = xm + (size_t)nx * w;
+            b_t2p = x + (size_t)nx * yp;  b_t2m = x + (size_t)nx * ym;
+        }
+    }
+};
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) fluid_march_kernel(SweepParams<T> P, int chunk)
+{
+    constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int npencil = nx * (D == 1 ? nz : ny);
+    const long gid = (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
+    const int nchunk = (D == 1 ? ny : nz) / chunk;
+    if (gid >= (long)npencil * nchunk) return;
+    const int p = (int)(gid % npencil);
+    const int j0 = (int)(gid / npencil) * chunk;
+    const MarchGeom<D> G(nx, ny, nz, p);
+    const int nd = G.nd;
+    const T* __restrict__ in_u[5] = { P.in[RHO], P.in[MX + N_], P.in[MX + T1], P.in[MX + T2], P.in[EN] };
+    T* out_u[5] = { P.out[RHO], P.out[MX + N_], P.out[MX + T1], P.out[MX + T2], P.out[EN] };
+    const T* __restrict__ bn = P.in[BX + N_];
+    const T* __restrict__ bt1 = P.in[BX + T1];
+    const T* __restrict__ bt2 = P.in[BX + T2];
+
+    if (P.flag && *P.flag) {
+        for (int j = j0; j < j0 + chunk; ++j) {
+            const size_t o = G.base + G.sd * j;
+            for (int q = 0; q < 5; ++q) out_u[q][o] = in_u[q][o];
+        }
+        return;
+    }
+    T tau, halftau, c;
+    step_scalars(P, tau, halftau, c);
+    const T gamma = P.gamma;
+
+    // register window (index relative to the look-ahead position L)
+    T u3[5], u2[5], u1[5], u0[5];    // U at L-3, L-2, L-1, L
+    T bbm[3], bb0[3];                 // Bbar at L-1, L
+    T frm[5];                         // stage-1 F^R at L-1
+    T f1m[5];                         // stage-1 interface flux at L-3/2
+    T r4[5], r3[5], r2[5];            // stage-2 F^R at L-4, L-3, L-2
+    T l3[5], l2[5];                   // stage-2 F^L at L-3, L-2
+    T phim[5];                        // net flux at interface (L-3)-1/2
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        u3[q] = u2[q] = u1[q] = T(0);
+        frm[q] = f1m[q] = r4[q] = r3[q] = r2[q] = l3[q] = l2[q] = phim[q] = T(0);
+    }
+    bbm[0] = bbm[1] = bbm[2] = T(0);
+    int jl = j0 - 3;
+    if (jl < 0) jl += nd;
+    T bn_cur = bn[G.base + G.sd * jl];          // b_n at L
+    for (int L = j0 - 3; L <= j0 + chunk + 2; ++L) {
+        const int jn = jl + 1 == nd ? 0 : jl + 1;
+        const size_t o = G.base + G.sd * jl;
+        const size_t on = G.base + G.sd * jn;
+        const size_t off = G.sd * jl;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) u0[q] = in_u[q][o];
+        const T bn_next = bn[on];
+        bb0[0] = T(0.5) * (bn_cur + bn_next);
+        bb0[1] = T(0.5) * (bt1[o] + bt1[G.b_t1p + off]);
+        bb0[2] = T(0.5) * (bt2[o] + bt2[G.b_t2p + off]);
+        bn_cur = bn_next;
+
+        // stage 1 at L: split, interface flux at L-1/2, half step at L-1
+        T fr0[5], fl0[5], f1[5], uh[5];
+        relax_split(u0, bb0, gamma, c, fr0, fl0);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            f1[q] = frm[q] - fl0[q];
+            uh[q] = u1[q] - halftau * (f1[q] - f1m[q]);
+        }
+        // stage 2 at L-1
+        T r1[5], l1[5];
+        relax_split(uh, bbm, gamma, c, r1, l1);
+        // net flux at interface (L-3)+1/2 and the update of cell L-3
+        const int j = L - 3;
+        T phi[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+            phi[q] = limited_right(r4[q], r3[q], r2[q]) - limited_left(l3[q], l2[q], l1[q]);
+        if (j >= j0) {
+            const size_t oj = G.base + G.sd * (size_t)(j >= nd ? j - nd : j);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) out_u[q][oj] = u3[q] - tau * (phi[q] - phim[q]);
+        }
+        // shift the window
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            phim[q] = phi[q];
+            r4[q] = r3[q]; r3[q] = r2[q]; r2[q] = r1[q];
+            l3[q] = l2[q]; l2[q] = l1[q];
+            frm[q] = fr0[q]; f1m[q] = f1[q];
+            u3[q] = u2[q]; u2[q] = u1[q]; u1[q] = u0[q];
+        }
+        bbm[0] = bb0[0]; bbm[1] = bb0[1]; bbm[2] = bb0[2];
+        jl = jn;
+    }
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) mag_march_kernel(SweepParams<T> P, int chunk)
+{
+    constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const int npencil = nx * (D == 1 ? nz : ny);
+    const long gid = (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
+    const int nchunk = (D == 1 ? ny : nz) / chunk;
+    if (gid >= (long)npencil * nchunk) return;
+    const int p = (int)(gid % npencil);
+    const int j0 = (int)(gid / npencil) * chunk;
+    const MarchGeom<D> G(nx, ny, nz, p);
+    const int nd = G.nd;
+    const T* __restrict__ rho = P.in[RHO];
+    const T* __restrict__ mn = P.in[MX + N_];
+    const T* __restrict__ bq1 = P.in[BX + T1];
+    const T* __restrict__ bq2 = P.in[BX + T2];
+    const T* __restrict__ bnin = P.in[BX + N_];
+
+    if (P.flag && *P.flag) {
+        for (int j = j0; j < j0 + chunk; ++j) {
+            const size_t o = G.base + G.sd * j;
+            P.out[BX][o] = P.in[BX][o];
+            P.out[BY][o] = P.in[BY][o];
+            P.out[BZ][o] = P.in[BZ][o];
+        }
+        return;
+    }
+    T tau, halftau, cdummy;
+    step_scalars(P, tau, halftau, cdummy);
+
+    // pencils: 0 P, 1 P-t1, 2 P+t1, 3 P-t2, 4 P+t2
+    const size_t pb[5] = { G.base, G.b_t1m, G.b_t1p, G.b_t2m, G.b_t2p };
+    // chains: 0 own-t1, 1 plus-t1, 2 own-t2, 3 plus-t2; velocity pencils
+    // (chain pencil, chain pencil - e), field q = b_e at the chain pencil
+    constexpr int vr0[4] = { 0, 2, 0, 4 };
+    constexpr int vr1[4] = { 1, 0, 3, 0 };
+    const size_t qb[4] = { G.base, G.b_t1p, G.base, G.b_t2p };
+
+    // register window, relative to the look-ahead position L at the start
+    // of a step; the edge flux f is produced for j = L-3
+    T wm[4];                 // face velocity at L-1
+    T a3[4], a2[4];          // edge velocity at L-3, L-2
+    T q3[4], q2[4], q1[4];   // q at L-3, L-2, L-1
+    T gm[4];                 // first-order flux at L-2
+    T h4[4], h3[4], h2[4];   // half-step q at L-4, L-3, L-2
+    T fm[4];                 // edge flux at L-4 (= j-1)
+    T bnw[3];                // b_n at L-3, L-2, L-1
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        wm[ch] = a3[ch] = a2[ch] = T(0);
+        q3[ch] = q2[ch] = q1[ch] = gm[ch] = h4[ch] = h3[ch] = h2[ch] = fm[ch] = T(0);
+    }
+    bnw[0] = bnw[1] = bnw[2] = T(0);
+    int jl = j0 - 3;
+    if (jl < 0) jl += nd;
+    for (int L = j0 - 3; L <= j0 + chunk + 2; ++L) {
+        const size_t off = G.sd * jl;
+        T v[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) v[r] = mn[pb[r] + off] / rho[pb[r] + off];
+        T q0[4];
+        q0[0] = bq1[qb[0] + off];
+        q0[1] = bq1[qb[1] + off];
+        q0[2] = bq2[qb[2] + off];
+        q0[3] = bq2[qb[3] + off];
+        const T bn0 = bnin[G.base + off];
+
+        T f[4];
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const T w0 = face_avg(v[vr0[ch]], v[vr1[ch]]);       // w at L
+            const T a1 = edge_avg(wm[ch], w0);                   // a at L-1
+            const T g1 = upwind_flux1(a1, q1[ch], q0[ch]);      // G1 at L-1
+            const T hq1 = q1[ch] - halftau * (g1 - gm[ch]);     // qh at L-1
+            // edge flux at j = L-3 from a(L-3) and qh at L-4..L-1
+            f[ch] = upwind_flux2(a3[ch], h4[ch], h3[ch], h2[ch], hq1);
+            // shift
+            wm[ch] = w0;
+            a3[ch] = a2[ch]; a2[ch] = a1;
+            gm[ch] = g1;
+            h4[ch] = h3[ch]; h3[ch] = h2[ch]; h2[ch] = hq1;
+        }
+        const int j = L - 3;
+        if (j >= j0) {
+            const size_t oj = G.base + G.sd * (size_t)(j >= nd ? j - nd : j);
+            // advection of b_t1, b_t2 on this pencil; constraint on b_n
+            P.out[BX + T1][oj] = q3[0] - tau * (f[0] - fm[0]);
+            P.out[BX + T2][oj] = q3[2] - tau * (f[2] - fm[2]);
+            const T b = bnw[0] + tau * (fm[1] - fm[0]);
+            P.out[BX + N_][oj] = b + tau * (fm[3] - fm[2]);
+        }
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            fm[ch] = f[ch];
+            q3[ch] = q2[ch]; q2[ch] = q1[ch]; q1[ch] = q0[ch];
+        }
+        bnw[0] = bnw[1]; bnw[1] = bnw[2]; bnw[2] = bn0;
+        jl = jl + 1 == nd ? 0 : jl + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static void row_shape(int nx, int& tpr, int& rows_per_wg, int& threads)
+{
+    tpr = nx / 4;
+    rows_per_wg = 256 / tpr;
+    if (rows_per_wg < 1) rows_per_wg = 1;
+    threads = rows_per_wg * tpr;
+}
+
+template <typename T>
+hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+{
+    if (d == 0) {
+        int tpr, rpw, threads;
+        row_shape<T>(P.nx, tpr, rpw, threads);
+        const int nrows = P.ny * P.nz;
+        const int grid = (nrows + rpw - 1) / rpw;
+        const size_t lds = sizeof(T) * 25 * threads;
+        hipLaunchKernelGGL(fluid_x_kernel<T>, dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+    } else {
+        const int nd = d == 1 ? P.ny : P.nz;
+        const int npencil = P.nx * (d == 1 ? P.nz : P.ny);
+        int chunk = tune.chunk[d];
+        if (chunk <= 0 || nd % chunk) chunk = nd;
+        const long lanes = (long)npencil * (nd / chunk);
+        const int grid = (int)((lanes + 255) / 256);
+        if (d == 1)
+            hipLaunchKernelGGL((fluid_march_kernel<T, 1>), dim3(grid), dim3(256), 0, s, P, chunk);
+        else
+            hipLaunchKernelGGL((fluid_march_kernel<T, 2>), dim3(grid), dim3(256), 0, s, P, chunk);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+{
+    if (d == 0) {
+        int tpr, rpw, threads;
+        row_shape<T>(P.nx, tpr, rpw, threads);
+        const int nrows = P.ny * P.nz;
+        const int grid = (nrows + rpw - 1) / rpw;
+        const size_t lds = sizeof(T) * 16 * threads;
+        hipLaunchKernelGGL(mag_x_kernel<T>, dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+    } else {
+        const int nd = d == 1 ? P.ny : P.nz;
+        const int npencil = P.nx * (d == 1 ? P.nz : P.ny);
+        int chunk = tune.chunk[d];
+        if (chunk <= 0 || nd % chunk) chunk = nd;
+        const long lanes = (long)npencil * (nd / chunk);
+        const int grid = (int)((lanes + 255) / 256);
+        if (d == 1)
+            hipLaunchKernelGGL((mag_march_kernel<T, 1>), dim3(grid), dim3(256), 0, s, P, chunk);
+        else
+            hipLaunchKernelGGL((mag_march_kernel<T, 2>), dim3(grid), dim3(256), 0, s, P, chunk);
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_fluid<float>(const SweepParams<float>&, int, const LaunchTuning&, hipStream_t);
+template hipError_t launch_fluid<double>(const SweepParams<double>&, int, const LaunchTuning&, hipStream_t);
+template hipError_t launch_magnetic<float>(const SweepParams<float>&, int, const LaunchTuning&, hipStream_t);
+template hipError_t launch_magnetic<double>(const SweepParams<double>&, int, const LaunchTuning&, hipStream_t);
+
+}  // namespace mhd

@@ -1,0 +1,308 @@
+"""Python binding of the HIP MHD library (``libmhd.so``, C ABI in include/mhd.h).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  If the library is missing this module raises on
+import of the library (``load()``); there is no CPU fallback.
+
+The functions ``mhd_*`` mirror the C ABI one to one.  ``Solver`` wraps a
+handle for numpy host arrays of shape ``(8, nz, ny, nx)`` (float64) and for
+torch device tensors (PyTorch is used only for device memory and streams).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhd.so")
+
+MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ENONPHYS, MHD_ESTATE = 0, -1, -2, -3, -4, -5
+MHD_F32, MHD_F64 = 0, 1
+MHD_TUNE_CHUNK_Y, MHD_TUNE_CHUNK_Z = 1, 2
+
+_lib = None
+
+
+class MHDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class NonPhysicalState(MHDError):
+    pass
+
+
+def load():
+    """Load libmhd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"HIP library {LIB_PATH} not built: run paper_1004_1680_amd/build.py "
+            "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "mhd_create": (vp, [i, i, i, d]),
+        "mhd_create_ex": (vp, [i, i, i, d, i, vp]),
+        "mhd_destroy": (None, [vp]),
+        "mhd_info": (i, [vp, ip, ip]),
+        "mhd_set_state": (i, [vp, dp, sz]),
+        "mhd_get_state": (i, [vp, dp, sz]),
+        "mhd_set_state_device": (i, [vp, vp, sz, i]),
+        "mhd_get_state_device": (i, [vp, vp, sz, i]),
+        "mhd_cfl_dt": (i, [vp, d, dp]),
+        "mhd_set_relaxation_speed": (i, [vp, d]),
+        "mhd_get_relaxation_speed": (i, [vp, dp]),
+        "mhd_fluid": (i, [vp, i, d]),
+        "mhd_magnetic": (i, [vp, i, d]),
+        "mhd_sweep": (i, [vp, i, d]),
+        "mhd_step": (i, [vp, d]),
+        "mhd_step_auto": (i, [vp, d]),
+        "mhd_status": (i, [vp, ctypes.POINTER(ctypes.c_longlong)]),
+        "mhd_time": (i, [vp, dp]),
+        "mhd_diag": (i, [vp, dp]),
+        "mhd_restrict": (i, [vp, vp]),
+        "mhd_set_launch": (i, [vp, i, i]),
+        "mhd_get_launch": (i, [vp, i, ip]),
+        "mhd_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return [l for l in ("mhd_create", "mhd_create_ex", "mhd_destroy", "mhd_info", "mhd_set_state",
+                        "mhd_get_state", "mhd_set_state_device", "mhd_get_state_device",
+                        "mhd_cfl_dt", "mhd_set_relaxation_speed", "mhd_get_relaxation_speed",
+                        "mhd_fluid", "mhd_magnetic", "mhd_sweep", "mhd_step", "mhd_step_auto",
+                        "mhd_status", "mhd_time", "mhd_diag", "mhd_restrict", "mhd_set_launch",
+                        "mhd_get_launch", "mhd_last_error")]
+
+
+def last_error():
+    return load().mhd_last_error().decode()
+
+
+def check(r):
+    if r != MHD_OK:
+        msg = last_error()
+        if r == MHD_ENONPHYS:
+            raise NonPhysicalState(r, msg)
+        raise MHDError(r, msg)
+    return r
+
+
+# --- one-to-one wrappers of the C ABI ---------------------------------------
+
+def mhd_create(nx, ny, nz, gamma):
+    return load().mhd_create(nx, ny, nz, gamma)
+
+
+def mhd_create_ex(nx, ny, nz, gamma, prec, stream=None):
+    return load().mhd_create_ex(nx, ny, nz, gamma, prec, stream)
+
+
+def mhd_destroy(h):
+    load().mhd_destroy(h)
+
+
+def mhd_set_state(h, host):
+    host = np.ascontiguousarray(host, dtype=np.float64)
+    return load().mhd_set_state(h, host.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), host.size)
+
+
+def mhd_get_state(h, out):
+    return load().mhd_get_state(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size)
+
+
+def mhd_cfl_dt(h, cfl):
+    dt = ctypes.c_double(0.0)
+    r = load().mhd_cfl_dt(h, cfl, ctypes.byref(dt))
+    return r, dt.value
+
+
+def mhd_fluid(h, dim, dt):
+    return load().mhd_fluid(h, dim, dt)
+
+
+def mhd_magnetic(h, dim, dt):
+    return load().mhd_magnetic(h, dim, dt)
+
+
+def mhd_sweep(h, dim, dt):
+    return load().mhd_sweep(h, dim, dt)
+
+
+def mhd_step(h, dt):
+    return load().mhd_step(h, dt)
+
+
+def mhd_step_auto(h, cfl):
+    return load().mhd_step_auto(h, cfl)
+
+
+def mhd_diag(h):
+    out = (ctypes.c_double * 9)()
+    r = load().mhd_diag(h, out)
+    return r, np.array(out[:])
+
+
+def mhd_restrict(fine, coarse):
+    return load().mhd_restrict(fine, coarse)
+
+
+# --- convenience handle ------------------------------------------------------
+
+def _torch_stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Solver:
+    """One periodic grid of n = (nx, ny, nz) cells on the current HIP device.
+
+    prec: "f32" or "f64".  stream: a torch.cuda.Stream (or raw handle) on
+    which every kernel is enqueued; None = the default stream."""
+
+    def __init__(self, n, gamma=5.0 / 3.0, prec="f32", stream=None):
+        self.lib = load()
+        self.n = tuple(int(v) for v in n)
+        self.gamma = float(gamma)
+        self.prec = {"f32": MHD_F32, "f64": MHD_F64}[prec]
+        self.h = self.lib.mhd_create_ex(self.n[0], self.n[1], self.n[2], self.gamma, self.prec,
+                                        _torch_stream(stream))
+        if not self.h:
+            raise MHDError(MHD_EINVAL, last_error())
+
+    def close(self):
+        if self.h:
+            self.lib.mhd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (8, self.n[2], self.n[1], self.n[0])
+
+    @property
+    def ncell(self):
+        return self.n[0] * self.n[1] * self.n[2]
+
+    def set_state(self, s):
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        if s.shape != self.shape:
+            raise ValueError(f"state shape {s.shape} != {self.shape}")
+        check(self.lib.mhd_set_state(self.h, s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     s.size))
+
+    def get_state(self):
+        out = np.empty(self.shape, dtype=np.float64)
+        check(self.lib.mhd_get_state(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     out.size))
+        return out
+
+    def set_state_tensor(self, t):
+        """t: contiguous torch CUDA tensor (float32 or float64) of shape self.shape"""
+        import torch
+        prec = MHD_F64 if t.dtype == torch.float64 else MHD_F32
+        assert t.is_cuda and t.is_contiguous() and tuple(t.shape) == self.shape
+        check(self.lib.mhd_set_state_device(self.h, ctypes.c_void_p(t.data_ptr()), t.numel(), prec))
+
+    def get_state_tensor(self, out=None, dtype=None):
+        import torch
+        if out is None:
+            dtype = dtype or (torch.float64 if self.prec == MHD_F64 else torch.float32)
+            out = torch.empty(self.shape, dtype=dtype, device="cuda")
+        prec = MHD_F64 if out.dtype == torch.float64 else MHD_F32
+        check(self.lib.mhd_get_state_device(self.h, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                            prec))
+        return out
+
+    def cfl_dt(self, cfl=0.7):
+        dt = ctypes.c_double(0.0)
+        check(self.lib.mhd_cfl_dt(self.h, cfl, ctypes.byref(dt)))
+        return dt.value
+
+    def set_relaxation_speed(self, c):
+        check(self.lib.mhd_set_relaxation_speed(self.h, c))
+
+    def relaxation_speed(self):
+        c = ctypes.c_double(0.0)
+        check(self.lib.mhd_get_relaxation_speed(self.h, ctypes.byref(c)))
+        return c.value
+
+    def fluid(self, dim, dt):
+        check(self.lib.mhd_fluid(self.h, dim, dt))
+
+    def magnetic(self, dim, dt):
+        check(self.lib.mhd_magnetic(self.h, dim, dt))
+
+    def sweep(self, code, dt):
+        check(self.lib.mhd_sweep(self.h, code, dt))
+
+    def step(self, dt):
+        check(self.lib.mhd_step(self.h, dt))
+
+    def step_auto(self, cfl=0.7):
+        check(self.lib.mhd_step_auto(self.h, cfl))
+
+    def status(self):
+        n = ctypes.c_longlong(0)
+        check(self.lib.mhd_status(self.h, ctypes.byref(n)))
+        return n.value
+
+    def time(self):
+        t = ctypes.c_double(0.0)
+        check(self.lib.mhd_time(self.h, ctypes.byref(t)))
+        return t.value
+
+    def diag(self):
+        out = (ctypes.c_double * 9)()
+        check(self.lib.mhd_diag(self.h, out))
+        return np.array(out[:])
+
+    def set_chunk(self, axis, value):
+        """march chunk length along axis 1 (y) or 2 (z); 0 = built-in"""
+        check(self.lib.mhd_set_launch(self.h, axis, value))
+
+    def chunk(self, axis):
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_get_launch(self.h, axis, ctypes.byref(v)))
+        return v.value
+
+    def restrict_to(self, coarse):
+        check(self.lib.mhd_restrict(self.h, coarse.h))
+
+    def run(self, nsteps, cfl=0.7, t_end=None):
+        """nsteps full steps, dt from the CFL condition before each (host
+        path).  With t_end, the last step is shortened to end exactly there.
+        Returns the list of dt."""
+        dts = []
+        t = 0.0
+        for _ in range(nsteps if t_end is None else 10 ** 9):
+            if t_end is not None and t >= t_end * (1 - 1e-14):
+                break
+            dt = self.cfl_dt(cfl)
+            if t_end is not None:
+                dt = min(dt, 0.5 * (t_end - t))
+            self.step(dt)
+            t += 2.0 * dt
+            dts.append(dt)
+        return dts
