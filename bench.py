@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.7)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -153,16 +155,22 @@ def main():
     ms_per_step = el * 1e3 / args.steps
     value = ncell * args.steps / el / 1e6
 
-    # per-kernel durations (HIP events on the solver's stream)
+    # per-kernel durations (HIP events on the solver's stream); the state is
+    # restored before each operator so that repeated launches with a frozen
+    # dt never run away from the CFL condition
     log("[bench] per-kernel timing")
-    dt = S.cfl_dt(args.cfl)
+    saved = S.get_state_tensor()
     kern = {}
     for op in ("fluid", "magnetic"):
         for d in range(3):
+            S.set_state_tensor(saved)
+            dt = S.cfl_dt(args.cfl) * 0.25
             ms = time_operator(S, op, d, dt, args.kernel_reps, stream, torch)
             gbs = ALG_WORDS[op] * esize * ncell / (ms * 1e-3) / 1e9
             kern[f"{op}_{'xyz'[d]}"] = {"ms": round(ms, 5), "alg_GBs": round(gbs, 1)}
     # CFL (partial + final reduction)
+    S.set_state_tensor(saved)
+    del saved
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -178,6 +186,19 @@ def main():
     op = dom.split("_")[0]
     bytes_per_launch = ALG_WORDS[op] * esize * ncell
     achieved = bytes_per_launch / (kern[dom]["ms"] * 1e-3) / 1e9
+    # measured HBM traffic of that kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE,
+    # copy-calibrated), valid only while the kernel sources are unchanged
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", f"sweeps_{args.workload}_{wl['prec']}_hbm_traffic.md".replace("_f32_", "_fp32_").replace("_f64_", "_fp64_"))
+    if not os.path.exists(tpath):
+        tpath = os.path.join(ROOT, "profiles", f"sweeps_{args.workload}_hbm_traffic.md")
+    from paper_1004_1680_amd.profile_summary import read_traffic
+    tmap = read_traffic(tpath)
+    tname = {"x": "{op}_x_kernel<{t}>", "y": "{op}_march_kernel<{t}, 1>",
+             "z": "{op}_march_kernel<{t}, 2>"}[dom[-1]].format(
+        op="fluid" if op == "fluid" else "mag", t="double" if esize == 8 else "float")
+    if tname in tmap:
+        traffic = tmap[tname]
     step_alg = STEP_WORDS * esize * ncell / (ms_per_step * 1e-3) / 1e9
 
     out = {
@@ -198,13 +219,21 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_cell": ALG_WORDS[op] * esize},
         "step_hbm_frac": round(step_alg / HBM_PEAK_GBS, 4),
         "kernels": kern,
         "steps_completed": nsteps_ok,
     }
     S.close()
+    if args.calibrate_copy:
+        # a plain copy kernel of known size: 1 GiB read + 1 GiB written
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -17,6 +17,38 @@ namespace mhd {
 enum { RHO = 0, MX = 1, MY = 2, MZ = 3, EN = 4, BX = 5, BY = 6, BZ = 7 };
 constexpr int NFIELD = 8;
 
+// Division policy of the two precision tiers.  FP64 divides with IEEE
+// rounding everywhere (the same rounding as a plain evaluation of each
+// formula).  FP32 multiplies by the hardware reciprocal (v_rcp_f32, within
+// 1 ulp), and takes one reciprocal of rho per cell: an FP32 IEEE division is
+// a ~10-instruction sequence and the sweeps would otherwise spend most of
+// their instructions on the 18 divisions per cell.
+template <typename T> struct Arith;
+template <> struct Arith<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float by_rho(float m, float rho, float inv) { return m * inv; }
+};
+template <> struct Arith<double> {
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double by_rho(double m, double rho, double) { return m / rho; }
+};
+
+// u - s d and u + s d: plain in FP64; one fused multiply-add in FP32.
+template <typename T>
+__device__ __forceinline__ T sub_scaled(T u, T s, T d)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(-s, d, u);
+    else return u - s * d;
+}
+template <typename T>
+__device__ __forceinline__ T add_scaled(T u, T s, T d)
+{
+    if constexpr (sizeof(T) == 4) return __builtin_fmaf(s, d, u);
+    else return u + s * d;
+}
+
 // Flux of equations (1)-(3) along the sweep axis with b frozen:
 // (m_n, m_n v_n + P* - Bn^2, m_t1 v_n - Bn Bt1, m_t2 v_n - Bn Bt2,
 //  (e + P*) v_n - Bn (B.v)), P* = p + b^2/2 (section II.A).
@@ -24,34 +56,62 @@ template <typename T>
 __device__ __forceinline__ void fluid_flux(const T u[5], const T bb[3], T gamma, T f[5])
 {
     const T rho = u[0], mn = u[1], mt1 = u[2], mt2 = u[3], e = u[4];
-    const T vn = mn / rho;
-    const T vt1 = mt1 / rho;
-    const T vt2 = mt2 / rho;
-    const T b2 = bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
-    const T mm = mn * mn + mt1 * mt1 + mt2 * mt2;
-    const T p = (gamma - T(1)) * (e - T(0.5) * mm / rho - T(0.5) * b2);
-    const T ptot = p + T(0.5) * b2;
-    const T bv = bb[0] * vn + bb[1] * vt1 + bb[2] * vt2;
-    f[0] = mn;
-    f[1] = mn * vn + ptot - bb[0] * bb[0];
-    f[2] = mt1 * vn - bb[0] * bb[1];
-    f[3] = mt2 * vn - bb[0] * bb[2];
-    f[4] = (e + ptot) * vn - bb[0] * bv;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: one reciprocal of rho; sums of products as fused multiply-adds
+        const float inv = Arith<float>::rcp(rho);
+        const float vn = mn * inv, vt1 = mt1 * inv, vt2 = mt2 * inv;
+        const float b2 = __builtin_fmaf(bb[2], bb[2], __builtin_fmaf(bb[1], bb[1], bb[0] * bb[0]));
+        const float ke = 0.5f * __builtin_fmaf(mt2, vt2, __builtin_fmaf(mt1, vt1, mn * vn));
+        const float p = (gamma - 1.0f) * (e - ke - 0.5f * b2);
+        const float ptot = __builtin_fmaf(0.5f, b2, p);
+        const float bv = __builtin_fmaf(bb[2], vt2, __builtin_fmaf(bb[1], vt1, bb[0] * vn));
+        f[0] = mn;
+        f[1] = __builtin_fmaf(mn, vn, ptot) - bb[0] * bb[0];
+        f[2] = __builtin_fmaf(mt1, vn, -bb[0] * bb[1]);
+        f[3] = __builtin_fmaf(mt2, vn, -bb[0] * bb[2]);
+        f[4] = __builtin_fmaf(e + ptot, vn, -bb[0] * bv);
+    } else {
+        const T vn = mn / rho;
+        const T vt1 = mt1 / rho;
+        const T vt2 = mt2 / rho;
+        const T b2 = bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
+        const T mm = mn * mn + mt1 * mt1 + mt2 * mt2;
+        const T p = (gamma - T(1)) * (e - T(0.5) * mm / rho - T(0.5) * b2);
+        const T ptot = p + T(0.5) * b2;
+        const T bv = bb[0] * vn + bb[1] * vt1 + bb[2] * vt2;
+        f[0] = mn;
+        f[1] = mn * vn + ptot - bb[0] * bb[0];
+        f[2] = mt1 * vn - bb[0] * bb[1];
+        f[3] = mt2 * vn - bb[0] * bb[2];
+        f[4] = (e + ptot) * vn - bb[0] * bv;
+    }
 }
 
 // Relaxed split of the flux into right- and left-moving parts with the
 // relaxation speed c (Jin & Xin relaxation, section II.B):
 // F^R = (c u + F)/2, F^L = (c u - F)/2.
+// The FP32 tier folds the factor 1/2 into c and F (exact scalings) so that
+// each part is one fused multiply-add.
 template <typename T>
 __device__ __forceinline__ void relax_split(const T u[5], const T bb[3], T gamma, T c,
                                             T fr[5], T fl[5])
 {
     T f[5];
     fluid_flux(u, bb, gamma, f);
+    if constexpr (sizeof(T) == 4) {
+        const T hc = T(0.5) * c;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        fr[q] = T(0.5) * (c * u[q] + f[q]);
-        fl[q] = T(0.5) * (c * u[q] - f[q]);
+        for (int q = 0; q < 5; ++q) {
+            const T hf = T(0.5) * f[q];
+            fr[q] = __builtin_fmaf(hc, u[q], hf);
+            fl[q] = __builtin_fmaf(hc, u[q], -hf);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            fr[q] = T(0.5) * (c * u[q] + f[q]);
+            fl[q] = T(0.5) * (c * u[q] - f[q]);
+        }
     }
 }
 
@@ -60,21 +120,55 @@ template <typename T>
 __device__ __forceinline__ T van_leer(T a, T b)
 {
     const T ab = a * b;
-    return ab > T(0) ? T(2) * ab / (a + b) : T(0);
+    return ab > T(0) ? Arith<T>::div(T(2) * ab, a + b) : T(0);
+}
+
+// velocity m / rho
+template <typename T>
+__device__ __forceinline__ T velocity(T m, T rho)
+{
+    return Arith<T>::div(m, rho);
+}
+
+// van Leer correction from two one-sided differences d1, d2 (not halved):
+// vl(d1/2, d2/2) = d1 d2 / (d1 + d2) when d1 d2 > 0.  The FP32 tier uses
+// this reduced form (3 fewer multiplications); the FP64 tier keeps the
+// halved differences of the plain formula.
+template <typename T>
+__device__ __forceinline__ T vl_half(T d1, T d2)
+{
+    if constexpr (sizeof(T) == 4) {
+        const T p = d1 * d2;
+        return p > T(0) ? p * Arith<T>::rcp(d1 + d2) : T(0);
+    } else {
+        return van_leer(T(0.5) * d1, T(0.5) * d2);
+    }
+}
+
+// x + vl_half(d1, d2), the correction added in one fused operation in FP32
+template <typename T>
+__device__ __forceinline__ T plus_vl_half(T x, T d1, T d2)
+{
+    if constexpr (sizeof(T) == 4) {
+        const T p = d1 * d2;
+        return p > T(0) ? __builtin_fmaf(p, Arith<T>::rcp(d1 + d2), x) : x;
+    } else {
+        return x + van_leer(T(0.5) * d1, T(0.5) * d2);
+    }
 }
 
 // Second-order right-moving part at interface i+1/2 from F^R at i-1, i, i+1.
 template <typename T>
 __device__ __forceinline__ T limited_right(T rm, T r0, T rp)
 {
-    return r0 + van_leer(T(0.5) * (r0 - rm), T(0.5) * (rp - r0));
+    return plus_vl_half(r0, r0 - rm, rp - r0);
 }
 
 // Second-order left-moving part at interface i+1/2 from F^L at i, i+1, i+2.
 template <typename T>
 __device__ __forceinline__ T limited_left(T l0, T lp, T lpp)
 {
-    return lp + van_leer(T(0.5) * (l0 - lp), T(0.5) * (lp - lpp));
+    return plus_vl_half(lp, l0 - lp, lp - lpp);
 }
 
 // Constrained transport (section II.B): edge velocity of v_d on the edge at
@@ -94,14 +188,17 @@ __device__ __forceinline__ T upwind_flux1(T a, T q0, T q1)
 }
 
 // qm = q(c-d), q0 = q(c), q1 = q(c+d), q2 = q(c+2d) of the half-step field.
+// Upwind cell c (a > 0): q0 + vl(q0 - qm, q1 - q0); upwind cell c+d
+// (a < 0): q1 + vl(q1 - q2, q0 - q1); times a.  The operands are selected
+// first (no divergent branch); a = 0 gives a signed zero.
 template <typename T>
 __device__ __forceinline__ T upwind_flux2(T a, T qm, T q0, T q1, T q2)
 {
-    if (a > T(0))
-        return a * (q0 + van_leer(T(0.5) * (q0 - qm), T(0.5) * (q1 - q0)));
-    if (a < T(0))
-        return a * (q1 + van_leer(T(0.5) * (q1 - q2), T(0.5) * (q0 - q1)));
-    return T(0);
+    const bool right = a > T(0);
+    const T up = right ? q0 : q1;
+    const T d1 = right ? q0 - qm : q1 - q2;
+    const T d2 = right ? q1 - q0 : q0 - q1;
+    return a * plus_vl_half(up, d1, d2);
 }
 
 // Index helpers for a periodic [nz][ny][nx] grid.

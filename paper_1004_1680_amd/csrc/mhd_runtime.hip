@@ -135,8 +135,8 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
             fail(MHD_EINVAL, "grid dimension %d = %d: must be >= 8 and a multiple of 4", d, n[d]);
             return nullptr;
         }
-    if (nx > 1024 || ny > 4096 || nz > 4096) {
-        fail(MHD_EINVAL, "grid dimension above the limit (nx <= 1024, ny, nz <= 4096)");
+    if (nx > 1024 || ny > 4096 || nz > 4096 || (long long)nx * ny * nz >= (1LL << 31)) {
+        fail(MHD_EINVAL, "grid above the limit (nx <= 1024, ny, nz <= 4096, < 2^31 cells)");
         return nullptr;
     }
     if (!(gamma > 1.0) || !isfinite(gamma)) {

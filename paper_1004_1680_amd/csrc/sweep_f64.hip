@@ -1,0 +1,9 @@
+// FP64 tier of the sweep kernels.  Built without contraction (see
+// build.py): every product and sum is rounded as written, with IEEE
+// division, which reproduces a plain evaluation of each formula.
+#include "sweep_kernels.h"
+
+namespace mhd {
+template hipError_t launch_fluid<double>(const SweepParams<double>&, int, const LaunchTuning&, hipStream_t);
+template hipError_t launch_magnetic<double>(const SweepParams<double>&, int, const LaunchTuning&, hipStream_t);
+}  // namespace mhd

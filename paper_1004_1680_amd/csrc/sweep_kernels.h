@@ -1,4 +1,4 @@
-// Sweep kernels of the MHD update step for gfx950 (section II.B of Pang, Pen
+// Sweep kernels (templates) of the MHD update step for gfx950 (section II.B of Pang, Pen
 // & Perrone, arXiv:1004.1680): the relaxing-TVD fluid operator F_d and the
 // constrained-transport magnetic operator M_d along each axis d.
 //
@@ -20,6 +20,7 @@
 // L1/L2 caches.  Workgroup indices are remapped so that consecutive tiles
 // land on the same XCD (the hardware deals workgroups round-robin over the
 // 8 XCDs, each with its own L2).
+#pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr,
         const T f1prev = B[q * nt + tprev];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            uh[k][q] = u[k][q] - halftau * (f1[k][q] - (k > 0 ? f1[k - 1][q] : f1prev));
+            uh[k][q] = sub_scaled(u[k][q], halftau, f1[k][q] - (k > 0 ? f1[k - 1][q] : f1prev));
     }
 
     // stage 2: fluxes of the half-step state, van Leer limited
@@ -215,7 +216,7 @@ __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr,
         const T phiprev = B[q * nt + tprev];
         T o[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = u[k][q] - tau * (phi[k][q] - (k > 0 ? phi[k - 1][q] : phiprev));
+        for (int k = 0; k < 4; ++k) o[k] = sub_scaled(u[k][q], tau, phi[k][q] - (k > 0 ? phi[k - 1][q] : phiprev));
         vec4<T>::store(P.out[q] + base + i0, o);
     }
 }
@@ -278,8 +279,8 @@ __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, i
                 m[0] = m[1] = m[2] = m[3] = T(0);
             }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[r][k] = m[k] / rho[k];
-            v[r][4] = mn / rhon;
+            for (int k = 0; k < 4; ++k) v[r][k] = velocity(m[k], rho[k]);
+            v[r][4] = velocity(mn, rhon);
         }
     }
     // chains: 0 own-y, 1 plus-y, 2 own-z, 3 plus-z
@@ -326,7 +327,7 @@ __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, i
         const T gprev = B[ch * nt + tprev];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            qh[ch][k] = q[ch][k] - halftau * (g[ch][k] - (k > 0 ? g[ch][k - 1] : gprev));
+            qh[ch][k] = sub_scaled(q[ch][k], halftau, g[ch][k] - (k > 0 ? g[ch][k - 1] : gprev));
     }
     // exchange 2: half-step values at the thread edges
 #pragma unroll
@@ -368,10 +369,10 @@ __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, i
         const T fp_y = k > 0 ? f[1][k - 1] : fprev[1];
         const T fo_z = k > 0 ? f[2][k - 1] : fprev[2];
         const T fp_z = k > 0 ? f[3][k - 1] : fprev[3];
-        oy[k] = q[0][k] - tau * (f[0][k] - fo_y);
-        oz[k] = q[2][k] - tau * (f[2][k] - fo_z);
-        T b = bx[k] + tau * (fp_y - fo_y);
-        bx[k] = b + tau * (fp_z - fo_z);
+        oy[k] = sub_scaled(q[0][k], tau, f[0][k] - fo_y);
+        oz[k] = sub_scaled(q[2][k], tau, f[2][k] - fo_z);
+        T b = add_scaled(bx[k], tau, fp_y - fo_y);
+        bx[k] = add_scaled(b, tau, fp_z - fo_z);
     }
     vec4<T>::store(P.out[BY] + b0 + i0, oy);
     vec4<T>::store(P.out[BZ] + b0 + i0, oz);
@@ -383,20 +384,25 @@ __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, i
 // ---------------------------------------------------------------------------
 // Lane -> pencil: p = x + nx * w over the transverse plane (w = z for a y
 // sweep, w = y for a z sweep); global lane id = chunk * npencil + p.
-// Launch: 256 threads, grid = ceil(npencil * nchunks / 256).
+// Launch: 256 threads, grid = ceil(npencil * nchunks / 256).  The state has
+// fewer than 2^31 cells per field, so offsets are 32-bit.
+//
+// The march runs in groups of U positions whose body is unrolled, so the
+// register window moves by renaming instead of copying; the start is moved
+// back by up to U-1 extra warm-up positions to make the count a multiple of
+// U (positions before the chunk produce no output).
 
 template <int D> struct MarchGeom {
-    // axis strides and transverse neighbour offsets of the pencil at p
-    int nd;           // pencil length
-    size_t sd;        // stride along d
-    size_t base;      // offset of (pencil, 0)
-    size_t b_t1p, b_t2p, b_t1m, b_t2m;   // bases of pencils P+t1, P+t2, P-t1, P-t2
+    int nd;              // pencil length
+    unsigned sd;         // stride along d
+    unsigned base;       // offset of (pencil, 0)
+    unsigned b_t1p, b_t2p, b_t1m, b_t2m;   // bases of pencils P+t1, P+t2, P-t1, P-t2
     __device__ MarchGeom(int nx, int ny, int nz, int p)
     {
         const int x = p % nx, w = p / nx;
         const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
         if (D == 1) {           // n = y, t1 = z, t2 = x; w = z
-            const size_t sz = (size_t)nx * ny;
+            const unsigned sz = (unsigned)nx * ny;
             const int zp = w + 1 == nz ? 0 : w + 1, zm = w == 0 ? nz - 1 : w - 1;
             nd = ny; sd = nx;
             base = x + sz * w;
@@ -404,13 +410,24 @@ template <int D> struct MarchGeom {
             b_t2p = xp + sz * w;  b_t2m = xm + sz * w;
         } else {                // n = z, t1 = x, t2 = y; w = y
             const int yp = w + 1 == ny ? 0 : w + 1, ym = w == 0 ? ny - 1 : w - 1;
-            nd = nz; sd = (size_t)nx * ny;
-            base = x + (size_t)nx * w;
-            b_t1p = xp + (size_t)nx * w;  b_t1m = xm + (size_t)nx * w;
-            b_t2p = x + (size_t)nx * yp;  b_t2m = x + (size_t)nx * ym;
+            nd = nz; sd = (unsigned)nx * ny;
+            base = x + (unsigned)nx * w;
+            b_t1p = xp + (unsigned)nx * w;  b_t1m = xm + (unsigned)nx * w;
+            b_t2p = x + (unsigned)nx * yp;  b_t2m = x + (unsigned)nx * ym;
         }
     }
 };
+
+// positions unrolled per group: 4 in FP32; 2 in FP64, whose window takes
+// twice the registers
+template <typename T> constexpr int march_unroll() { return sizeof(T) == 4 ? 4 : 2; }
+
+template <int U>
+__device__ __forceinline__ int march_start(int j0, int chunk)
+{
+    const int total = chunk + 6;
+    return j0 - 3 - ((U - (total % U)) % U);
+}
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256) fluid_march_kernel(SweepParams<T> P, int chunk)
@@ -433,7 +450,7 @@ __global__ void __launch_bounds__(256) fluid_march_kernel(SweepParams<T> P, int 
 
     if (P.flag && *P.flag) {
         for (int j = j0; j < j0 + chunk; ++j) {
-            const size_t o = G.base + G.sd * j;
+            const unsigned o = G.base + G.sd * j;
             for (int q = 0; q < 5; ++q) out_u[q][o] = in_u[q][o];
         }
         return;
@@ -443,8 +460,8 @@ __global__ void __launch_bounds__(256) fluid_march_kernel(SweepParams<T> P, int 
     const T gamma = P.gamma;
 
     // register window (index relative to the look-ahead position L)
-    T u3[5], u2[5], u1[5], u0[5];    // U at L-3, L-2, L-1, L
-    T bbm[3], bb0[3];                 // Bbar at L-1, L
+    T u3[5], u2[5], u1[5];            // U at L-3, L-2, L-1
+    T bbm[3];                         // Bbar at L-1
     T frm[5];                         // stage-1 F^R at L-1
     T f1m[5];                         // stage-1 interface flux at L-3/2
     T r4[5], r3[5], r2[5];            // stage-2 F^R at L-4, L-3, L-2
@@ -456,55 +473,74 @@ __global__ void __launch_bounds__(256) fluid_march_kernel(SweepParams<T> P, int 
         frm[q] = f1m[q] = r4[q] = r3[q] = r2[q] = l3[q] = l2[q] = phim[q] = T(0);
     }
     bbm[0] = bbm[1] = bbm[2] = T(0);
-    int jl = j0 - 3;
-    if (jl < 0) jl += nd;
+    constexpr int U = march_unroll<T>();
+    const int Lstart = march_start<U>(j0, chunk);
+    int jl = Lstart < 0 ? Lstart + nd : Lstart;
     T bn_cur = bn[G.base + G.sd * jl];          // b_n at L
-    for (int L = j0 - 3; L <= j0 + chunk + 2; ++L) {
-        const int jn = jl + 1 == nd ? 0 : jl + 1;
-        const size_t o = G.base + G.sd * jl;
-        const size_t on = G.base + G.sd * jn;
-        const size_t off = G.sd * jl;
+    // inputs of the next position, loaded one step ahead so that their
+    // latency overlaps the arithmetic of the current step
+    T nu[5], nbn, nt1a, nt1b, nt2a, nt2b;
+    auto prefetch = [&](int jpos) {
+        const int jn = jpos + 1 == nd ? 0 : jpos + 1;
+        const unsigned off = G.sd * jpos;
+        const unsigned o = G.base + off;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) u0[q] = in_u[q][o];
-        const T bn_next = bn[on];
-        bb0[0] = T(0.5) * (bn_cur + bn_next);
-        bb0[1] = T(0.5) * (bt1[o] + bt1[G.b_t1p + off]);
-        bb0[2] = T(0.5) * (bt2[o] + bt2[G.b_t2p + off]);
-        bn_cur = bn_next;
+        for (int q = 0; q < 5; ++q) nu[q] = in_u[q][o];
+        nbn = bn[G.base + G.sd * jn];
+        nt1a = bt1[o];
+        nt1b = bt1[G.b_t1p + off];
+        nt2a = bt2[o];
+        nt2b = bt2[G.b_t2p + off];
+    };
+    prefetch(jl);
+    for (int L0 = Lstart; L0 <= j0 + chunk + 2; L0 += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int L = L0 + k;
+            T u0[5], bb0[3];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) u0[q] = nu[q];
+            const T bn_next = nbn;
+            bb0[0] = T(0.5) * (bn_cur + bn_next);
+            bb0[1] = T(0.5) * (nt1a + nt1b);
+            bb0[2] = T(0.5) * (nt2a + nt2b);
+            bn_cur = bn_next;
+            jl = jl + 1 == nd ? 0 : jl + 1;
+            prefetch(jl);
 
-        // stage 1 at L: split, interface flux at L-1/2, half step at L-1
-        T fr0[5], fl0[5], f1[5], uh[5];
-        relax_split(u0, bb0, gamma, c, fr0, fl0);
+            // stage 1 at L: split, interface flux at L-1/2, half step at L-1
+            T fr0[5], fl0[5], f1[5], uh[5];
+            relax_split(u0, bb0, gamma, c, fr0, fl0);
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            f1[q] = frm[q] - fl0[q];
-            uh[q] = u1[q] - halftau * (f1[q] - f1m[q]);
+            for (int q = 0; q < 5; ++q) {
+                f1[q] = frm[q] - fl0[q];
+                uh[q] = sub_scaled(u1[q], halftau, f1[q] - f1m[q]);
+            }
+            // stage 2 at L-1
+            T r1[5], l1[5];
+            relax_split(uh, bbm, gamma, c, r1, l1);
+            // net flux at interface (L-3)+1/2 and the update of cell L-3
+            const int j = L - 3;
+            T phi[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                phi[q] = limited_right(r4[q], r3[q], r2[q]) - limited_left(l3[q], l2[q], l1[q]);
+            if (j >= j0) {
+                const unsigned oj = G.base + G.sd * (unsigned)j;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) out_u[q][oj] = sub_scaled(u3[q], tau, phi[q] - phim[q]);
+            }
+            // shift the window
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                phim[q] = phi[q];
+                r4[q] = r3[q]; r3[q] = r2[q]; r2[q] = r1[q];
+                l3[q] = l2[q]; l2[q] = l1[q];
+                frm[q] = fr0[q]; f1m[q] = f1[q];
+                u3[q] = u2[q]; u2[q] = u1[q]; u1[q] = u0[q];
+            }
+            bbm[0] = bb0[0]; bbm[1] = bb0[1]; bbm[2] = bb0[2];
         }
-        // stage 2 at L-1
-        T r1[5], l1[5];
-        relax_split(uh, bbm, gamma, c, r1, l1);
-        // net flux at interface (L-3)+1/2 and the update of cell L-3
-        const int j = L - 3;
-        T phi[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q)
-            phi[q] = limited_right(r4[q], r3[q], r2[q]) - limited_left(l3[q], l2[q], l1[q]);
-        if (j >= j0) {
-            const size_t oj = G.base + G.sd * (size_t)(j >= nd ? j - nd : j);
-#pragma unroll
-            for (int q = 0; q < 5; ++q) out_u[q][oj] = u3[q] - tau * (phi[q] - phim[q]);
-        }
-        // shift the window
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            phim[q] = phi[q];
-            r4[q] = r3[q]; r3[q] = r2[q]; r2[q] = r1[q];
-            l3[q] = l2[q]; l2[q] = l1[q];
-            frm[q] = fr0[q]; f1m[q] = f1[q];
-            u3[q] = u2[q]; u2[q] = u1[q]; u1[q] = u0[q];
-        }
-        bbm[0] = bb0[0]; bbm[1] = bb0[1]; bbm[2] = bb0[2];
-        jl = jn;
     }
 }
 
@@ -529,7 +565,7 @@ __global__ void __launch_bounds__(256) mag_march_kernel(SweepParams<T> P, int ch
 
     if (P.flag && *P.flag) {
         for (int j = j0; j < j0 + chunk; ++j) {
-            const size_t o = G.base + G.sd * j;
+            const unsigned o = G.base + G.sd * j;
             P.out[BX][o] = P.in[BX][o];
             P.out[BY][o] = P.in[BY][o];
             P.out[BZ][o] = P.in[BZ][o];
@@ -540,12 +576,12 @@ __global__ void __launch_bounds__(256) mag_march_kernel(SweepParams<T> P, int ch
     step_scalars(P, tau, halftau, cdummy);
 
     // pencils: 0 P, 1 P-t1, 2 P+t1, 3 P-t2, 4 P+t2
-    const size_t pb[5] = { G.base, G.b_t1m, G.b_t1p, G.b_t2m, G.b_t2p };
+    const unsigned pb[5] = { G.base, G.b_t1m, G.b_t1p, G.b_t2m, G.b_t2p };
     // chains: 0 own-t1, 1 plus-t1, 2 own-t2, 3 plus-t2; velocity pencils
     // (chain pencil, chain pencil - e), field q = b_e at the chain pencil
     constexpr int vr0[4] = { 0, 2, 0, 4 };
     constexpr int vr1[4] = { 1, 0, 3, 0 };
-    const size_t qb[4] = { G.base, G.b_t1p, G.base, G.b_t2p };
+    const unsigned qb[4] = { G.base, G.b_t1p, G.base, G.b_t2p };
 
     // register window, relative to the look-ahead position L at the start
     // of a step; the edge flux f is produced for j = L-3
@@ -562,51 +598,69 @@ __global__ void __launch_bounds__(256) mag_march_kernel(SweepParams<T> P, int ch
         q3[ch] = q2[ch] = q1[ch] = gm[ch] = h4[ch] = h3[ch] = h2[ch] = fm[ch] = T(0);
     }
     bnw[0] = bnw[1] = bnw[2] = T(0);
-    int jl = j0 - 3;
-    if (jl < 0) jl += nd;
-    for (int L = j0 - 3; L <= j0 + chunk + 2; ++L) {
-        const size_t off = G.sd * jl;
-        T v[5];
+    constexpr int U = march_unroll<T>();
+    const int Lstart = march_start<U>(j0, chunk);
+    int jl = Lstart < 0 ? Lstart + nd : Lstart;
+    // inputs of the next position, loaded one step ahead
+    T nrho[5], nm[5], nq[4], nbn;
+    auto prefetch = [&](int jpos) {
+        const unsigned off = G.sd * jpos;
 #pragma unroll
-        for (int r = 0; r < 5; ++r) v[r] = mn[pb[r] + off] / rho[pb[r] + off];
-        T q0[4];
-        q0[0] = bq1[qb[0] + off];
-        q0[1] = bq1[qb[1] + off];
-        q0[2] = bq2[qb[2] + off];
-        q0[3] = bq2[qb[3] + off];
-        const T bn0 = bnin[G.base + off];
+        for (int r = 0; r < 5; ++r) {
+            nrho[r] = rho[pb[r] + off];
+            nm[r] = mn[pb[r] + off];
+        }
+        nq[0] = bq1[qb[0] + off];
+        nq[1] = bq1[qb[1] + off];
+        nq[2] = bq2[qb[2] + off];
+        nq[3] = bq2[qb[3] + off];
+        nbn = bnin[G.base + off];
+    };
+    prefetch(jl);
+    for (int L0 = Lstart; L0 <= j0 + chunk + 2; L0 += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int L = L0 + k;
+            T v[5];
+#pragma unroll
+            for (int r = 0; r < 5; ++r) v[r] = velocity(nm[r], nrho[r]);
+            T q0[4];
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) q0[ch] = nq[ch];
+            const T bn0 = nbn;
+            jl = jl + 1 == nd ? 0 : jl + 1;
+            prefetch(jl);
 
-        T f[4];
+            T f[4];
 #pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-            const T w0 = face_avg(v[vr0[ch]], v[vr1[ch]]);       // w at L
-            const T a1 = edge_avg(wm[ch], w0);                   // a at L-1
-            const T g1 = upwind_flux1(a1, q1[ch], q0[ch]);      // G1 at L-1
-            const T hq1 = q1[ch] - halftau * (g1 - gm[ch]);     // qh at L-1
-            // edge flux at j = L-3 from a(L-3) and qh at L-4..L-1
-            f[ch] = upwind_flux2(a3[ch], h4[ch], h3[ch], h2[ch], hq1);
-            // shift
-            wm[ch] = w0;
-            a3[ch] = a2[ch]; a2[ch] = a1;
-            gm[ch] = g1;
-            h4[ch] = h3[ch]; h3[ch] = h2[ch]; h2[ch] = hq1;
-        }
-        const int j = L - 3;
-        if (j >= j0) {
-            const size_t oj = G.base + G.sd * (size_t)(j >= nd ? j - nd : j);
-            // advection of b_t1, b_t2 on this pencil; constraint on b_n
-            P.out[BX + T1][oj] = q3[0] - tau * (f[0] - fm[0]);
-            P.out[BX + T2][oj] = q3[2] - tau * (f[2] - fm[2]);
-            const T b = bnw[0] + tau * (fm[1] - fm[0]);
-            P.out[BX + N_][oj] = b + tau * (fm[3] - fm[2]);
-        }
+            for (int ch = 0; ch < 4; ++ch) {
+                const T w0 = face_avg(v[vr0[ch]], v[vr1[ch]]);       // w at L
+                const T a1 = edge_avg(wm[ch], w0);                   // a at L-1
+                const T g1 = upwind_flux1(a1, q1[ch], q0[ch]);      // G1 at L-1
+                const T hq1 = sub_scaled(q1[ch], halftau, g1 - gm[ch]);   // qh at L-1
+                // edge flux at j = L-3 from a(L-3) and qh at L-4..L-1
+                f[ch] = upwind_flux2(a3[ch], h4[ch], h3[ch], h2[ch], hq1);
+                wm[ch] = w0;
+                a3[ch] = a2[ch]; a2[ch] = a1;
+                gm[ch] = g1;
+                h4[ch] = h3[ch]; h3[ch] = h2[ch]; h2[ch] = hq1;
+            }
+            const int j = L - 3;
+            if (j >= j0) {
+                const unsigned oj = G.base + G.sd * (unsigned)j;
+                // advection of b_t1, b_t2 on this pencil; constraint on b_n
+                P.out[BX + T1][oj] = sub_scaled(q3[0], tau, f[0] - fm[0]);
+                P.out[BX + T2][oj] = sub_scaled(q3[2], tau, f[2] - fm[2]);
+                const T b = add_scaled(bnw[0], tau, fm[1] - fm[0]);
+                P.out[BX + N_][oj] = add_scaled(b, tau, fm[3] - fm[2]);
+            }
 #pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-            fm[ch] = f[ch];
-            q3[ch] = q2[ch]; q2[ch] = q1[ch]; q1[ch] = q0[ch];
+            for (int ch = 0; ch < 4; ++ch) {
+                fm[ch] = f[ch];
+                q3[ch] = q2[ch]; q2[ch] = q1[ch]; q1[ch] = q0[ch];
+            }
+            bnw[0] = bnw[1]; bnw[1] = bnw[2]; bnw[2] = bn0;
         }
-        bnw[0] = bnw[1]; bnw[1] = bnw[2]; bnw[2] = bn0;
-        jl = jl + 1 == nd ? 0 : jl + 1;
     }
 }
 
@@ -615,7 +669,7 @@ __global__ void __launch_bounds__(256) mag_march_kernel(SweepParams<T> P, int ch
 // ---------------------------------------------------------------------------
 
 template <typename T>
-static void row_shape(int nx, int& tpr, int& rows_per_wg, int& threads)
+inline void row_shape(int nx, int& tpr, int& rows_per_wg, int& threads)
 {
     tpr = nx / 4;
     rows_per_wg = 256 / tpr;
@@ -672,10 +726,5 @@ hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& t
     }
     return hipGetLastError();
 }
-
-template hipError_t launch_fluid<float>(const SweepParams<float>&, int, const LaunchTuning&, hipStream_t);
-template hipError_t launch_fluid<double>(const SweepParams<double>&, int, const LaunchTuning&, hipStream_t);
-template hipError_t launch_magnetic<float>(const SweepParams<float>&, int, const LaunchTuning&, hipStream_t);
-template hipError_t launch_magnetic<double>(const SweepParams<double>&, int, const LaunchTuning&, hipStream_t);
 
 }  // namespace mhd

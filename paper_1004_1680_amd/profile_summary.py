@@ -1,0 +1,118 @@
+"""Summaries of rocprofv3 output for the MHD kernels.
+
+  python -m paper_1004_1680_amd.profile_summary stats  <kernel_stats.csv> <command...>
+  python -m paper_1004_1680_amd.profile_summary traffic <fetch.csv> <write.csv> <ncell> <esize> <command...>
+
+``stats`` prints a per-kernel table (calls, average / min / max duration).
+``traffic`` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch)
+of two ``rocprofv3 --pmc`` runs into HBM bytes per launch, scaled by what
+the same counters read for the plain 1 GiB copy that ``bench.py
+--calibrate-copy`` runs (a kernel of known traffic), and prints them next to
+the algorithmic bytes.  It also prints the hash of the kernel sources the
+counters belong to; ``bench.py`` reports the traffic only while the sources
+still hash to it.
+"""
+import collections
+import csv
+import hashlib
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/sweep_kernels.h", "csrc/mhd_device.h", "csrc/sweep_f32.hip",
+                  "csrc/sweep_f64.hip", "csrc/reduce_kernels.hip"]
+ALG_WORDS = {"fluid": 13, "mag": 8, "cfl_partial": 8}
+COPY_BYTES = 1 << 30
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short(name):
+    name = name.replace("mhd::", "").replace("void ", "")
+    return name.split("(")[0]
+
+
+def stats(path, command):
+    rows = list(csv.DictReader(open(path)))
+    out = [f"command: {command}", "",
+           "| kernel | calls | avg us | min us | max us | % time |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                   f"{float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def per_kernel(path, counter):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            d[r["Kernel_Name"]].append((float(r["Counter_Value"]) * 1024.0, int(r["Grid_Size"])))
+    return d
+
+
+def copy_factor(d):
+    """bytes moved / bytes counted for the 1 GiB copy dispatches"""
+    vals = [v for k, lst in d.items() if "copyBuffer" in k for v, g in lst]
+    big = [v for v in vals if v > 0.25 * COPY_BYTES]
+    ref = max(big) if big else None
+    return COPY_BYTES / ref if ref else None
+
+
+def traffic(fetch_csv, write_csv, ncell, esize, command):
+    F = per_kernel(fetch_csv, "FETCH_SIZE")
+    W = per_kernel(write_csv, "WRITE_SIZE")
+    ff, fw = copy_factor(F), copy_factor(W)
+    out = [f"command: {command}", f"kernel source hash: {source_hash()}",
+           f"copy calibration: reads x{ff:.3f}, writes x{fw:.3f} "
+           f"(1 GiB copy: counters / known bytes)", "",
+           "| kernel | read MiB/launch | write MiB/launch | algorithmic MiB | traffic / algorithmic |",
+           "|---|---|---|---|---|"]
+    for k in sorted(F):
+        if "mhd::" not in k:
+            continue
+        s = short(k)
+        kind = "fluid" if "fluid" in s else ("mag" if "mag" in s else ("cfl_partial" if "cfl_partial" in s else None))
+        if kind is None:
+            continue
+        rd = sum(v for v, g in F[k]) / len(F[k]) * ff
+        wr = sum(v for v, g in W[k]) / len(W[k]) * fw if W.get(k) else 0.0
+        alg = ALG_WORDS[kind] * esize * ncell
+        out.append(f"| {s} | {rd / 2**20:.1f} | {wr / 2**20:.1f} | {alg / 2**20:.1f} | "
+                   f"{(rd + wr) / alg:.3f} |")
+        out.append(f"traffic_bytes[{s}] = {int(rd + wr)}")
+    return "\n".join(out)
+
+
+def read_traffic(path):
+    """{kernel: bytes per launch} from a traffic summary, or {} if the kernel
+    sources have changed since it was written"""
+    if not os.path.exists(path):
+        return {}
+    txt = open(path).read()
+    want = f"kernel source hash: {source_hash()}"
+    if want not in txt:
+        return {}
+    out = {}
+    for line in txt.splitlines():
+        if line.startswith("traffic_bytes["):
+            k = line[len("traffic_bytes["):line.index("]")]
+            out[k] = int(line.split("=")[1])
+    return out
+
+
+if __name__ == "__main__":
+    mode = sys.argv[1]
+    if mode == "stats":
+        print(stats(sys.argv[2], " ".join(sys.argv[3:])))
+    elif mode == "traffic":
+        print(traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5]),
+                      " ".join(sys.argv[6:])))
+    elif mode == "hash":
+        print(source_hash())
