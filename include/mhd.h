@@ -166,6 +166,55 @@ enum { MHD_TUNE_CHUNK_Y = 1, MHD_TUNE_CHUNK_Z = 2 };
 int mhd_set_launch(mhd_ctx *h, int key, int value);
 int mhd_get_launch(const mhd_ctx *h, int key, int *value);
 
+/* ------------------------------------------------------------------------
+ * Batched ensembles of uneven periodic boxes.  Each box is an independent
+ * grid advanced by the same method (section II) with its own CFL time step
+ * and relaxation speed; a step is the per-box CFL (FP64, on the device) and
+ * the 12 operators, each operator ONE persistent launch over the work items
+ * (box, tile) of all boxes, then the per-box time advance.  A box evolves
+ * bit for bit as it would in a single-grid handle.  Box dims follow the
+ * single-grid rules.  Not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct mhd_batch mhd_batch;
+
+/* dims: 3*nbox ints (nx, ny, nz of each box).  hip_stream may be NULL (the
+ * batch then creates its own stream, needed for graph capture). */
+mhd_batch *mhd_batch_create(int nbox, const int *dims, double gamma, int prec,
+                            void *hip_stream);
+void mhd_batch_destroy(mhd_batch *b);
+int mhd_batch_info(const mhd_batch *b, int *nbox, long long *ncell);
+
+/* State of one box (n == 8 * its cell count doubles, single-grid layout);
+ * synchronous; set resets the box's time and records. */
+int mhd_batch_set_state(mhd_batch *b, int box, const double *host, size_t n);
+int mhd_batch_get_state(mhd_batch *b, int box, double *host, size_t n);
+
+/* One step of every box with its own dt = cfl h / vmax (asynchronous). */
+int mhd_batch_step_auto(mhd_batch *b, double cfl);
+
+/* nsteps steps; use_graph != 0 captures one step in a HIP graph (once per
+ * cfl value and launch shape) and replays it.  Asynchronous. */
+int mhd_batch_run(mhd_batch *b, double cfl, int nsteps, int use_graph);
+
+/* Synchronise; steps[b] / nonphys[b] (each may be NULL) receive the steps a
+ * box completed and its record (0 none, 1 non-physical state, 2 zero
+ * signal speed).  A box with a record is left unchanged by later steps
+ * until this call clears the record; returns MHD_ENONPHYS if any box had
+ * one. */
+int mhd_batch_status(mhd_batch *b, long long *steps, int *nonphys);
+
+/* Simulated time of every box (nbox doubles). */
+int mhd_batch_time(mhd_batch *b, double *times);
+
+/* Launch shape (results do not depend on it): persistent workgroups of the
+ * x, y, z operator launches (multiples of 8), and the target march chunk
+ * (each box takes the largest divisor of its axis length <= target, >= 8).
+ * Launch-shape parameters, not part of the method. */
+enum { MHD_BATCH_GRID_X = 10, MHD_BATCH_GRID_Y = 11, MHD_BATCH_GRID_Z = 12,
+       MHD_BATCH_CHUNK = 13 };
+int mhd_batch_set_launch(mhd_batch *b, int key, int value);
+int mhd_batch_get_launch(const mhd_batch *b, int key, int *value);
+
 /* Thread-local message describing the last error (never NULL). */
 const char *mhd_last_error(void);
 

@@ -1,0 +1,134 @@
+"""Launch-shape autotuner for the MHD kernels.
+
+Results never depend on the launch shape (the tests check this bit for bit),
+only the time does.  The tuner times a few steps of each candidate shape on
+the live state and keeps the fastest; choices are cached in a JSON file
+(``$MHD_AUTOTUNE_CACHE``, default ``~/.cache/mhd_autotune.json``) keyed by
+device, problem and precision.
+
+* single grid: the march chunk length along y and z (the x sweeps hold
+  whole rows and have no shape to choose);
+* batched ensemble: the persistent grid of the operator launches and the
+  target march chunk.
+
+The state is saved before tuning and restored afterwards, so tuning does not
+advance the simulation.
+"""
+import json
+import os
+import time
+
+from . import mhd
+
+CACHE = os.environ.get("MHD_AUTOTUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "mhd_autotune.json"))
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(db):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def _device_tag():
+    try:
+        import torch
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "gfx950"
+
+
+def divisors(n, lo=8):
+    return [d for d in range(lo, n + 1) if n % d == 0]
+
+
+def chunk_candidates(n):
+    """divisors of n near powers of two, plus the whole pencil"""
+    out = set()
+    for p in (16, 32, 64, 128, 256, 512, 1024):
+        ds = [d for d in divisors(n) if d <= p]
+        if ds:
+            out.add(max(ds))
+    out.add(n)
+    return sorted(out)
+
+
+def tune_solver(S, cfl=0.7, steps=3, use_cache=True):
+    """Choose the y and z march chunks of a Solver; returns {axis: chunk}."""
+    key = f"{_device_tag()}:single:{S.n[0]}x{S.n[1]}x{S.n[2]}:{'f64' if S.prec == mhd.MHD_F64 else 'f32'}"
+    db = _load()
+    if use_cache and key in db:
+        best = db[key]
+        S.set_chunk(1, best["1"])
+        S.set_chunk(2, best["2"])
+        return {1: best["1"], 2: best["2"]}
+    saved = S.get_state_tensor()
+    best = {}
+    for axis in (1, 2):
+        timings = {}
+        for ch in chunk_candidates(S.n[axis]):
+            S.set_chunk(axis, ch)
+            S.set_state_tensor(saved)
+            S.step_auto(cfl)
+            S.status()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                S.step_auto(cfl)
+            S.status()
+            timings[ch] = time.perf_counter() - t0
+        best[axis] = min(timings, key=timings.get)
+        S.set_chunk(axis, best[axis])
+    S.set_state_tensor(saved)
+    db[key] = {"1": best[1], "2": best[2]}
+    _store(db)
+    return best
+
+
+def tune_batch(B, cfl=0.7, steps=3, grids=(512, 1024, 2048), chunks=(16, 32, 64, 128),
+               use_cache=True):
+    """Choose the persistent grid and the target chunk of a Batch."""
+    sig = ",".join(str(n[0]) + "x" + str(n[1]) + "x" + str(n[2]) for n in B.dims)
+    key = f"{_device_tag()}:batch:{hash(sig) & 0xffffffff:08x}:{len(B.dims)}:{'f64' if B.prec == mhd.MHD_F64 else 'f32'}"
+    db = _load()
+    if use_cache and key in db:
+        g, c = db[key]["grid"], db[key]["chunk"]
+        for k in (mhd.MHD_BATCH_GRID_X, mhd.MHD_BATCH_GRID_Y, mhd.MHD_BATCH_GRID_Z):
+            B.set_launch(k, g)
+        B.set_launch(mhd.MHD_BATCH_CHUNK, c)
+        return {"grid": g, "chunk": c}
+    saved = [B.get_state(i) for i in range(B.nbox)]
+    timings = {}
+    for g in grids:
+        for c in chunks:
+            for k in (mhd.MHD_BATCH_GRID_X, mhd.MHD_BATCH_GRID_Y, mhd.MHD_BATCH_GRID_Z):
+                B.set_launch(k, g)
+            B.set_launch(mhd.MHD_BATCH_CHUNK, c)
+            B.run(1, cfl, graph=True)
+            B.status(raise_on_nonphysical=False)
+            t0 = time.perf_counter()
+            B.run(steps, cfl, graph=True)
+            B.status(raise_on_nonphysical=False)
+            timings[(g, c)] = time.perf_counter() - t0
+    g, c = min(timings, key=timings.get)
+    for k in (mhd.MHD_BATCH_GRID_X, mhd.MHD_BATCH_GRID_Y, mhd.MHD_BATCH_GRID_Z):
+        B.set_launch(k, g)
+    B.set_launch(mhd.MHD_BATCH_CHUNK, c)
+    for i, s in enumerate(saved):
+        B.set_state(i, s)
+    db[key] = {"grid": g, "chunk": c,
+               "timings_ms": {f"{a}/{b}": round(v * 1e3 / steps, 3) for (a, b), v in timings.items()}}
+    _store(db)
+    return {"grid": g, "chunk": c}

@@ -1,0 +1,476 @@
+// Batched ensembles of uneven periodic boxes (C ABI part of mhd.h).
+//
+// All boxes live in one pair of device buffers; box b holds its 8 fields
+// contiguously at an element offset.  A step is the per-box CFL (segmented
+// FP64 max-reduction, each box its own dt and relaxation speed) followed by
+// the 12 operators, each ONE persistent launch over the (box, tile) work
+// items of its direction, and the per-box time advance.  Every field is
+// written 6 times per step, so after a full step the state is back in the
+// first buffer: the captured HIP graph of one step can be replayed for any
+// number of steps.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/mhd.h"
+#include "mhd_kernels.h"
+#include "runtime_common.h"
+
+using namespace mhd;
+#define HIP_TRY MHD_HIP_TRY
+
+struct mhd_batch {
+    int nbox;
+    std::vector<BoxDesc> boxes;
+    BoxDesc* d_boxes;
+    double gamma;
+    int prec;
+    size_t esize;
+    hipStream_t stream;
+    bool own_stream;
+    int device;
+    size_t total;                 // elements per buffer
+    void* buf[2];
+    int cur[8];
+    double* scal;                 // nbox x SCAL_COUNT
+    int* flag;                    // nbox x FLAG_COUNT
+    int2* d_items[3];
+    int nitems[3];
+    int2* d_cfl_items;
+    int n_cfl_items;
+    int* d_item_first;
+    double* partial;
+    int* partial_bad;
+    int grid[3];
+    int chunk_target;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    double graph_cfl;
+    bool graph_valid;
+    bool failed;
+};
+
+static int pick_chunk(int n, int target)
+{
+    int best = 0;
+    for (int c = 8; c <= n; ++c)
+        if (n % c == 0 && c <= target) best = c;
+    if (!best)
+        for (int c = 8; c <= n; ++c)
+            if (n % c == 0) { best = c; break; }
+    return best;
+}
+
+static void free_lists(mhd_batch* b)
+{
+    for (int d = 0; d < 3; ++d)
+        if (b->d_items[d]) { (void)hipFree(b->d_items[d]); b->d_items[d] = nullptr; }
+    if (b->d_boxes) { (void)hipFree(b->d_boxes); b->d_boxes = nullptr; }
+}
+
+static void drop_graph(mhd_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_valid = false;
+}
+
+// (re)build box shapes and the work lists of the three directions
+static int build_lists(mhd_batch* b)
+{
+    free_lists(b);
+    drop_graph(b);
+    std::vector<int2> items[3];
+    for (int i = 0; i < b->nbox; ++i) {
+        BoxDesc& bd = b->boxes[i];
+        bd.chunk[0] = 0;
+        bd.chunk[1] = pick_chunk(bd.n[1], b->chunk_target);
+        bd.chunk[2] = pick_chunk(bd.n[2], b->chunk_target);
+        bd.tpr = bd.n[0] / 4;
+        bd.rpw = std::max(1, 256 / bd.tpr);
+        bd.ntile[0] = (bd.n[1] * bd.n[2] + bd.rpw - 1) / bd.rpw;
+        for (int d = 1; d < 3; ++d) {
+            const long lanes = (long)bd.n[0] * (d == 1 ? bd.n[2] : bd.n[1]) * (bd.n[d] / bd.chunk[d]);
+            bd.ntile[d] = (int)((lanes + 255) / 256);
+        }
+        for (int d = 0; d < 3; ++d)
+            for (int t = 0; t < bd.ntile[d]; ++t) items[d].push_back(make_int2(i, t));
+    }
+    HIP_TRY(b, hipMalloc(&b->d_boxes, sizeof(BoxDesc) * b->nbox));
+    HIP_TRY(b, hipMemcpy(b->d_boxes, b->boxes.data(), sizeof(BoxDesc) * b->nbox,
+                         hipMemcpyHostToDevice));
+    for (int d = 0; d < 3; ++d) {
+        b->nitems[d] = (int)items[d].size();
+        HIP_TRY(b, hipMalloc(&b->d_items[d], sizeof(int2) * items[d].size()));
+        HIP_TRY(b, hipMemcpy(b->d_items[d], items[d].data(), sizeof(int2) * items[d].size(),
+                             hipMemcpyHostToDevice));
+    }
+    return MHD_OK;
+}
+
+extern "C" void mhd_batch_destroy(mhd_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    free_lists(b);
+    void* ptrs[] = { b->buf[0], b->buf[1], b->scal, b->flag, b->d_cfl_items, b->d_item_first,
+                     b->partial, b->partial_bad };
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+extern "C" mhd_batch* mhd_batch_create(int nbox, const int* dims, double gamma, int prec,
+                                       void* hip_stream)
+{
+    if (nbox < 1 || !dims) {
+        mhd_fail(MHD_EINVAL, "need nbox >= 1 and a dims array of 3*nbox ints");
+        return nullptr;
+    }
+    if (!(gamma > 1.0) || !isfinite(gamma)) {
+        mhd_fail(MHD_EINVAL, "gamma must be > 1 (got %g)", gamma);
+        return nullptr;
+    }
+    if (prec != MHD_F32 && prec != MHD_F64) {
+        mhd_fail(MHD_EINVAL, "precision must be MHD_F32 or MHD_F64");
+        return nullptr;
+    }
+    for (int i = 0; i < nbox; ++i) {
+        for (int d = 0; d < 3; ++d)
+            if (dims[3 * i + d] < 8 || dims[3 * i + d] % 4) {
+                mhd_fail(MHD_EINVAL, "box %d dimension %d = %d: must be >= 8 and a multiple of 4", i,
+                         d, dims[3 * i + d]);
+                return nullptr;
+            }
+        if (dims[3 * i] > 1024 || dims[3 * i + 1] > 4096 || dims[3 * i + 2] > 4096 ||
+            (long long)dims[3 * i] * dims[3 * i + 1] * dims[3 * i + 2] >= (1LL << 31)) {
+            mhd_fail(MHD_EINVAL, "box %d above the size limit", i);
+            return nullptr;
+        }
+    }
+    mhd_batch* b = new mhd_batch();
+    b->nbox = nbox;
+    b->gamma = gamma;
+    b->prec = prec;
+    b->esize = prec == MHD_F64 ? sizeof(double) : sizeof(float);
+    b->chunk_target = 64;
+    b->d_boxes = nullptr;
+    for (int d = 0; d < 3; ++d) { b->d_items[d] = nullptr; b->grid[d] = 1024; }
+    b->buf[0] = b->buf[1] = nullptr;
+    b->scal = nullptr; b->flag = nullptr;
+    b->d_cfl_items = nullptr; b->d_item_first = nullptr;
+    b->partial = nullptr; b->partial_bad = nullptr;
+    b->graph = nullptr; b->exec = nullptr; b->graph_valid = false;
+    b->failed = false;
+    for (int q = 0; q < 8; ++q) b->cur[q] = 0;
+    if (hipGetDevice(&b->device) != hipSuccess) {
+        mhd_fail(MHD_EDEVICE, "no HIP device");
+        delete b;
+        return nullptr;
+    }
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+        b->own_stream = false;
+    } else {
+        // graph capture needs a stream other than the legacy default one
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            mhd_fail(MHD_EDEVICE, "stream creation failed");
+            delete b;
+            return nullptr;
+        }
+        b->own_stream = true;
+    }
+    b->boxes.resize(nbox);
+    size_t off = 0;
+    std::vector<int2> cfl_items;
+    std::vector<int> first(nbox + 1);
+    for (int i = 0; i < nbox; ++i) {
+        BoxDesc& bd = b->boxes[i];
+        memset(&bd, 0, sizeof bd);
+        for (int d = 0; d < 3; ++d) bd.n[d] = dims[3 * i + d];
+        bd.ncell = (unsigned)((size_t)bd.n[0] * bd.n[1] * bd.n[2]);
+        bd.off = off;
+        off += 8 * (size_t)bd.ncell;
+        first[i] = (int)cfl_items.size();
+        const int nblk = (int)((bd.ncell + CFL_CELLS - 1) / CFL_CELLS);
+        for (int k = 0; k < nblk; ++k) cfl_items.push_back(make_int2(i, k));
+    }
+    first[nbox] = (int)cfl_items.size();
+    b->total = off;
+    b->n_cfl_items = (int)cfl_items.size();
+    const size_t bytes = off * b->esize;
+    bool ok = hipMalloc(&b->buf[0], bytes) == hipSuccess && hipMalloc(&b->buf[1], bytes) == hipSuccess &&
+              hipMalloc(&b->scal, sizeof(double) * SCAL_COUNT * nbox) == hipSuccess &&
+              hipMalloc(&b->flag, sizeof(int) * FLAG_COUNT * nbox) == hipSuccess &&
+              hipMalloc(&b->d_cfl_items, sizeof(int2) * cfl_items.size()) == hipSuccess &&
+              hipMalloc(&b->d_item_first, sizeof(int) * (nbox + 1)) == hipSuccess &&
+              hipMalloc(&b->partial, sizeof(double) * cfl_items.size()) == hipSuccess &&
+              hipMalloc(&b->partial_bad, sizeof(int) * cfl_items.size()) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        mhd_fail(MHD_ENOMEM, "device allocation of 2 x %zu bytes failed", bytes);
+        mhd_batch_destroy(b);
+        return nullptr;
+    }
+    ok = hipMemcpy(b->d_cfl_items, cfl_items.data(), sizeof(int2) * cfl_items.size(),
+                   hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_item_first, first.data(), sizeof(int) * (nbox + 1),
+                   hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(b->buf[0], 0, bytes) == hipSuccess && hipMemset(b->buf[1], 0, bytes) == hipSuccess &&
+         hipMemset(b->scal, 0, sizeof(double) * SCAL_COUNT * nbox) == hipSuccess &&
+         hipMemset(b->flag, 0, sizeof(int) * FLAG_COUNT * nbox) == hipSuccess;
+    if (!ok || build_lists(b) != MHD_OK) {
+        mhd_fail(MHD_EDEVICE, "batch initialisation failed");
+        mhd_batch_destroy(b);
+        return nullptr;
+    }
+    return b;
+}
+
+static int check_batch(const mhd_batch* b)
+{
+    if (!b) return mhd_fail(MHD_EINVAL, "null batch handle");
+    if (b->failed) return mhd_fail(MHD_ESTATE, "batch handle failed earlier (HIP error)");
+    return MHD_OK;
+}
+
+extern "C" int mhd_batch_info(const mhd_batch* b, int* nbox, long long* ncell)
+{
+    if (!b) return mhd_fail(MHD_EINVAL, "null batch handle");
+    long long n = 0;
+    for (const BoxDesc& bd : b->boxes) n += bd.ncell;
+    if (nbox) *nbox = b->nbox;
+    if (ncell) *ncell = n;
+    return MHD_OK;
+}
+
+template <typename T>
+static T* box_field(mhd_batch* b, int box, int f, int which)
+{
+    const BoxDesc& bd = b->boxes[box];
+    return reinterpret_cast<T*>(b->buf[which]) + bd.off + (size_t)f * bd.ncell;
+}
+
+extern "C" int mhd_batch_set_state(mhd_batch* b, int box, const double* host, size_t n)
+{
+    int r = check_batch(b);
+    if (r) return r;
+    if (box < 0 || box >= b->nbox) return mhd_fail(MHD_EINVAL, "box index %d out of range", box);
+    if (!host) return mhd_fail(MHD_EINVAL, "null host pointer");
+    const BoxDesc& bd = b->boxes[box];
+    if (n != 8 * (size_t)bd.ncell) return mhd_fail(MHD_EINVAL, "state size %zu != 8 * cells of box", n);
+    HIP_TRY(b, hipSetDevice(b->device));
+    const size_t N = bd.ncell;
+    if (b->prec == MHD_F64) {
+        HIP_TRY(b, hipMemcpyAsync(box_field<double>(b, box, 0, 0), host, 8 * N * sizeof(double),
+                                  hipMemcpyHostToDevice, b->stream));
+    } else {
+        double* stage = nullptr;
+        if (hipMalloc(&stage, 8 * N * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return mhd_fail(MHD_ENOMEM, "staging allocation failed");
+        }
+        hipError_t e = hipMemcpyAsync(stage, host, 8 * N * sizeof(double), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = launch_convert_in<float>(stage, box_field<float>(b, box, 0, 0), 8 * N, b->stream);
+        const hipError_t e2 = hipStreamSynchronize(b->stream);
+        (void)hipFree(stage);
+        HIP_TRY(b, e);
+        HIP_TRY(b, e2);
+    }
+    // this box starts afresh: time 0, no record
+    HIP_TRY(b, hipMemsetAsync(b->scal + (size_t)box * SCAL_COUNT, 0, sizeof(double) * SCAL_COUNT, b->stream));
+    HIP_TRY(b, hipMemsetAsync(b->flag + (size_t)box * FLAG_COUNT, 0, sizeof(int) * FLAG_COUNT, b->stream));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    return MHD_OK;
+}
+
+extern "C" int mhd_batch_get_state(mhd_batch* b, int box, double* host, size_t n)
+{
+    int r = check_batch(b);
+    if (r) return r;
+    if (box < 0 || box >= b->nbox) return mhd_fail(MHD_EINVAL, "box index %d out of range", box);
+    if (!host) return mhd_fail(MHD_EINVAL, "null host pointer");
+    const BoxDesc& bd = b->boxes[box];
+    if (n != 8 * (size_t)bd.ncell) return mhd_fail(MHD_EINVAL, "state size %zu != 8 * cells of box", n);
+    HIP_TRY(b, hipSetDevice(b->device));
+    const size_t N = bd.ncell;
+    if (b->prec == MHD_F64) {
+        HIP_TRY(b, hipMemcpyAsync(host, box_field<double>(b, box, 0, 0), 8 * N * sizeof(double),
+                                  hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(b, hipStreamSynchronize(b->stream));
+        return MHD_OK;
+    }
+    double* stage = nullptr;
+    if (hipMalloc(&stage, 8 * N * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return mhd_fail(MHD_ENOMEM, "staging allocation failed");
+    }
+    hipError_t e = launch_convert_out<float>(box_field<float>(b, box, 0, 0), stage, 8 * N, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, stage, 8 * N * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+    const hipError_t e2 = hipStreamSynchronize(b->stream);
+    (void)hipFree(stage);
+    HIP_TRY(b, e);
+    HIP_TRY(b, e2);
+    return MHD_OK;
+}
+
+template <typename T>
+static int enqueue_batch_step(mhd_batch* b, double cfl)
+{
+    const T* base[8];
+    for (int q = 0; q < 8; ++q) base[q] = reinterpret_cast<const T*>(b->buf[b->cur[q]]);
+    HIP_TRY(b, launch_batch_cfl<T>(base, b->d_boxes, b->d_cfl_items, b->n_cfl_items,
+                                   b->d_item_first, b->nbox, b->gamma, cfl, b->partial,
+                                   b->partial_bad, b->scal, b->flag, b->stream));
+    static const int order[12][2] = { { 0, 0 }, { 1, 0 }, { 0, 1 }, { 1, 1 }, { 0, 2 }, { 1, 2 },
+                                      { 1, 2 }, { 0, 2 }, { 1, 1 }, { 0, 1 }, { 1, 0 }, { 0, 0 } };
+    for (int k = 0; k < 12; ++k) {
+        const int op = order[k][0], d = order[k][1];
+        BatchParams<T> P;
+        for (int q = 0; q < 8; ++q) {
+            P.in_base[q] = reinterpret_cast<const T*>(b->buf[b->cur[q]]);
+            P.out_base[q] = reinterpret_cast<T*>(b->buf[1 - b->cur[q]]);
+        }
+        P.boxes = b->d_boxes;
+        P.items = b->d_items[d];
+        P.nitems = b->nitems[d];
+        P.gamma = (T)b->gamma;
+        P.scal = b->scal;
+        P.flag = b->flag;
+        const int grid = std::max(8, std::min(b->grid[d], (b->nitems[d] + 7) / 8 * 8));
+        HIP_TRY(b, launch_batch_op<T>(P, op, d, grid, b->stream));
+        if (op == 0)
+            for (int q = 0; q < 5; ++q) b->cur[q] = 1 - b->cur[q];
+        else
+            for (int q = 5; q < 8; ++q) b->cur[q] = 1 - b->cur[q];
+    }
+    HIP_TRY(b, launch_batch_advance(b->scal, b->flag, b->nbox, b->stream));
+    return MHD_OK;
+}
+
+static int enqueue_step(mhd_batch* b, double cfl)
+{
+    return b->prec == MHD_F64 ? enqueue_batch_step<double>(b, cfl) : enqueue_batch_step<float>(b, cfl);
+}
+
+extern "C" int mhd_batch_step_auto(mhd_batch* b, double cfl)
+{
+    int r = check_batch(b);
+    if (r) return r;
+    if (!(cfl > 0.0) || !isfinite(cfl)) return mhd_fail(MHD_EINVAL, "cfl must be > 0");
+    HIP_TRY(b, hipSetDevice(b->device));
+    return enqueue_step(b, cfl);
+}
+
+extern "C" int mhd_batch_run(mhd_batch* b, double cfl, int nsteps, int use_graph)
+{
+    int r = check_batch(b);
+    if (r) return r;
+    if (!(cfl > 0.0) || !isfinite(cfl)) return mhd_fail(MHD_EINVAL, "cfl must be > 0");
+    if (nsteps < 0) return mhd_fail(MHD_EINVAL, "nsteps must be >= 0");
+    HIP_TRY(b, hipSetDevice(b->device));
+    if (!use_graph) {
+        for (int s = 0; s < nsteps; ++s)
+            if ((r = enqueue_step(b, cfl))) return r;
+        return MHD_OK;
+    }
+    if (!b->graph_valid || b->graph_cfl != cfl) {
+        drop_graph(b);
+        HIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        r = enqueue_step(b, cfl);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (r) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+        }
+        HIP_TRY(b, e);
+        b->graph = g;
+        HIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_cfl = cfl;
+        b->graph_valid = true;
+    }
+    for (int s = 0; s < nsteps; ++s) HIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+    return MHD_OK;
+}
+
+// steps[b] (if not null) = steps box b completed; nonphys[b] (if not null) =
+// its record (0 none, 1 non-physical, 2 zero signal speed).  Returns
+// MHD_ENONPHYS if any box has a record; records are then cleared.
+extern "C" int mhd_batch_status(mhd_batch* b, long long* steps, int* nonphys)
+{
+    int r = check_batch(b);
+    if (r) return r;
+    HIP_TRY(b, hipSetDevice(b->device));
+    std::vector<int> fl((size_t)FLAG_COUNT * b->nbox);
+    HIP_TRY(b, hipMemcpyAsync(fl.data(), b->flag, sizeof(int) * fl.size(), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    int any = 0;
+    for (int i = 0; i < b->nbox; ++i) {
+        if (steps) steps[i] = fl[(size_t)i * FLAG_COUNT + FLAG_STEPS];
+        const int np = fl[(size_t)i * FLAG_COUNT + FLAG_NONPHYS];
+        if (nonphys) nonphys[i] = np;
+        if (np) {
+            any = 1;
+            HIP_TRY(b, hipMemsetAsync(b->flag + (size_t)i * FLAG_COUNT + FLAG_NONPHYS, 0, sizeof(int), b->stream));
+        }
+    }
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    if (any) return mhd_fail(MHD_ENONPHYS, "a box reached a non-physical state; its steps were skipped");
+    return MHD_OK;
+}
+
+extern "C" int mhd_batch_time(mhd_batch* b, double* times)
+{
+    int r = check_batch(b);
+    if (r) return r;
+    if (!times) return mhd_fail(MHD_EINVAL, "null output");
+    HIP_TRY(b, hipSetDevice(b->device));
+    std::vector<double> sc((size_t)SCAL_COUNT * b->nbox);
+    HIP_TRY(b, hipMemcpyAsync(sc.data(), b->scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    for (int i = 0; i < b->nbox; ++i) times[i] = sc[(size_t)i * SCAL_COUNT + SCAL_TIME];
+    return MHD_OK;
+}
+
+extern "C" int mhd_batch_set_launch(mhd_batch* b, int key, int value)
+{
+    int r = check_batch(b);
+    if (r) return r;
+    HIP_TRY(b, hipSetDevice(b->device));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    if (key == MHD_BATCH_GRID_X || key == MHD_BATCH_GRID_Y || key == MHD_BATCH_GRID_Z) {
+        if (value < 8 || value % 8) return mhd_fail(MHD_EINVAL, "persistent grid must be a positive multiple of 8");
+        b->grid[key - MHD_BATCH_GRID_X] = value;
+        drop_graph(b);
+        return MHD_OK;
+    }
+    if (key == MHD_BATCH_CHUNK) {
+        if (value < 8) return mhd_fail(MHD_EINVAL, "chunk target must be >= 8");
+        b->chunk_target = value;
+        return build_lists(b);
+    }
+    return mhd_fail(MHD_EINVAL, "unknown launch key %d", key);
+}
+
+extern "C" int mhd_batch_get_launch(const mhd_batch* b, int key, int* value)
+{
+    if (!b || !value) return mhd_fail(MHD_EINVAL, "null argument");
+    if (key == MHD_BATCH_GRID_X || key == MHD_BATCH_GRID_Y || key == MHD_BATCH_GRID_Z)
+        *value = b->grid[key - MHD_BATCH_GRID_X];
+    else if (key == MHD_BATCH_CHUNK)
+        *value = b->chunk_target;
+    else
+        return mhd_fail(MHD_EINVAL, "unknown launch key %d", key);
+    return MHD_OK;
+}

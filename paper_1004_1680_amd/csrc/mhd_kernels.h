@@ -29,6 +29,54 @@ struct LaunchTuning {
     int chunk[3];
 };
 
+// ---------------------------------------------------------------------------
+// Batched ensembles: boxes of different sizes in one pair of buffers.  Box b
+// holds its 8 fields contiguously (field-major, x fastest) at element
+// offset off in each buffer.  Work items (box, tile) of one sweep direction
+// are processed by a persistent grid of workgroups.
+// ---------------------------------------------------------------------------
+struct BoxDesc {
+    int n[3];
+    int chunk[3];                 // march chunk along y (1) and z (2)
+    int tpr, rpw;                 // row-kernel shape (threads per row, rows per tile)
+    int ntile[3];                 // tiles per direction
+    unsigned ncell;
+    unsigned long long off;       // element offset of the box in each buffer
+};
+
+template <typename T>
+struct BatchParams {
+    const T* in_base[8];          // buffer holding the current copy of each field
+    T* out_base[8];               // the other buffer
+    const BoxDesc* boxes;
+    const int2* items;            // (box, tile)
+    int nitems;
+    T gamma;
+    const double* scal;           // per box: SCAL_COUNT doubles
+    const int* flag;              // per box: FLAG_COUNT ints (null: never skip)
+};
+
+// op 0 fluid, 1 magnetic; d = sweep axis; grid = persistent workgroups (x8)
+template <typename T>
+hipError_t launch_batch_op(const BatchParams<T>& B, int op, int d, int grid, hipStream_t s);
+
+template <typename T>
+struct BatchCflArgs {
+    const T* base[8];             // buffer holding the current copy of each field
+    const BoxDesc* boxes;
+    const int2* items;
+};
+
+// per-box CFL: items (box, block of CFL_CELLS cells); item_first[b] ..
+// item_first[b+1]-1 are box b's items
+constexpr int CFL_CELLS = 2048;
+template <typename T>
+hipError_t launch_batch_cfl(const T* const base[8], const BoxDesc* boxes, const int2* items,
+                            int nitems, const int* item_first, int nbox, double gamma,
+                            double cfl, double* partial, int* partial_bad, double* scal,
+                            int* flag, hipStream_t s);
+hipError_t launch_batch_advance(double* scal, int* flag, int nbox, hipStream_t s);
+
 template <typename T>
 hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s);
 template <typename T>

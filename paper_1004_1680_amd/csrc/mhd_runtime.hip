@@ -22,12 +22,13 @@
 
 #include "../../include/mhd.h"
 #include "mhd_kernels.h"
+#include "runtime_common.h"
 
 using namespace mhd;
 
 static thread_local std::string g_last_error = "no error";
 
-static int fail(int code, const char* fmt, ...)
+int mhd_fail(int code, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -37,6 +38,7 @@ static int fail(int code, const char* fmt, ...)
     g_last_error = buf;
     return code;
 }
+#define fail mhd_fail
 
 struct mhd_ctx {
     int n[3];
@@ -67,15 +69,7 @@ struct mhd_ctx {
 // helpers
 // ---------------------------------------------------------------------------
 
-#define HIP_TRY(h, expr)                                                               \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess) {                                                        \
-            (h)->failed = true;                                                        \
-            return fail(MHD_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),   \
-                        __FILE__, __LINE__);                                           \
-        }                                                                              \
-    } while (0)
+#define HIP_TRY MHD_HIP_TRY
 
 static int check_handle(const mhd_ctx* h)
 {

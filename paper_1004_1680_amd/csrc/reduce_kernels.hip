@@ -46,8 +46,41 @@ int cfl_blocks(size_t ncell)
     return (int)b;
 }
 
-// Signal speed max_d |v_d| + sqrt((gamma p + |Bbar|^2)/rho) of every cell in
-// FP64; per-block maximum and non-physical flag.
+// Signal speed max_d |v_d| + sqrt((gamma p + |Bbar|^2)/rho) of cell c of an
+// nx x ny x nz grid in FP64; folds it into vmax, or raises bad for a
+// non-physical cell.
+template <typename T>
+__device__ __forceinline__ void cell_signal_speed(const T* const* f, size_t c, int nx, int ny,
+                                                  int nz, double gamma, double& vmax, int& bad)
+{
+    const size_t sy = nx, sz = (size_t)nx * ny;
+    const int i = (int)(c % nx);
+    const int j = (int)((c / sy) % ny);
+    const int k = (int)(c / sz);
+    const size_t cx = i + 1 == nx ? c - (nx - 1) : c + 1;
+    const size_t cy = j + 1 == ny ? c - (ny - 1) * sy : c + sy;
+    const size_t cz = k + 1 == nz ? c - (size_t)(nz - 1) * sz : c + sz;
+    const double rho = (double)f[0][c];
+    const double mx = (double)f[1][c], my = (double)f[2][c], mz = (double)f[3][c];
+    const double e = (double)f[4][c];
+    const double bx = 0.5 * ((double)f[5][c] + (double)f[5][cx]);
+    const double by = 0.5 * ((double)f[6][c] + (double)f[6][cy]);
+    const double bz = 0.5 * ((double)f[7][c] + (double)f[7][cz]);
+    const double b2 = bx * bx + by * by + bz * bz;
+    const double mm = mx * mx + my * my + mz * mz;
+    const double p = (gamma - 1.0) * (e - 0.5 * mm / rho - 0.5 * b2);
+    const double vx = fabs(mx / rho), vy = fabs(my / rho), vz = fabs(mz / rho);
+    double vm = vx > vy ? vx : vy;
+    vm = vm > vz ? vm : vz;
+    const double sp = vm + sqrt((gamma * p + b2) / rho);
+    if (!(rho > 0.0) || !(p >= 0.0) || !isfinite(sp) || !isfinite(e) || !isfinite(mm) ||
+        !isfinite(b2))
+        bad = 1;
+    else if (sp > vmax)
+        vmax = sp;
+}
+
+// per-block maximum and non-physical flag of the signal speed
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS) cfl_partial_kernel(
     const T* __restrict__ rho_, const T* __restrict__ mx_, const T* __restrict__ my_,
@@ -56,36 +89,12 @@ __global__ void __launch_bounds__(RED_THREADS) cfl_partial_kernel(
     double* partial, int* partial_bad)
 {
     const size_t N = (size_t)nx * ny * nz;
-    const size_t sy = nx, sz = (size_t)nx * ny;
+    const T* f[8] = { rho_, mx_, my_, mz_, e_, bx_, by_, bz_ };
     double vmax = 0.0;
     int bad = 0;
     for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < N;
-         c += (size_t)gridDim.x * RED_THREADS) {
-        const int i = (int)(c % nx);
-        const int j = (int)((c / sy) % ny);
-        const int k = (int)(c / sz);
-        const size_t cx = i + 1 == nx ? c - (nx - 1) : c + 1;
-        const size_t cy = j + 1 == ny ? c - (ny - 1) * sy : c + sy;
-        const size_t cz = k + 1 == nz ? c - (size_t)(nz - 1) * sz : c + sz;
-        const double rho = (double)rho_[c];
-        const double mx = (double)mx_[c], my = (double)my_[c], mz = (double)mz_[c];
-        const double e = (double)e_[c];
-        const double bx = 0.5 * ((double)bx_[c] + (double)bx_[cx]);
-        const double by = 0.5 * ((double)by_[c] + (double)by_[cy]);
-        const double bz = 0.5 * ((double)bz_[c] + (double)bz_[cz]);
-        const double b2 = bx * bx + by * by + bz * bz;
-        const double mm = mx * mx + my * my + mz * mz;
-        const double p = (gamma - 1.0) * (e - 0.5 * mm / rho - 0.5 * b2);
-        const double vx = fabs(mx / rho), vy = fabs(my / rho), vz = fabs(mz / rho);
-        double vm = vx > vy ? vx : vy;
-        vm = vm > vz ? vm : vz;
-        const double sp = vm + sqrt((gamma * p + b2) / rho);
-        if (!(rho > 0.0) || !(p >= 0.0) || !isfinite(sp) || !isfinite(e) || !isfinite(mm) ||
-            !isfinite(b2))
-            bad = 1;
-        else if (sp > vmax)
-            vmax = sp;
-    }
+         c += (size_t)gridDim.x * RED_THREADS)
+        cell_signal_speed(f, c, nx, ny, nz, gamma, vmax, bad);
     __shared__ double smax[RED_THREADS / 64];
     __shared__ int sbad[RED_THREADS / 64];
     vmax = wave_max(vmax);
@@ -154,6 +163,116 @@ template hipError_t launch_cfl<float>(const float* const[8], int, int, int, doub
                                       double*, int*, int, double*, int*, hipStream_t);
 template hipError_t launch_cfl<double>(const double* const[8], int, int, int, double, double,
                                        double*, int*, int, double*, int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Per-box CFL of a batched ensemble
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS) batch_cfl_partial_kernel(
+    BatchCflArgs<T> A, double gamma, double* partial, int* partial_bad)
+{
+    const int2 it = A.items[blockIdx.x];
+    const BoxDesc bd = A.boxes[it.x];
+    const T* f[8];
+    for (int q = 0; q < 8; ++q) f[q] = A.base[q] + bd.off + (size_t)q * bd.ncell;
+    double vmax = 0.0;
+    int bad = 0;
+    const size_t c0 = (size_t)it.y * CFL_CELLS;
+    const size_t c1 = c0 + CFL_CELLS < bd.ncell ? c0 + CFL_CELLS : bd.ncell;
+    for (size_t c = c0 + threadIdx.x; c < c1; c += RED_THREADS)
+        cell_signal_speed(f, c, bd.n[0], bd.n[1], bd.n[2], gamma, vmax, bad);
+    __shared__ double smax[RED_THREADS / 64];
+    __shared__ int sbad[RED_THREADS / 64];
+    vmax = wave_max(vmax);
+    bad = wave_or(bad);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { smax[w] = vmax; sbad[w] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = smax[0];
+        int b = sbad[0];
+        for (int q = 1; q < RED_THREADS / 64; ++q) { m = fmax(m, smax[q]); b |= sbad[q]; }
+        partial[blockIdx.x] = m;
+        partial_bad[blockIdx.x] = b;
+    }
+}
+
+// one workgroup per box: max over the box's items; dt and relaxation speed
+// of the box, or its non-physical flag (then dt = 0)
+__global__ void __launch_bounds__(RED_THREADS) batch_cfl_final_kernel(
+    const double* partial, const int* partial_bad, const int* item_first, const BoxDesc* boxes,
+    double cfl, double* scal, int* flag)
+{
+    const int b = blockIdx.x;
+    double m = 0.0;
+    int bad = 0;
+    for (int i = item_first[b] + threadIdx.x; i < item_first[b + 1]; i += RED_THREADS) {
+        m = fmax(m, partial[i]);
+        bad |= partial_bad[i];
+    }
+    __shared__ double smax[RED_THREADS / 64];
+    __shared__ int sbad[RED_THREADS / 64];
+    m = wave_max(m);
+    bad = wave_or(bad);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { smax[w] = m; sbad[w] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double vmax = smax[0];
+        int bb = sbad[0];
+        for (int q = 1; q < RED_THREADS / 64; ++q) { vmax = fmax(vmax, smax[q]); bb |= sbad[q]; }
+        double* sc = scal + (size_t)b * SCAL_COUNT;
+        if (bb || !(vmax > 0.0)) {
+            sc[SCAL_DT] = 0.0;
+            sc[SCAL_VMAX] = 0.0;
+            flag[(size_t)b * FLAG_COUNT + FLAG_NONPHYS] = bb ? 1 : 2;
+        } else {
+            sc[SCAL_DT] = cfl * (1.0 / (double)boxes[b].n[0]) / vmax;
+            sc[SCAL_VMAX] = vmax;
+            sc[SCAL_C] = vmax;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_batch_cfl(const T* const base[8], const BoxDesc* boxes, const int2* items,
+                            int nitems, const int* item_first, int nbox, double gamma,
+                            double cfl, double* partial, int* partial_bad, double* scal,
+                            int* flag, hipStream_t s)
+{
+    BatchCflArgs<T> A;
+    for (int q = 0; q < 8; ++q) A.base[q] = base[q];
+    A.boxes = boxes;
+    A.items = items;
+    hipLaunchKernelGGL(batch_cfl_partial_kernel<T>, dim3(nitems), dim3(RED_THREADS), 0, s, A,
+                       gamma, partial, partial_bad);
+    hipLaunchKernelGGL(batch_cfl_final_kernel, dim3(nbox), dim3(RED_THREADS), 0, s, partial,
+                       partial_bad, item_first, boxes, cfl, scal, flag);
+    return hipGetLastError();
+}
+template hipError_t launch_batch_cfl<float>(const float* const[8], const BoxDesc*, const int2*,
+                                            int, const int*, int, double, double, double*, int*,
+                                            double*, int*, hipStream_t);
+template hipError_t launch_batch_cfl<double>(const double* const[8], const BoxDesc*, const int2*,
+                                             int, const int*, int, double, double, double*, int*,
+                                             double*, int*, hipStream_t);
+
+// per-box time advance (skipped for a box with a non-physical record)
+__global__ void batch_advance_kernel(double* scal, int* flag, int nbox)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nbox && flag[(size_t)b * FLAG_COUNT + FLAG_NONPHYS] == 0) {
+        scal[(size_t)b * SCAL_COUNT + SCAL_TIME] += 2.0 * scal[(size_t)b * SCAL_COUNT + SCAL_DT];
+        flag[(size_t)b * FLAG_COUNT + FLAG_STEPS] += 1;
+    }
+}
+
+hipError_t launch_batch_advance(double* scal, int* flag, int nbox, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_advance_kernel, dim3((nbox + 63) / 64), dim3(64), 0, s, scal, flag, nbox);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Diagnostics

@@ -85,22 +85,25 @@ __device__ __forceinline__ void step_scalars(const SweepParams<T>& P, T& tau, T&
 // grid = ceil(ny*nz / rows_per_wg) workgroups; dynamic LDS = 25 * blockDim
 // values of T (fluid) or 16 * blockDim (magnetic).
 
+// One tile of rows_per_wg rows of one grid; every thread of the workgroup
+// calls it (it holds barriers).  Threads beyond rows_per_wg * tpr idle.
 template <typename T>
-__global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+__device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
+                                             int rows_per_wg, T* const A)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* const A = reinterpret_cast<T*>(smem_raw);          // 20 values / thread
-    T* const B = A + 20 * blockDim.x;                       // 5 values / thread
+    T* const B = A + 20 * blockDim.x;                       // A: 20, B: 5 values / thread
     const int nt = blockDim.x;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int t = threadIdx.x;
     const int rloc = t / tpr, tr = t - rloc * tpr;
-    const int row = xcd_tile(gridDim.x) * rows_per_wg + rloc;
-    const bool active = row < ny * nz;
+    const int row = tile * rows_per_wg + rloc;
+    const bool active = rloc < rows_per_wg && row < ny * nz;
     const int y = active ? row % ny : 0, z = active ? row / ny : 0;
-    const int tprev = rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1);
-    const int tnext = rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1);
-    const size_t N = (size_t)nx * ny * nz;
+    // idle threads (rloc >= rows_per_wg) exchange with themselves, so every
+    // LDS index stays below blockDim.x
+    const bool inrow = rloc < rows_per_wg;
+    const int tprev = inrow ? rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1) : t;
+    const int tnext = inrow ? rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1) : t;
     const size_t base = (size_t)nx * ((size_t)y + (size_t)ny * z);
     const size_t base_yp = (size_t)nx * ((size_t)(y + 1 == ny ? 0 : y + 1) + (size_t)ny * z);
     const size_t base_zp = (size_t)nx * ((size_t)y + (size_t)ny * (z + 1 == nz ? 0 : z + 1));
@@ -221,25 +224,34 @@ __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr,
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    fluid_x_tile(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+}
+
 // Magnetic sweep along x: e = y then z.  For each e two edge-flux chains
 // are evaluated: "own" (edges of this row, velocity from rows P and P-e)
 // and "plus" (edges of row P+e, velocity from rows P+e and P), the latter
 // for the constraint update of b_x.
 template <typename T>
-__global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+__device__ __forceinline__ void mag_x_tile(const SweepParams<T>& P, int tile, int tpr,
+                                           int rows_per_wg, T* const A)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* const A = reinterpret_cast<T*>(smem_raw);          // 12 values / thread
-    T* const B = A + 12 * blockDim.x;                       // 4 values / thread
+    T* const B = A + 12 * blockDim.x;                       // A: 12, B: 4 values / thread
     const int nt = blockDim.x;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int t = threadIdx.x;
     const int rloc = t / tpr, tr = t - rloc * tpr;
-    const int row = xcd_tile(gridDim.x) * rows_per_wg + rloc;
-    const bool active = row < ny * nz;
+    const int row = tile * rows_per_wg + rloc;
+    const bool active = rloc < rows_per_wg && row < ny * nz;
     const int y = active ? row % ny : 0, z = active ? row / ny : 0;
-    const int tprev = rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1);
-    const int tnext = rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1);
+    // idle threads (rloc >= rows_per_wg) exchange with themselves, so every
+    // LDS index stays below blockDim.x
+    const bool inrow = rloc < rows_per_wg;
+    const int tprev = inrow ? rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1) : t;
+    const int tnext = inrow ? rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1) : t;
     const int i0 = 4 * tr;
     const int inext = (i0 + 4 == nx) ? 0 : i0 + 4;
     auto rbase = [&](int yy, int zz) -> size_t {
@@ -379,6 +391,13 @@ __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, i
     vec4<T>::store(P.out[BX] + b0 + i0, bx);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    mag_x_tile(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+}
+
 // ---------------------------------------------------------------------------
 // y and z sweeps: march kernels
 // ---------------------------------------------------------------------------
@@ -429,13 +448,13 @@ __device__ __forceinline__ int march_start(int j0, int chunk)
     return j0 - 3 - ((U - (total % U)) % U);
 }
 
+// One lane (pencil chunk gid) of a grid.
 template <typename T, int D>
-__global__ void __launch_bounds__(256) fluid_march_kernel(SweepParams<T> P, int chunk)
+__device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int npencil = nx * (D == 1 ? nz : ny);
-    const long gid = (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
     const int nchunk = (D == 1 ? ny : nz) / chunk;
     if (gid >= (long)npencil * nchunk) return;
     const int p = (int)(gid % npencil);
@@ -544,13 +563,21 @@ __global__ void __launch_bounds__(256) fluid_march_kernel(SweepParams<T> P, int 
     }
 }
 
+// at least 4 waves per SIMD for the FP32 march (<= 128 VGPRs), 2 for FP64
+template <typename T> constexpr int march_waves() { return sizeof(T) == 4 ? 4 : 2; }
+
 template <typename T, int D>
-__global__ void __launch_bounds__(256) mag_march_kernel(SweepParams<T> P, int chunk)
+__global__ void __launch_bounds__(256, march_waves<T>()) fluid_march_kernel(SweepParams<T> P, int chunk)
+{
+    fluid_march_lane<T, D>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void mag_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int npencil = nx * (D == 1 ? nz : ny);
-    const long gid = (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
     const int nchunk = (D == 1 ? ny : nz) / chunk;
     if (gid >= (long)npencil * nchunk) return;
     const int p = (int)(gid % npencil);
@@ -664,6 +691,12 @@ __global__ void __launch_bounds__(256) mag_march_kernel(SweepParams<T> P, int ch
     }
 }
 
+template <typename T, int D>
+__global__ void __launch_bounds__(256, march_waves<T>()) mag_march_kernel(SweepParams<T> P, int chunk)
+{
+    mag_march_lane<T, D>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
@@ -723,6 +756,76 @@ hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& t
             hipLaunchKernelGGL((mag_march_kernel<T, 1>), dim3(grid), dim3(256), 0, s, P, chunk);
         else
             hipLaunchKernelGGL((mag_march_kernel<T, 2>), dim3(grid), dim3(256), 0, s, P, chunk);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched ensembles: persistent kernels over (box, tile) work items
+// ---------------------------------------------------------------------------
+// The grid is a multiple of 8 workgroups.  XCD k (hardware workgroups k,
+// k+8, ...) takes the k-th eighth of the item list, whose items belong to
+// few boxes, so neighbour pencils of one box meet in one L2.  Each item runs
+// the same tile / lane function as the single-grid kernels, so a box of an
+// ensemble evolves bit for bit like the same box on its own.
+
+template <typename T>
+__device__ __forceinline__ SweepParams<T> box_params(const BatchParams<T>& B, int box,
+                                                     const BoxDesc& bd)
+{
+    SweepParams<T> P;
+#pragma unroll
+    for (int f = 0; f < 8; ++f) {
+        P.in[f] = B.in_base[f] + bd.off + (size_t)f * bd.ncell;
+        P.out[f] = B.out_base[f] + bd.off + (size_t)f * bd.ncell;
+    }
+    P.nx = bd.n[0]; P.ny = bd.n[1]; P.nz = bd.n[2];
+    P.gamma = B.gamma;
+    P.scal = B.scal + (size_t)box * SCAL_COUNT;
+    P.flag = B.flag ? B.flag + (size_t)box * FLAG_COUNT : nullptr;
+    return P;
+}
+
+template <typename T, int OP, int D>
+__global__ void __launch_bounds__(256, D == 0 ? 1 : march_waves<T>()) batch_sweep_kernel(BatchParams<T> B)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int g8 = gridDim.x >> 3;
+    const int xcd = blockIdx.x & 7, r = blockIdx.x >> 3;
+    const int per = (B.nitems + 7) >> 3;
+    const int i0 = xcd * per;
+    const int i1 = min(B.nitems, i0 + per);
+    for (int i = i0 + r; i < i1; i += g8) {
+        const int2 it = B.items[i];
+        const BoxDesc bd = B.boxes[it.x];
+        const SweepParams<T> P = box_params(B, it.x, bd);
+        if constexpr (D == 0) {
+            if constexpr (OP == 0)
+                fluid_x_tile(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
+            else
+                mag_x_tile(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
+        } else {
+            const long gid = (long)it.y * blockDim.x + threadIdx.x;
+            if constexpr (OP == 0)
+                fluid_march_lane<T, D>(P, gid, bd.chunk[D]);
+            else
+                mag_march_lane<T, D>(P, gid, bd.chunk[D]);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_batch_op(const BatchParams<T>& B, int op, int d, int grid, hipStream_t s)
+{
+    const size_t lds = d == 0 ? sizeof(T) * (op == 0 ? 25 : 16) * 256 : 0;
+    if (op == 0) {
+        if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, 0, 0>), dim3(grid), dim3(256), lds, s, B);
+        else if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, 0, 1>), dim3(grid), dim3(256), lds, s, B);
+        else hipLaunchKernelGGL((batch_sweep_kernel<T, 0, 2>), dim3(grid), dim3(256), lds, s, B);
+    } else {
+        if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, 1, 0>), dim3(grid), dim3(256), lds, s, B);
+        else if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, 1, 1>), dim3(grid), dim3(256), lds, s, B);
+        else hipLaunchKernelGGL((batch_sweep_kernel<T, 1, 2>), dim3(grid), dim3(256), lds, s, B);
     }
     return hipGetLastError();
 }

@@ -285,21 +285,29 @@ def sod(n, axis=0, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), gamma=1.4):
 
 def solenoidal_velocity(n, seed, kmin=1, kmax=8, slope=-4.0):
     """Gaussian random-phase solenoidal velocity field with per-mode power
-    |v_k|^2 proportional to k^slope for integer |k| in [kmin, kmax], unit rms."""
+    |v_k|^2 proportional to k^slope for integer |k| in [kmin, kmax], unit rms.
+    Built on the half spectrum of a real transform (kx >= 0)."""
     nx, ny, nz = n
     rng = np.random.default_rng(seed)
-    kx = np.fft.fftfreq(nx, 1.0 / nx)[None, None, :]
+    kx = np.fft.rfftfreq(nx, 1.0 / nx)[None, None, :]
     ky = np.fft.fftfreq(ny, 1.0 / ny)[None, :, None] * (nx / ny)
     kz = np.fft.fftfreq(nz, 1.0 / nz)[:, None, None] * (nx / nz)
     kk = np.sqrt(kx ** 2 + ky ** 2 + kz ** 2)
     kint = np.rint(kk)
     mask = (kint >= kmin) & (kint <= kmax)
-    amp = np.where(mask, np.maximum(kk, 1e-30) ** (slope / 2.0), 0.0)
-    vk = [amp * (rng.normal(size=kk.shape) + 1j * rng.normal(size=kk.shape)) for _ in range(3)]
+    amp = np.where(mask, np.maximum(kk, 1e-30) ** (slope / 2.0), 0.0).astype(np.float32)
+    shape = kk.shape
+    vk = [amp * (rng.standard_normal(shape, dtype=np.float32)
+                 + 1j * rng.standard_normal(shape, dtype=np.float32)) for _ in range(3)]
     # project out the component along k
-    kv = (kx * vk[0] + ky * vk[1] + kz * vk[2]) / np.maximum(kk, 1e-30) ** 2
+    inv = np.where(kk > 0, 1.0 / np.maximum(kk, 1e-30) ** 2, 0.0).astype(np.float32)
+    kv = (kx * vk[0] + ky * vk[1] + kz * vk[2]) * inv
     vk = [vk[0] - kx * kv, vk[1] - ky * kv, vk[2] - kz * kv]
-    v = [np.real(np.fft.ifftn(c)) for c in vk]
+    try:                               # threaded FFT when scipy is present
+        import scipy.fft as sfft
+        v = [sfft.irfftn(c, s=(nz, ny, nx), workers=-1).astype(np.float64) for c in vk]
+    except ImportError:
+        v = [np.fft.irfftn(c, s=(nz, ny, nx)).astype(np.float64) for c in vk]
     rms = np.sqrt(np.mean(v[0] ** 2 + v[1] ** 2 + v[2] ** 2))
     return [c / rms for c in v]
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmhd.so")
 MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ENONPHYS, MHD_ESTATE = 0, -1, -2, -3, -4, -5
 MHD_F32, MHD_F64 = 0, 1
 MHD_TUNE_CHUNK_Y, MHD_TUNE_CHUNK_Z = 1, 2
+MHD_BATCH_GRID_X, MHD_BATCH_GRID_Y, MHD_BATCH_GRID_Z, MHD_BATCH_CHUNK = 10, 11, 12, 13
 
 _lib = None
 
@@ -69,6 +70,17 @@ def load():
         "mhd_restrict": (i, [vp, vp]),
         "mhd_set_launch": (i, [vp, i, i]),
         "mhd_get_launch": (i, [vp, i, ip]),
+        "mhd_batch_create": (vp, [i, ip, d, i, vp]),
+        "mhd_batch_destroy": (None, [vp]),
+        "mhd_batch_info": (i, [vp, ip, ctypes.POINTER(ctypes.c_longlong)]),
+        "mhd_batch_set_state": (i, [vp, i, dp, sz]),
+        "mhd_batch_get_state": (i, [vp, i, dp, sz]),
+        "mhd_batch_step_auto": (i, [vp, d]),
+        "mhd_batch_run": (i, [vp, d, i, i]),
+        "mhd_batch_status": (i, [vp, ctypes.POINTER(ctypes.c_longlong), ip]),
+        "mhd_batch_time": (i, [vp, dp]),
+        "mhd_batch_set_launch": (i, [vp, i, i]),
+        "mhd_batch_get_launch": (i, [vp, i, ip]),
         "mhd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -85,7 +97,11 @@ def exported_symbols():
                         "mhd_cfl_dt", "mhd_set_relaxation_speed", "mhd_get_relaxation_speed",
                         "mhd_fluid", "mhd_magnetic", "mhd_sweep", "mhd_step", "mhd_step_auto",
                         "mhd_status", "mhd_time", "mhd_diag", "mhd_restrict", "mhd_set_launch",
-                        "mhd_get_launch", "mhd_last_error")]
+                        "mhd_get_launch", "mhd_batch_create", "mhd_batch_destroy",
+                        "mhd_batch_info", "mhd_batch_set_state", "mhd_batch_get_state",
+                        "mhd_batch_step_auto", "mhd_batch_run", "mhd_batch_status",
+                        "mhd_batch_time", "mhd_batch_set_launch", "mhd_batch_get_launch",
+                        "mhd_last_error")]
 
 
 def last_error():
@@ -306,3 +322,79 @@ class Solver:
             t += 2.0 * dt
             dts.append(dt)
         return dts
+
+
+class Batch:
+    """Ensemble of independent periodic boxes advanced together: one
+    persistent launch per operator over all boxes, per-box CFL time step,
+    optional HIP-graph replay of the step.  dims: list of (nx, ny, nz)."""
+
+    def __init__(self, dims, gamma=5.0 / 3.0, prec="f32", stream=None):
+        self.lib = load()
+        self.dims = [tuple(int(v) for v in n) for n in dims]
+        self.nbox = len(self.dims)
+        self.prec = {"f32": MHD_F32, "f64": MHD_F64}[prec]
+        arr = (ctypes.c_int * (3 * self.nbox))(*[v for n in self.dims for v in n])
+        self.h = self.lib.mhd_batch_create(self.nbox, arr, float(gamma), self.prec,
+                                           _torch_stream(stream))
+        if not self.h:
+            raise MHDError(MHD_EINVAL, last_error())
+
+    def close(self):
+        if self.h:
+            self.lib.mhd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ncell(self):
+        return sum(n[0] * n[1] * n[2] for n in self.dims)
+
+    def shape(self, box):
+        n = self.dims[box]
+        return (8, n[2], n[1], n[0])
+
+    def set_state(self, box, s):
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        if s.shape != self.shape(box):
+            raise ValueError(f"state shape {s.shape} != {self.shape(box)}")
+        check(self.lib.mhd_batch_set_state(self.h, box,
+                                           s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), s.size))
+
+    def get_state(self, box):
+        out = np.empty(self.shape(box), dtype=np.float64)
+        check(self.lib.mhd_batch_get_state(self.h, box,
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
+        return out
+
+    def step_auto(self, cfl=0.7):
+        check(self.lib.mhd_batch_step_auto(self.h, cfl))
+
+    def run(self, nsteps, cfl=0.7, graph=True):
+        check(self.lib.mhd_batch_run(self.h, cfl, nsteps, 1 if graph else 0))
+
+    def status(self, raise_on_nonphysical=True):
+        steps = (ctypes.c_longlong * self.nbox)()
+        nonphys = (ctypes.c_int * self.nbox)()
+        r = self.lib.mhd_batch_status(self.h, steps, nonphys)
+        if r != MHD_ENONPHYS or raise_on_nonphysical:
+            check(r)
+        return np.array(steps[:]), np.array(nonphys[:])
+
+    def times(self):
+        t = (ctypes.c_double * self.nbox)()
+        check(self.lib.mhd_batch_time(self.h, t))
+        return np.array(t[:])
+
+    def set_launch(self, key, value):
+        check(self.lib.mhd_batch_set_launch(self.h, key, value))
+
+    def launch(self, key):
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_batch_get_launch(self.h, key, ctypes.byref(v)))
+        return v.value
