@@ -215,6 +215,61 @@ enum { MHD_BATCH_GRID_X = 10, MHD_BATCH_GRID_Y = 11, MHD_BATCH_GRID_Z = 12,
 int mhd_batch_set_launch(mhd_batch *b, int key, int value);
 int mhd_batch_get_launch(const mhd_batch *b, int key, int *value);
 
+/* ------------------------------------------------------------------------
+ * Learned closure of a coarse grid (an addition to the paper's method).
+ * A 3-layer periodic 3x3x3 convolutional net, 8 -> 32 -> 32 -> 8 channels
+ * with ReLU, BF16 weights and activations, FP32 accumulation on MFMA,
+ * predicts the correction that takes one plain coarse step toward the
+ * restricted fine solution.  Its 8 outputs o are projected so that the
+ * correction keeps every conserved total and every cell's div b: fluid
+ * delta_f = s_f (o_f - mean o_f), f < 5; field delta_b = discrete curl of
+ * the edge potential (s_5 o_5, s_6 o_6, s_7 o_7) (A_x on x-edges etc.).
+ * Network input: (u_f - in_mean_f) / in_std_f of the plain-stepped state.
+ * Loss: mean over channels and cells of ((delta - target)/target_scale)^2.
+ * Parameters: 41544 floats, per layer l = 1..3 the weights
+ * W[27][cin][cout] (offset o = (dz+1)*9 + (dy+1)*3 + (dx+1)) then the bias
+ * [cout].  Grid dimensions must be multiples of 32.  States and targets are
+ * FP32 device arrays [8][nz][ny][nx] (the state layout).
+ * ------------------------------------------------------------------------ */
+typedef struct mhd_closure mhd_closure;
+mhd_closure *mhd_closure_create(int nx, int ny, int nz, void *hip_stream);
+void mhd_closure_destroy(mhd_closure *c);
+int mhd_closure_set_params(mhd_closure *c, const float *params, size_t n);
+int mhd_closure_get_params(mhd_closure *c, float *params, size_t n);
+int mhd_closure_set_scales(mhd_closure *c, const float *in_mean, const float *in_std,
+                           const float *out_scale, const float *target_scale);
+/* correction of a plain-stepped state u (device, FP32) into delta (device) */
+int mhd_closure_forward(mhd_closure *c, const float *u_dev, float *delta_dev);
+/* loss against a target correction and the gradient of every parameter
+ * (grad_host may be NULL; n = 41544); synchronous */
+int mhd_closure_grad(mhd_closure *c, const float *u_dev, const float *target_dev,
+                     double *loss, float *grad_host, size_t n);
+/* forward, backward and one Adam step (beta 0.9, 0.999, eps 1e-8) on the
+ * FP32 master parameters; loss (may be NULL) makes it synchronous */
+int mhd_closure_train_step(mhd_closure *c, const float *u_dev, const float *target_dev,
+                           float lr, double *loss);
+/* One learned coarse step of an FP32 handle on the closure's stream: the
+ * plain step (mhd_step_auto) then the correction; if the corrected state has
+ * rho <= 0, p < 0 or a non-finite value the plain step is kept and counted
+ * (mhd_closure_fallbacks). */
+int mhd_closure_step(mhd_closure *c, mhd_ctx *coarse, double cfl);
+int mhd_closure_fallbacks(mhd_closure *c, int *count);
+
+/* Single periodic 3x3x3 convolution layers on MFMA (BF16 inputs rounded to
+ * nearest even, FP32 accumulate), synchronous on `stream`: n[3] grid
+ * (multiples of 32), (cin, cout) in {(8,32), (32,32), (32,8), (8,8)},
+ * weights host FP32 [27][cin][cout] (rounded to BF16).
+ * forward: x bf16 [cell][cin] -> y fp32 [cell][cout] (+ bias, may be NULL);
+ * dgrad:   dy bf16 [cell][cout] -> dx fp32 [cell][cin];
+ * wgrad:   xT bf16 [cin][cell], dyT bf16 [cout][cell] -> dw host [27][cin][cout],
+ *          dbias host [cout] (may be NULL). */
+int mhd_conv3d_forward(const int *n, int cin, int cout, const void *x, const float *w_host,
+                       const float *bias_host, float *y, void *stream);
+int mhd_conv3d_dgrad(const int *n, int cin, int cout, const void *dy, const float *w_host,
+                     float *dx, void *stream);
+int mhd_conv3d_wgrad(const int *n, int cin, int cout, const void *xT, const void *dyT,
+                     float *dw_host, float *dbias_host, void *stream);
+
 /* Thread-local message describing the last error (never NULL). */
 const char *mhd_last_error(void);
 

@@ -13,6 +13,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mhd_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "closure_oracle.c")]
 _LIB = os.path.join(_HERE, "libmhd_oracle.so")
 _lib = None
 
@@ -27,7 +28,7 @@ class NonPhysical(RuntimeError):
 def build(verbose=False):
     """Compile the oracle with gcc (no fused multiply-add, OpenMP)."""
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", _LIB, _SRC, "-lm"]
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", _LIB, *_SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -38,7 +39,7 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(p) for p in _SRCS):
         build()
     lib = ctypes.CDLL(_LIB)
     dp = ctypes.POINTER(ctypes.c_double)
@@ -51,6 +52,14 @@ def load():
     lib.oracle_diag.argtypes = [i, i, i, dp, dp]
     lib.oracle_diag.restype = None
     lib.oracle_restrict.argtypes = [i, i, i, i, dp, dp]
+    lib.oracle_conv3d.argtypes = [i, i, i, i, i, dp, dp, dp, dp]
+    lib.oracle_conv3d_dgrad.argtypes = [i, i, i, i, i, dp, dp, dp]
+    lib.oracle_conv3d_wgrad.argtypes = [i, i, i, i, i, dp, dp, dp, dp]
+    lib.oracle_closure_project.argtypes = [i, i, i, dp, dp, dp]
+    lib.oracle_closure_project_T.argtypes = [i, i, i, dp, dp, dp]
+    for fn in ("oracle_conv3d", "oracle_conv3d_dgrad", "oracle_conv3d_wgrad",
+               "oracle_closure_project", "oracle_closure_project_T"):
+        getattr(lib, fn).restype = None
     for fn in ("oracle_fluid_sweep", "oracle_mag_sweep", "oracle_sweep",
                "oracle_step", "oracle_cfl", "oracle_restrict"):
         getattr(lib, fn).restype = ctypes.c_int

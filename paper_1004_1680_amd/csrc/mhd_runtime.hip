@@ -672,6 +672,18 @@ extern "C" int mhd_get_launch(const mhd_ctx* h, int key, int* value)
     return MHD_OK;
 }
 
+void* mhd_internal_state(mhd_ctx* h, int* all_in_first_buffer)
+{
+    int all = 1;
+    for (int q = 0; q < 8; ++q) all = all && h->cur[q] == 0;
+    *all_in_first_buffer = all;
+    return h->buf[0];
+}
+int mhd_internal_prec(const mhd_ctx* h) { return h->prec; }
+void mhd_internal_dims(const mhd_ctx* h, int n[3]) { n[0] = h->n[0]; n[1] = h->n[1]; n[2] = h->n[2]; }
+hipStream_t mhd_internal_stream(const mhd_ctx* h) { return h->stream; }
+double mhd_internal_gamma(const mhd_ctx* h) { return h->gamma; }
+
 extern "C" const char* mhd_last_error(void)
 {
     return g_last_error.c_str();

@@ -14,3 +14,11 @@ int mhd_fail(int code, const char* fmt, ...);
                             __FILE__, __LINE__);                                       \
         }                                                                              \
     } while (0)
+
+// Internal accessors of a single-grid handle (used by the closure runtime).
+struct mhd_ctx;
+void* mhd_internal_state(mhd_ctx* h, int* all_in_first_buffer);  // buffer 0 base
+int mhd_internal_prec(const mhd_ctx* h);
+void mhd_internal_dims(const mhd_ctx* h, int n[3]);
+hipStream_t mhd_internal_stream(const mhd_ctx* h);
+double mhd_internal_gamma(const mhd_ctx* h);

@@ -47,6 +47,7 @@ def load():
     vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
+    fp = ctypes.POINTER(ctypes.c_float)
     sig = {
         "mhd_create": (vp, [i, i, i, d]),
         "mhd_create_ex": (vp, [i, i, i, d, i, vp]),
@@ -81,6 +82,19 @@ def load():
         "mhd_batch_time": (i, [vp, dp]),
         "mhd_batch_set_launch": (i, [vp, i, i]),
         "mhd_batch_get_launch": (i, [vp, i, ip]),
+        "mhd_closure_create": (vp, [i, i, i, vp]),
+        "mhd_closure_destroy": (None, [vp]),
+        "mhd_closure_set_params": (i, [vp, fp, sz]),
+        "mhd_closure_get_params": (i, [vp, fp, sz]),
+        "mhd_closure_set_scales": (i, [vp, fp, fp, fp, fp]),
+        "mhd_closure_forward": (i, [vp, vp, vp]),
+        "mhd_closure_grad": (i, [vp, vp, vp, dp, fp, sz]),
+        "mhd_closure_train_step": (i, [vp, vp, vp, ctypes.c_float, dp]),
+        "mhd_closure_step": (i, [vp, vp, d]),
+        "mhd_closure_fallbacks": (i, [vp, ip]),
+        "mhd_conv3d_forward": (i, [ip, i, i, vp, fp, fp, vp, vp]),
+        "mhd_conv3d_dgrad": (i, [ip, i, i, vp, fp, vp, vp]),
+        "mhd_conv3d_wgrad": (i, [ip, i, i, vp, vp, fp, fp, vp]),
         "mhd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -101,7 +115,11 @@ def exported_symbols():
                         "mhd_batch_info", "mhd_batch_set_state", "mhd_batch_get_state",
                         "mhd_batch_step_auto", "mhd_batch_run", "mhd_batch_status",
                         "mhd_batch_time", "mhd_batch_set_launch", "mhd_batch_get_launch",
-                        "mhd_last_error")]
+                        "mhd_closure_create", "mhd_closure_destroy", "mhd_closure_set_params",
+                        "mhd_closure_get_params", "mhd_closure_set_scales", "mhd_closure_forward",
+                        "mhd_closure_grad", "mhd_closure_train_step", "mhd_closure_step",
+                        "mhd_closure_fallbacks", "mhd_conv3d_forward", "mhd_conv3d_dgrad",
+                        "mhd_conv3d_wgrad", "mhd_last_error")]
 
 
 def last_error():
@@ -398,3 +416,105 @@ class Batch:
         v = ctypes.c_int(0)
         check(self.lib.mhd_batch_get_launch(self.h, key, ctypes.byref(v)))
         return v.value
+
+
+# --- learned closure ---------------------------------------------------------
+
+NPARAM = 27 * 8 * 32 + 32 + 27 * 32 * 32 + 32 + 27 * 32 * 8 + 8
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Closure:
+    """Learned correction of a coarse grid n (multiples of 32).  Device
+    arrays are torch CUDA float32 tensors of shape (8, nz, ny, nx)."""
+
+    def __init__(self, n, stream=None):
+        self.lib = load()
+        self.n = tuple(int(v) for v in n)
+        self.stream = stream
+        self.h = self.lib.mhd_closure_create(self.n[0], self.n[1], self.n[2], _torch_stream(stream))
+        if not self.h:
+            raise MHDError(MHD_EINVAL, last_error())
+
+    def close(self):
+        if self.h:
+            self.lib.mhd_closure_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        check(self.lib.mhd_closure_set_params(self.h, _fptr(p), p.size))
+
+    def params(self):
+        p = np.empty(NPARAM, dtype=np.float32)
+        check(self.lib.mhd_closure_get_params(self.h, _fptr(p), p.size))
+        return p
+
+    def set_scales(self, in_mean, in_std, out_scale, target_scale):
+        a = [np.ascontiguousarray(v, dtype=np.float32) for v in (in_mean, in_std, out_scale, target_scale)]
+        check(self.lib.mhd_closure_set_scales(self.h, *[_fptr(v) for v in a]))
+
+    def forward(self, u, out=None):
+        import torch
+        out = torch.empty_like(u) if out is None else out
+        check(self.lib.mhd_closure_forward(self.h, _dptr(u), _dptr(out)))
+        return out
+
+    def grad(self, u, target):
+        g = np.empty(NPARAM, dtype=np.float32)
+        L = ctypes.c_double(0.0)
+        check(self.lib.mhd_closure_grad(self.h, _dptr(u), _dptr(target), ctypes.byref(L), _fptr(g), g.size))
+        return L.value, g
+
+    def train_step(self, u, target, lr, want_loss=True):
+        L = ctypes.c_double(0.0)
+        check(self.lib.mhd_closure_train_step(self.h, _dptr(u), _dptr(target), ctypes.c_float(lr),
+                                              ctypes.byref(L) if want_loss else None))
+        return L.value if want_loss else None
+
+    def step(self, solver, cfl=0.7):
+        check(self.lib.mhd_closure_step(self.h, solver.h, cfl))
+
+    def fallbacks(self):
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_closure_fallbacks(self.h, ctypes.byref(v)))
+        return v.value
+
+
+def conv3d_forward(n, x, w, bias, y, stream=None):
+    """x: bf16 bits (torch int16/uint16 CUDA) [cell][cin]; w numpy [27][cin][cout];
+    y: torch float32 CUDA [cell][cout]"""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    b = None if bias is None else np.ascontiguousarray(bias, dtype=np.float32)
+    nn = (ctypes.c_int * 3)(*n)
+    check(load().mhd_conv3d_forward(nn, w.shape[1], w.shape[2], _dptr(x), _fptr(w),
+                                    _fptr(b) if b is not None else None, _dptr(y), _torch_stream(stream)))
+
+
+def conv3d_dgrad(n, dy, w, dx, stream=None):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    nn = (ctypes.c_int * 3)(*n)
+    check(load().mhd_conv3d_dgrad(nn, w.shape[1], w.shape[2], _dptr(dy), _fptr(w), _dptr(dx),
+                                  _torch_stream(stream)))
+
+
+def conv3d_wgrad(n, cin, cout, xT, dyT, stream=None):
+    dw = np.empty((27, cin, cout), dtype=np.float32)
+    db = np.empty(cout, dtype=np.float32)
+    nn = (ctypes.c_int * 3)(*n)
+    check(load().mhd_conv3d_wgrad(nn, cin, cout, _dptr(xT), _dptr(dyT), _fptr(dw), _fptr(db),
+                                  _torch_stream(stream)))
+    return dw, db

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_symbols():
     txt = open(os.path.join(ROOT, "include", "mhd.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(mhd_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(mhd_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():

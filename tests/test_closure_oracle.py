@@ -1,0 +1,88 @@
+"""Pins of the closure oracle: the convolution against an independent
+roll-based evaluation, dgrad/wgrad against the adjoint identities they must
+satisfy, the projection against the invariants it exists for (no change of
+any total, zero discrete div b) and its adjoint, and the full gradient
+against central finite differences."""
+import numpy as np
+import pytest
+
+from oracle import closure as C
+
+
+def roll_conv(x, w, b, n):
+    """y = b + sum_o shift(x, d(o)) @ w[o], with numpy rolls on the grid"""
+    nx, ny, nz = n
+    X = x.reshape(nz, ny, nx, -1)
+    y = np.zeros((nz, ny, nx, w.shape[2])) + (0 if b is None else b)
+    for o in range(27):
+        dx, dy, dz = o % 3 - 1, (o // 3) % 3 - 1, o // 9 - 1
+        S = np.roll(X, shift=(-dz, -dy, -dx), axis=(0, 1, 2))   # S[c] = X[c + d]
+        y += S @ w[o]
+    return y.reshape(nx * ny * nz, -1)
+
+
+N3 = (8, 4, 6)
+
+
+@pytest.mark.parametrize("cin,cout", [(8, 32), (32, 32), (32, 8)])
+def test_conv_matches_roll_evaluation(cin, cout):
+    rng = np.random.default_rng(cin + cout)
+    N = np.prod(N3)
+    x = rng.normal(size=(N, cin))
+    w = rng.normal(size=(27, cin, cout))
+    b = rng.normal(size=cout)
+    assert np.allclose(C.conv3d(x, w, b, N3), roll_conv(x, w, b, N3), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("cin,cout", [(8, 32), (32, 8)])
+def test_dgrad_and_wgrad_are_adjoints(cin, cout):
+    rng = np.random.default_rng(7)
+    N = np.prod(N3)
+    x = rng.normal(size=(N, cin))
+    dy = rng.normal(size=(N, cout))
+    w = rng.normal(size=(27, cin, cout))
+    # <conv(x; w), dy> = <x, dgrad(dy; w)> = <wgrad(x, dy), w>
+    lhs = np.sum(C.conv3d(x, w, None, N3) * dy)
+    assert np.sum(x * C.conv3d_dgrad(dy, w, N3)) == pytest.approx(lhs, rel=1e-12)
+    dw, db = C.conv3d_wgrad(x, dy, N3, cin, cout)
+    assert np.sum(dw * w) == pytest.approx(lhs, rel=1e-12)
+    assert np.allclose(db, dy.sum(axis=0), rtol=1e-12)
+
+
+def test_projection_keeps_totals_and_div_b():
+    rng = np.random.default_rng(3)
+    n = (8, 12, 4)
+    N = np.prod(n)
+    o = rng.normal(size=(N, 8))
+    sc = rng.uniform(0.5, 2.0, 8)
+    d = C.project(o, sc, n)
+    assert np.all(np.abs(d[:5].sum(axis=1)) < 1e-12 * np.abs(d[:5]).sum(axis=1))
+    bx, by, bz = (d[5 + k].reshape(n[2], n[1], n[0]) for k in range(3))
+    div = (np.roll(bx, -1, 2) - bx) + (np.roll(by, -1, 1) - by) + (np.roll(bz, -1, 0) - bz)
+    assert np.abs(div).max() < 1e-12 * np.abs(d[5:]).max()
+    # adjoint: <project(o), g> = <o, project_T(g)>
+    g = rng.normal(size=(8, N))
+    assert np.sum(d * g) == pytest.approx(np.sum(o * C.project_T(g, sc, n)), rel=1e-12)
+
+
+def test_gradient_matches_finite_differences():
+    n = (8, 8, 4)
+    N = np.prod(n)
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(N, 8))
+    ps = C.init_params(1)
+    sc = rng.uniform(0.5, 1.5, 8)
+    t = rng.normal(size=(8, N))
+    ts = rng.uniform(0.5, 2.0, 8)
+    L, g = C.loss_and_grad(x, ps, sc, t, ts, n)
+    v, gv = C.flatten(ps), C.flatten(g)
+    assert v.size == 41544
+    for idx in (3, 500, 6950, 7000, 20000, 34000, 41000):
+        e = 1e-6
+        vp, vm = v.copy(), v.copy()
+        vp[idx] += e
+        vm[idx] -= e
+        Lp, _ = C.loss_and_grad(x, C.unflatten(vp), sc, t, ts, n)
+        Lm, _ = C.loss_and_grad(x, C.unflatten(vm), sc, t, ts, n)
+        fd = (Lp - Lm) / (2 * e)
+        assert gv[idx] == pytest.approx(fd, rel=1e-5, abs=1e-11), idx
