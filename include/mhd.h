@@ -249,11 +249,26 @@ int mhd_closure_grad(mhd_closure *c, const float *u_dev, const float *target_dev
 int mhd_closure_train_step(mhd_closure *c, const float *u_dev, const float *target_dev,
                            float lr, double *loss);
 /* One learned coarse step of an FP32 handle on the closure's stream: the
- * plain step (mhd_step_auto) then the correction; if the corrected state has
- * rho <= 0, p < 0 or a non-finite value the plain step is kept and counted
- * (mhd_closure_fallbacks). */
+ * plain step (mhd_step_auto) then u += theta * delta with the largest theta
+ * in {1, 1/2, 1/4, 1/8} for which no cell has rho <= 0, p < 0 (pressure
+ * from the cell-centred field) or a non-finite value; if none qualifies the
+ * plain step is kept.  A uniform theta keeps the conserved totals and div b
+ * of the correction.  No host synchronisation.  Counters since creation
+ * (synchronous reads): mhd_closure_fallbacks, steps whose correction was
+ * dropped; mhd_closure_reduced, steps applied with theta < 1. */
 int mhd_closure_step(mhd_closure *c, mhd_ctx *coarse, double cfl);
 int mhd_closure_fallbacks(mhd_closure *c, int *count);
+int mhd_closure_reduced(mhd_closure *c, int *count);
+/* Training-set preparation on the closure's stream (device FP32 arrays in
+ * the state layout, 8 * nx * ny * nz values each):
+ * residual: target = u_ref - u_plain, the correction that takes the plain
+ *   coarse step u_plain to the restricted fine state u_ref (asynchronous);
+ * stats: FP64 per-field sums over the cells, out[32] = { sum u_f, sum u_f^2,
+ *   sum |u_f|, sum |target_f| } with f = 0..7 fastest (synchronous), from
+ *   which the normalisation of mhd_closure_set_scales is formed. */
+int mhd_closure_residual(mhd_closure *c, const float *u_ref_dev, const float *u_plain_dev,
+                         float *target_dev);
+int mhd_closure_stats(mhd_closure *c, const float *u_dev, const float *target_dev, double *out);
 
 /* Single periodic 3x3x3 convolution layers on MFMA (BF16 inputs rounded to
  * nearest even, FP32 accumulate), synchronous on `stream`: n[3] grid

@@ -1,0 +1,426 @@
+"""Training data, training and evaluation of the learned coarse closure.
+
+Every numerical step runs in the library's kernels through the C ABI: the
+fine and coarse solvers (mhd_step, mhd_cfl_dt), the restriction operator
+(mhd_restrict), and the closure's MFMA forward/backward and Adam
+(mhd_closure_*).  PyTorch holds device tensors and forms the per-pair
+target difference and the normalisation statistics of the training set.
+
+Data (one pair per coarse step of a fine trajectory):
+  u_c      = R u_f(t)                  restriction by r of the fine state
+  u_plain  = plain coarse step of u_c  (dt_c from the coarse CFL condition)
+  target   = R u_f(t + 2 dt_c) - u_plain, the fine run stepped to exactly
+             t + 2 dt_c (last fine step shortened)
+The closure learns u_plain -> target; its learned coarse step is
+u_plain + correction, with the plain step kept when the corrected state is
+not physical.
+
+Evaluation: from a held-out initial state, the learned coarse solver, the
+plain coarse solver and plain solvers at 2x and 4x the coarse resolution run
+to the same final time; each is restricted to the coarse grid and compared
+with the restricted fine solution (relative L1 averaged over the 8 fields),
+together with its wall time.
+"""
+import json
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import mhd
+
+FAMILIES = {1: [0], 2: [1, 2, 3], 3: [4], 4: [5, 6, 7]}
+
+
+def l1_rel(a, b):
+    """mean over the 8 fields of mean|a - b| / mean|b| (a zero reference
+    field uses the scale of its family)"""
+    errs = []
+    for idx in FAMILIES.values():
+        fam = float(np.mean(np.abs(b[idx])))
+        for f in idx:
+            den = float(np.mean(np.abs(b[f])))
+            if den == 0.0:
+                den = fam if fam > 0 else 1.0
+            errs.append(float(np.mean(np.abs(a[f] - b[f]))) / den)
+    return float(np.mean(errs))
+
+
+def _sync(torch):
+    torch.cuda.synchronize()
+
+
+def advance_to(S, t_end, cfl=0.7, t0=0.0, log=None, every=200):
+    """host-dt steps of S from time t0 to exactly t_end; returns steps"""
+    t, k = t0, 0
+    while t < t_end * (1.0 - 1e-12):
+        dt = min(S.cfl_dt(cfl), 0.5 * (t_end - t))
+        S.step(dt)
+        t += 2.0 * dt
+        k += 1
+        if log and k % every == 0:
+            log(f"[closure] {S.n[0]}^3 run: step {k}, t = {t:.4f} of {t_end:.4f}")
+    return k
+
+
+def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print):
+    """(u_plain, target) device tensor pairs from fine trajectories of the
+    Orszag-Tang family (one per seed); cl: the Closure of the coarse grid,
+    whose residual kernel forms the targets"""
+    nc = nf // r
+    F = mhd.Solver((nf,) * 3, prec="f32", stream=stream)
+    C = mhd.Solver((nc,) * 3, prec="f32", stream=stream)
+    pairs = []
+    for sd in seeds:
+        F.set_state_tensor(I.orszag_tang_torch((nf,) * 3, seed=sd))
+        t = 0.0
+        for k in range(steps_per_traj):
+            try:
+                F.restrict_to(C)
+                dtc = C.cfl_dt(cfl)
+                C.step(dtc)
+                u_plain = C.get_state_tensor().clone()
+                nfine = advance_to(F, t + 2.0 * dtc, cfl, t0=t)
+            except mhd.NonPhysicalState as e:
+                # the plain scheme does not guarantee positivity: the
+                # trajectory ends here, its earlier pairs are kept
+                log(f"[closure] seed {sd} ends at coarse step {k} (t = {t:.4f}): {e}")
+                break
+            t += 2.0 * dtc
+            F.restrict_to(C)
+            target = cl.residual(C.get_state_tensor(), u_plain)
+            pairs.append((u_plain, target))
+            if k % 8 == 0:
+                log(f"[closure] seed {sd} coarse step {k}: dt_c {dtc:.3e}, {nfine} fine steps")
+    F.close()
+    C.close()
+    return pairs
+
+
+def fit_scales(cl, pairs, mode="family"):
+    """Normalisation of the closure from the training set (FP64 per-field
+    sums from the library's statistics kernel).
+
+    in_mean, in_std: per-channel mean and standard deviation of the inputs.
+    out_scale: mean |target| pooled over each field family (density,
+      momentum, energy, magnetic field), so the network output is O(1) and
+      the three axes are treated alike.
+    target_scale (the loss weight 1 / s^2 of each field):
+      "family": the same pooled mean |target|;
+      "state":  mean |u| pooled over the family, i.e. the loss measures the
+                error relative to the size of the field, as the relative L1
+                error of the evaluation does."""
+    tot = np.zeros((4, 8))
+    n = 0
+    for u, t in pairs:
+        tot += cl.stats(u, t)
+        n += u[0].numel()
+    mean = tot[0] / n
+    var = np.maximum(tot[1] / n - mean * mean, 0.0)
+    in_std = np.sqrt(var) + 1e-6 * (np.abs(mean) + 1e-6)
+    uabs = tot[2] / n
+    tabs = tot[3] / n
+    out_scale = np.empty(8)
+    state_scale = np.empty(8)
+    for idx in FAMILIES.values():
+        out_scale[idx] = max(float(np.mean(tabs[idx])), 1e-12)
+        state_scale[idx] = max(float(np.mean(uabs[idx])), 1e-12)
+    if mode == "family":
+        target_scale = out_scale.copy()
+    elif mode == "state":
+        target_scale = state_scale
+    else:
+        raise ValueError(f"unknown scale mode {mode!r}")
+    return mean, in_std, out_scale, target_scale
+
+
+def init_params(seed=0):
+    """He-normal weights, zero biases; the last layer starts small so the
+    untrained closure is close to the plain step"""
+    rng = np.random.default_rng(seed)
+    out = []
+    for cin, cout in ((8, 32), (32, 32), (32, 8)):
+        w = rng.normal(0.0, np.sqrt(2.0 / (27 * cin)), size=(27, cin, cout))
+        if cout == 8:
+            w *= 0.01
+        out += [w.ravel(), np.zeros(cout)]
+    return np.concatenate(out).astype(np.float32)
+
+
+def pair_scales(cl, pairs):
+    """per pair, mean |target| pooled over each field family (8-vector)"""
+    out = []
+    for u, t in pairs:
+        tabs = cl.stats(u, t)[3] / u[0].numel()
+        s = np.empty(8)
+        for idx in FAMILIES.values():
+            s[idx] = max(float(np.mean(tabs[idx])), 1e-30)
+        out.append(s)
+    return out
+
+
+def train(cl, pairs, val, epochs, lr, log=print, seed=0, lr_min_frac=0.05, scales=None, weighting="global"):
+    """Adam over shuffled pairs, cosine learning-rate decay from lr to
+    lr * lr_min_frac over all steps; returns (mean train loss, validation
+    loss) per epoch.
+
+    weighting: the loss scale of each pair (the target_scale of the closure
+      during its step):
+      "global": the training-set scales (set on the closure beforehand);
+      "pair":   the pair's own mean |target| per family, so that a smooth
+                early state with a small correction weighs as much as a
+                state with shocks;
+      "sqrt":   the geometric mean of the two."""
+    rng = np.random.default_rng(seed)
+    hist = []
+    total = max(1, epochs * len(pairs))
+    step = 0
+    t_start = time.perf_counter()
+    if weighting != "global":
+        if scales is None:
+            raise ValueError("per-pair weighting needs the training-set scales")
+        ps = pair_scales(cl, pairs)
+        vs = pair_scales(cl, val) if val else []
+        g = np.asarray(scales[3], dtype=np.float64)
+        if weighting == "sqrt":
+            ps = [np.sqrt(p * g) for p in ps]
+            vs = [np.sqrt(p * g) for p in vs]
+        elif weighting != "pair":
+            raise ValueError(f"unknown weighting {weighting!r}")
+
+    def set_ts(ts):
+        cl.set_scales(scales[0], scales[1], scales[2], ts)
+
+    for ep in range(epochs):
+        order = rng.permutation(len(pairs))
+        tr = []
+        for i in order:
+            if weighting != "global":
+                set_ts(ps[i])
+            f = 0.5 * (1.0 + np.cos(np.pi * step / total))
+            tr.append(cl.train_step(pairs[i][0], pairs[i][1], lr * (lr_min_frac + (1 - lr_min_frac) * f)))
+            step += 1
+        vl = []
+        for j, (u, t) in enumerate(val or []):
+            if weighting != "global":
+                set_ts(vs[j])
+            vl.append(cl.grad(u, t)[0])
+        hist.append((float(np.mean(tr)), float(np.mean(vl)) if vl else None))
+        log(f"[closure] epoch {ep}: train loss {hist[-1][0]:.4f}"
+            + (f", validation loss {hist[-1][1]:.4f}" if vl else "")
+            + f" ({time.perf_counter() - t_start:.1f} s)")
+    if weighting != "global":
+        set_ts(scales[3])
+    return hist
+
+
+def field_errors(cl, pairs):
+    """per-field one-step residual ratio sum|target - delta| / sum|target|
+    over pairs (below 1: the correction moves the plain step toward the
+    restricted fine solution)"""
+    num = np.zeros(8)
+    den = np.zeros(8)
+    for u, t in pairs:
+        d = cl.forward(u)
+        num += cl.stats(u, cl.residual(t, d))[3]
+        den += cl.stats(u, t)[3]
+    return num / np.maximum(den, 1e-300)
+
+
+def _timed_auto(S, u0, k, cfl, torch):
+    """wall time of k device-dt steps of S from state u0 (one sync at the end)"""
+    S.set_state_tensor(u0)
+    _sync(torch)
+    t0 = time.perf_counter()
+    for _ in range(k):
+        S.step_auto(cfl)
+    S.status()
+    _sync(torch)
+    return time.perf_counter() - t0
+
+
+def evaluate(cl, nf, r, seed, nsteps, torch, stream, cfl=0.7, log=print):
+    """learned vs plain coarse solvers against the restricted fine truth.
+
+    The learned solver takes nsteps closure steps (device dt), which fixes
+    the final time T.  The fine solver and the plain solvers at nc, 2nc, 4nc
+    (below the fine size) reach exactly T with host-chosen dt (last step
+    shortened); each solution is restricted to nc and compared with the
+    restricted fine solution.  Every wall time is that of device-dt steps
+    with one synchronisation at the end: the learned run as timed, a plain
+    run as the same number of plain steps it needed to reach T."""
+    nc = nf // r
+    res = {}
+    levels = []
+    m = 1
+    while nc * m < nf and m <= 4:
+        levels.append(nc * m)
+        m *= 2
+    F = mhd.Solver((nf,) * 3, prec="f32", stream=stream)
+    F.set_state_tensor(I.orszag_tang_torch((nf,) * 3, seed=seed))
+    ics = {}
+    for n in levels:
+        P = mhd.Solver((n,) * 3, prec="f32", stream=stream)
+        F.restrict_to(P)
+        ics[n] = P.get_state_tensor().clone()
+        P.close()
+
+    C = mhd.Solver((nc,) * 3, prec="f32", stream=stream)
+    t_learned = _timed_auto_closure(cl, C, ics[nc], nsteps, cfl, torch)
+    T = C.time()
+    learned = C.get_state()
+    fallbacks = cl.fallbacks()
+    reduced = cl.reduced()
+
+    nfine = advance_to(F, T, cfl, log=log)
+    F.restrict_to(C)
+    truth = C.get_state()
+    F.close()
+    res["T"] = T
+    res["fine"] = {"n": nf, "steps": nfine}
+    res["learned"] = {"n": nc, "L1": l1_rel(learned, truth), "wall_s": t_learned, "steps": nsteps,
+                      "fallbacks": fallbacks, "reduced": reduced}
+
+    for n in levels:
+        P = mhd.Solver((n,) * 3, prec="f32", stream=stream)
+        P.set_state_tensor(ics[n])
+        k = advance_to(P, T, cfl, log=log)
+        if n != nc:
+            P.restrict_to(C)
+            st = C.get_state()
+        else:
+            st = P.get_state()
+        wall = _timed_auto(P, ics[n], k, cfl, torch)
+        P.close()
+        res[f"plain_{n}"] = {"n": n, "L1": l1_rel(st, truth), "wall_s": wall, "steps": k}
+        log(f"[closure] plain {n}^3: L1 {res[f'plain_{n}']['L1']:.4e}, {k} steps in {wall:.4f} s")
+    C.close()
+    log(f"[closure] learned {nc}^3: L1 {res['learned']['L1']:.4e}, {nsteps} steps in {t_learned:.4f} s "
+        f"({reduced} reduced, {fallbacks} dropped corrections)")
+
+    # plain wall time at the learned L1 (log-log interpolation between the
+    # plain resolutions that bracket it)
+    plains = [(res[f"plain_{n}"]["L1"], res[f"plain_{n}"]["wall_s"]) for n in levels]
+    L = res["learned"]["L1"]
+    eq = None
+    for (l0, w0), (l1, w1) in zip(plains, plains[1:]):
+        if l1 <= L <= l0 and l0 > l1:
+            a = (np.log(l0) - np.log(L)) / (np.log(l0) - np.log(l1))
+            eq = float(np.exp((1 - a) * np.log(w0) + a * np.log(w1)))
+            break
+    res["plain_wall_at_equal_L1_s"] = eq
+    res["speedup_at_equal_L1"] = (eq / t_learned) if eq else None
+    return res
+
+
+def _timed_auto_closure(cl, C, u0, k, cfl, torch):
+    C.set_state_tensor(u0)
+    _sync(torch)
+    t0 = time.perf_counter()
+    for _ in range(k):
+        cl.step(C, cfl)
+    C.status()
+    _sync(torch)
+    return time.perf_counter() - t0
+
+
+def save(path, cl, scales, meta=None):
+    """trained closure -> .npz (parameters, the four scale vectors, metadata
+    as a JSON string)"""
+    np.savez(path, params=cl.params(), in_mean=np.asarray(scales[0]), in_std=np.asarray(scales[1]),
+             out_scale=np.asarray(scales[2]), target_scale=np.asarray(scales[3]),
+             meta=np.array(json.dumps(meta or {})))
+
+
+def load(path, n, stream=None):
+    """Closure of grid n with the parameters and scales stored by save()"""
+    z = np.load(path, allow_pickle=False)
+    cl = mhd.Closure(n, stream=stream)
+    cl.set_params(z["params"])
+    scales = (z["in_mean"], z["in_std"], z["out_scale"], z["target_scale"])
+    cl.set_scales(*scales)
+    return cl, scales, json.loads(str(z["meta"]))
+
+
+def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, steps_per_traj=24,
+                  val_steps=None, epochs=10, lr=1e-3, cfl=0.7, scale_mode="family", log=print,
+                  weighting="global"):
+    """data generation and training; returns (closure, scales, info)"""
+    import torch
+    stream = torch.cuda.current_stream()
+    nc = nf // r
+    cl = mhd.Closure((nc,) * 3, stream=stream)
+    t0 = time.perf_counter()
+    pairs = generate_pairs(cl, nf, r, train_seeds, steps_per_traj, stream, cfl, log)
+    val = generate_pairs(cl, nf, r, (val_seed,), val_steps or steps_per_traj, stream, cfl, log)
+    _sync(torch)
+    t_data = time.perf_counter() - t0
+    scales = fit_scales(cl, pairs, scale_mode)
+    cl.set_params(init_params(0))
+    cl.set_scales(*scales)
+    val_loss0 = float(np.mean([cl.grad(u, t)[0] for u, t in val]))
+    t0 = time.perf_counter()
+    hist = train(cl, pairs, val, epochs, lr, log, scales=scales, weighting=weighting)
+    _sync(torch)
+    t_train = time.perf_counter() - t0
+    fe = field_errors(cl, val)
+    log("[closure] validation one-step residual ratio per field: " + " ".join(f"{v:.3f}" for v in fe))
+    info = {"nf": nf, "ratio": r, "train_seeds": list(train_seeds), "steps_per_traj": steps_per_traj,
+            "pairs": len(pairs), "data_s": t_data, "train_s": t_train, "epochs": epochs, "lr": lr,
+            "train_steps": epochs * len(pairs), "val_loss_untrained": val_loss0, "history": hist,
+            "val_field_residual": fe.tolist(), "scale_mode": scale_mode, "weighting": weighting}
+    del pairs, val
+    return cl, scales, info
+
+
+def run(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, test_seed=200, steps_per_traj=24,
+        epochs=10, lr=1e-3, eval_steps=24, cfl=0.7, scale_mode="family", log=print, weighting="global"):
+    """train then evaluate; returns (result dict, closure)"""
+    import torch
+    stream = torch.cuda.current_stream()
+    cl, scales, info = train_closure(nf, r, train_seeds, val_seed, steps_per_traj, None, epochs, lr, cfl,
+                                     scale_mode, log, weighting)
+    res = evaluate(cl, nf, r, test_seed, eval_steps, torch, stream, cfl, log)
+    res.update(info)
+    res["scales"] = [np.asarray(v).tolist() for v in scales]
+    return res, cl
+
+
+if __name__ == "__main__":
+    import argparse
+    ap = argparse.ArgumentParser(description="train / evaluate the learned coarse closure")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--nf", type=int, default=256)
+    t.add_argument("--ratio", type=int, default=8)
+    t.add_argument("--seeds", type=int, default=12, help="training trajectories (seeds 1..N)")
+    t.add_argument("--steps", type=int, default=24, help="coarse steps (pairs) per trajectory")
+    t.add_argument("--val-steps", type=int, default=None)
+    t.add_argument("--epochs", type=int, default=10)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--weighting", default="global", choices=("global", "pair", "sqrt"))
+    t.add_argument("--out", required=True, help=".npz file for the trained closure")
+    e = sub.add_parser("eval")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--steps", type=int, default=200, help="learned coarse steps of the rollout")
+    e.add_argument("--seed", type=int, default=200, help="held-out initial state")
+    args = ap.parse_args()
+    say = lambda m: print(m, flush=True)
+    import torch
+    stream = torch.cuda.current_stream()
+    if args.cmd == "train":
+        cl, scales, info = train_closure(args.nf, args.ratio, tuple(range(1, args.seeds + 1)),
+                                         steps_per_traj=args.steps, val_steps=args.val_steps,
+                                         epochs=args.epochs, lr=args.lr, log=say,
+                                         weighting=args.weighting)
+        save(args.out, cl, scales, info)
+        print(json.dumps(info))
+    else:
+        z = np.load(args.weights, allow_pickle=False)
+        meta = json.loads(str(z["meta"]))
+        nf, r = meta["nf"], meta["ratio"]
+        cl, scales, meta = load(args.weights, (nf // r,) * 3, stream)
+        res = evaluate(cl, nf, r, args.seed, args.steps, torch, stream, log=say)
+        res["training"] = {k: meta[k] for k in ("pairs", "epochs", "train_steps", "data_s", "train_s")
+                           if k in meta}
+        print(json.dumps(res))

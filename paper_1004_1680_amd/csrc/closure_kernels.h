@@ -60,10 +60,14 @@ hipError_t launch_project_T(const float* g, const double* gmean, const int n[3],
                             hipStream_t s);
 hipError_t launch_loss(const float* delta, const float* target, size_t N, const ClosureScales& sc, float* g,
                        double* partial, double* out, hipStream_t s);
-hipError_t launch_apply_guard(const float* u, const float* delta, const int n[3], float gamma, float* unew,
-                              int* bad, hipStream_t s);
-hipError_t launch_cond_copy(const float* src, float* dst, size_t n, const int* bad, int* fallbacks, hipStream_t s);
+constexpr int GUARD_LEVELS = 4;     // theta = 1, 1/2, 1/4, 1/8
+hipError_t launch_guard_levels(const float* u, const float* delta, const int n[3], float gamma, int* bad,
+                               hipStream_t s);
+hipError_t launch_apply_level(float* u, const float* delta, size_t n, const int* bad, int* counts, hipStream_t s);
 hipError_t launch_zero_int(int* p, hipStream_t s);
+constexpr int STATS_BLOCKS = 256;
+hipError_t launch_residual(const float* ref, const float* plain, size_t n, float* out, hipStream_t s);
+hipError_t launch_stats(const float* u, const float* t, size_t N, double* partial, double* out, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
 

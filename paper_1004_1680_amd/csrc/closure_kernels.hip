@@ -520,57 +520,80 @@ hipError_t launch_loss(const float* delta, const float* target, size_t N, const 
     return hipGetLastError();
 }
 
-// u_new = u + delta; raises *bad if a cell has rho <= 0, p < 0 or a
-// non-finite value (pressure from the cell-centred field of u_new)
-__global__ void apply_guard_kernel(const float* __restrict__ u, const float* __restrict__ delta, int nx, int ny,
-                                   int nz, float gamma, float* __restrict__ unew, int* bad)
+// Guard of the corrected state u + theta delta for theta = 2^-k, k = 0..3:
+// bit k of *bad is raised if some cell has rho <= 0, p < 0 or a non-finite
+// value at that theta (pressure from the cell-centred field, the mean of
+// the two faces).
+__global__ void guard_levels_kernel(const float* __restrict__ u, const float* __restrict__ delta, int nx, int ny,
+                                    int nz, float gamma, int* bad)
 {
     const size_t N = (size_t)nx * ny * nz;
     int b = 0;
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
-        const size_t cx = (size_t)wrap1(i + 1, nx) + (size_t)nx * (j + (size_t)ny * k);
-        const size_t cy = (size_t)i + (size_t)nx * (wrap1(j + 1, ny) + (size_t)ny * k);
-        const size_t cz = (size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k + 1, nz));
-        float v[8];
+        const size_t cn[3] = { (size_t)wrap1(i + 1, nx) + (size_t)nx * (j + (size_t)ny * k),
+                               (size_t)i + (size_t)nx * (wrap1(j + 1, ny) + (size_t)ny * k),
+                               (size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k + 1, nz)) };
+        float u0[8], d0[8], u1[3], d1[3];
         for (int f = 0; f < 8; ++f) {
-            v[f] = u[(size_t)f * N + c] + delta[(size_t)f * N + c];
-            unew[(size_t)f * N + c] = v[f];
+            u0[f] = u[(size_t)f * N + c];
+            d0[f] = delta[(size_t)f * N + c];
         }
-        const float bx = 0.5f * (v[5] + u[5 * N + cx] + delta[5 * N + cx]);
-        const float by = 0.5f * (v[6] + u[6 * N + cy] + delta[6 * N + cy]);
-        const float bz = 0.5f * (v[7] + u[7 * N + cz] + delta[7 * N + cz]);
-        const float p = (gamma - 1.0f) * (v[4] - 0.5f * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0] -
-                                           0.5f * (bx * bx + by * by + bz * bz));
-        bool ok = v[0] > 0.0f && p >= 0.0f;
-        for (int f = 0; f < 8; ++f) ok = ok && isfinite(v[f]);
-        if (!ok) b = 1;
+        for (int a = 0; a < 3; ++a) {
+            u1[a] = u[(size_t)(5 + a) * N + cn[a]];
+            d1[a] = delta[(size_t)(5 + a) * N + cn[a]];
+        }
+        for (int lev = 0; lev < GUARD_LEVELS; ++lev) {
+            const float th = ldexpf(1.0f, -lev);
+            float v[8];
+            bool ok = true;
+            for (int f = 0; f < 8; ++f) {
+                v[f] = u0[f] + th * d0[f];
+                ok = ok && isfinite(v[f]);
+            }
+            float b2 = 0.0f;
+            for (int a = 0; a < 3; ++a) {
+                const float bc = 0.5f * (v[5 + a] + (u1[a] + th * d1[a]));
+                b2 += bc * bc;
+            }
+            const float p = (gamma - 1.0f) * (v[4] - 0.5f * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0] -
+                                               0.5f * b2);
+            ok = ok && v[0] > 0.0f && p >= 0.0f;
+            if (!ok) b |= 1 << lev;
+        }
     }
-    if (b) atomicOr(bad, 1);
+    if (b) atomicOr(bad, b);
 }
 
-hipError_t launch_apply_guard(const float* u, const float* delta, const int n[3], float gamma, float* unew,
-                              int* bad, hipStream_t s)
+hipError_t launch_guard_levels(const float* u, const float* delta, const int n[3], float gamma, int* bad,
+                               hipStream_t s)
 {
-    hipLaunchKernelGGL(apply_guard_kernel, dim3(2048), dim3(256), 0, s, u, delta, n[0], n[1], n[2], gamma, unew, bad);
+    hipLaunchKernelGGL(guard_levels_kernel, dim3(2048), dim3(256), 0, s, u, delta, n[0], n[1], n[2], gamma, bad);
     return hipGetLastError();
 }
 
-// dst = src unless *bad (then dst stays, and *fallbacks counts it)
-__global__ void cond_copy_kernel(const float* __restrict__ src, float* __restrict__ dst, size_t n, const int* bad,
-                                 int* fallbacks)
+// u += theta delta with the largest theta = 2^-k whose guard bit is clear;
+// none clear: u stays (the plain step).  counts[0] counts dropped
+// corrections, counts[1] reduced ones (theta < 1).
+__global__ void apply_level_kernel(float* __restrict__ u, const float* __restrict__ delta, size_t n, const int* bad,
+                                   int* counts)
 {
-    if (*bad) {
-        if (blockIdx.x == 0 && threadIdx.x == 0 && fallbacks) *fallbacks += 1;
-        return;
+    const int mask = *bad;
+    int lev = 0;
+    while (lev < GUARD_LEVELS && (mask >> lev) & 1) ++lev;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && counts) {
+        if (lev == GUARD_LEVELS) counts[0] += 1;
+        else if (lev > 0) counts[1] += 1;
     }
+    if (lev == GUARD_LEVELS) return;
+    const float th = ldexpf(1.0f, -lev);
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
-        dst[t] = src[t];
+        u[t] = u[t] + th * delta[t];
 }
 
-hipError_t launch_cond_copy(const float* src, float* dst, size_t n, const int* bad, int* fallbacks, hipStream_t s)
+hipError_t launch_apply_level(float* u, const float* delta, size_t n, const int* bad, int* counts, hipStream_t s)
 {
-    hipLaunchKernelGGL(cond_copy_kernel, dim3(2048), dim3(256), 0, s, src, dst, n, bad, fallbacks);
+    hipLaunchKernelGGL(apply_level_kernel, dim3(2048), dim3(256), 0, s, u, delta, n, bad, counts);
     return hipGetLastError();
 }
 
@@ -600,6 +623,66 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, floa
 {
     const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
     hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+// target = u_ref - u_plain, elementwise over 8N values
+__global__ void residual_kernel(const float* __restrict__ ref, const float* __restrict__ plain, size_t n,
+                                float* __restrict__ out)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        out[t] = ref[t] - plain[t];
+}
+
+hipError_t launch_residual(const float* ref, const float* plain, size_t n, float* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(residual_kernel, dim3(2048), dim3(256), 0, s, ref, plain, n, out);
+    return hipGetLastError();
+}
+
+// Per-field sums of a field-major pair (u, t), blockIdx.y = field:
+// partial[(b * 8 + f) * 4 + {0,1,2,3}] = sum u, sum u^2, sum |u|, sum |t|
+__global__ void __launch_bounds__(256) stats_partial_kernel(const float* __restrict__ u,
+                                                            const float* __restrict__ t, size_t N,
+                                                            double* __restrict__ partial)
+{
+    const int f = blockIdx.y;
+    const float* uf = u + (size_t)f * N;
+    const float* tf = t + (size_t)f * N;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < N; c += (size_t)gridDim.x * 256) {
+        const double x = uf[c];
+        a0 += x;
+        a1 += x * x;
+        a2 += fabs(x);
+        a3 += fabs((double)tf[c]);
+    }
+    __shared__ double sh[4][256];
+    sh[0][threadIdx.x] = a0; sh[1][threadIdx.x] = a1; sh[2][threadIdx.x] = a2; sh[3][threadIdx.x] = a3;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partial[((size_t)blockIdx.x * 8 + f) * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// out[q * 8 + f] = sum over blocks of partial[(b * 8 + f) * 4 + q]
+__global__ void stats_final_kernel(const double* __restrict__ partial, int nblk, double* __restrict__ out)
+{
+    const int k = threadIdx.x;
+    if (k >= 32) return;
+    const int q = k / 8, f = k % 8;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += partial[((size_t)b * 8 + f) * 4 + q];
+    out[k] = acc;
+}
+
+hipError_t launch_stats(const float* u, const float* t, size_t N, double* partial, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(stats_partial_kernel, dim3(STATS_BLOCKS, 8), dim3(256), 0, s, u, t, N, partial);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(64), 0, s, partial, STATS_BLOCKS, out);
     return hipGetLastError();
 }
 

@@ -4,8 +4,9 @@
 // takes one plain coarse step toward the restricted fine solution.  The
 // output is projected so that the correction changes no conserved total and
 // no cell's div b (mean-free fluid corrections, discrete curl of an edge
-// potential); a correction that would leave the physical range is dropped
-// (the plain step is kept).  Training: MSE loss, backward pass on the same
+// potential); a correction that would leave the physical range is scaled
+// by the largest of 1, 1/2, 1/4, 1/8 that keeps every cell physical, or
+// dropped (the plain step is kept).  Training: MSE loss, backward pass on the same
 // MFMA kernels, Adam on FP32 master weights.
 #include <hip/hip_runtime.h>
 
@@ -44,9 +45,9 @@ struct mhd_closure {
     uint16_t* wpT[3];      // packed dgrad weights (layers 2, 3)
     bool packed;
     uint16_t *x0, *x0T, *a1, *a1T, *a2, *a2T, *gob, *gobT, *g2, *g2T, *g1, *g1T;
-    float *o, *delta, *g, *go, *unew;
+    float *o, *delta, *g, *go;
     float* wpart;          // wgrad partials
-    double *chpart, *chout, *loss;
+    double *chpart, *chout, *loss, *stpart, *stout;
     int *bad, *fallbacks;
     int rows_per_wg, nwg;
 };
@@ -64,8 +65,8 @@ extern "C" void mhd_closure_destroy(mhd_closure* c)
     (void)hipStreamSynchronize(c->stream);
     void* ptrs[] = { c->params, c->grads, c->adam_m, c->adam_v, c->wp[0], c->wp[1], c->wp[2], c->wpT[0],
                      c->wpT[1], c->wpT[2], c->x0, c->x0T, c->a1, c->a1T, c->a2, c->a2T, c->gob, c->gobT,
-                     c->g2, c->g2T, c->g1, c->g1T, c->o, c->delta, c->g, c->go, c->unew, c->wpart,
-                     c->chpart, c->chout, c->loss, c->bad, c->fallbacks };
+                     c->g2, c->g2T, c->g1, c->g1T, c->o, c->delta, c->g, c->go, c->wpart,
+                     c->chpart, c->chout, c->loss, c->stpart, c->stout, c->bad, c->fallbacks };
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -104,10 +105,11 @@ extern "C" mhd_closure* mhd_closure_create(int nx, int ny, int nz, void* hip_str
     A((void**)&c->g2, N * 32 * 2); A((void**)&c->g2T, N * 32 * 2);
     A((void**)&c->g1, N * 32 * 2); A((void**)&c->g1T, N * 32 * 2);
     A((void**)&c->o, N * 8 * 4); A((void**)&c->delta, N * 8 * 4); A((void**)&c->g, N * 8 * 4);
-    A((void**)&c->go, N * 8 * 4); A((void**)&c->unew, N * 8 * 4);
+    A((void**)&c->go, N * 8 * 4);
     A((void**)&c->wpart, (size_t)c->nwg * 27 * 32 * 32 * 4);
     A((void**)&c->chpart, (size_t)CHSUM_BLOCKS * 8 * 8); A((void**)&c->chout, 16 * 8);
-    A((void**)&c->loss, 8); A((void**)&c->bad, 4); A((void**)&c->fallbacks, 4);
+    A((void**)&c->loss, 8); A((void**)&c->bad, 4); A((void**)&c->fallbacks, 8);
+    A((void**)&c->stpart, (size_t)STATS_BLOCKS * 8 * 4 * 8); A((void**)&c->stout, 32 * 8);
     if (!ok) {
         (void)hipGetLastError();
         mhd_fail(MHD_ENOMEM, "closure allocation failed");
@@ -115,7 +117,7 @@ extern "C" mhd_closure* mhd_closure_create(int nx, int ny, int nz, void* hip_str
         return nullptr;
     }
     ok = hipMemset(c->params, 0, NPARAM * 4) == hipSuccess && hipMemset(c->adam_m, 0, NPARAM * 4) == hipSuccess &&
-         hipMemset(c->adam_v, 0, NPARAM * 4) == hipSuccess && hipMemset(c->fallbacks, 0, 4) == hipSuccess &&
+         hipMemset(c->adam_v, 0, NPARAM * 4) == hipSuccess && hipMemset(c->fallbacks, 0, 8) == hipSuccess &&
          hipMemset(c->bad, 0, 4) == hipSuccess;
     if (!ok) {
         mhd_fail(MHD_EDEVICE, "closure initialisation failed");
@@ -294,8 +296,29 @@ extern "C" int mhd_closure_step(mhd_closure* c, mhd_ctx* coarse, double cfl)
     if (!all0) return mhd_fail(MHD_ESTATE, "coarse state not in its first buffer");
     if ((r = forward(c, u))) return r;
     HIP_TRY(c, launch_zero_int(c->bad, c->stream));
-    HIP_TRY(c, launch_apply_guard(u, c->delta, c->n, (float)mhd_internal_gamma(coarse), c->unew, c->bad, c->stream));
-    HIP_TRY(c, launch_cond_copy(c->unew, u, c->N * 8, c->bad, c->fallbacks, c->stream));
+    HIP_TRY(c, launch_guard_levels(u, c->delta, c->n, (float)mhd_internal_gamma(coarse), c->bad, c->stream));
+    HIP_TRY(c, launch_apply_level(u, c->delta, c->N * 8, c->bad, c->fallbacks, c->stream));
+    return MHD_OK;
+}
+
+extern "C" int mhd_closure_residual(mhd_closure* c, const float* u_ref_dev, const float* u_plain_dev,
+                                    float* target_dev)
+{
+    int r = check_cl(c);
+    if (r) return r;
+    if (!u_ref_dev || !u_plain_dev || !target_dev) return mhd_fail(MHD_EINVAL, "null device pointer");
+    HIP_TRY(c, launch_residual(u_ref_dev, u_plain_dev, c->N * 8, target_dev, c->stream));
+    return MHD_OK;
+}
+
+extern "C" int mhd_closure_stats(mhd_closure* c, const float* u_dev, const float* target_dev, double* out)
+{
+    int r = check_cl(c);
+    if (r) return r;
+    if (!u_dev || !target_dev || !out) return mhd_fail(MHD_EINVAL, "null pointer");
+    HIP_TRY(c, launch_stats(u_dev, target_dev, c->N, c->stpart, c->stout, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(out, c->stout, 32 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MHD_OK;
 }
 
@@ -305,6 +328,16 @@ extern "C" int mhd_closure_fallbacks(mhd_closure* c, int* count)
     if (r) return r;
     if (!count) return mhd_fail(MHD_EINVAL, "null output");
     HIP_TRY(c, hipMemcpyAsync(count, c->fallbacks, 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MHD_OK;
+}
+
+extern "C" int mhd_closure_reduced(mhd_closure* c, int* count)
+{
+    int r = check_cl(c);
+    if (r) return r;
+    if (!count) return mhd_fail(MHD_EINVAL, "null output");
+    HIP_TRY(c, hipMemcpyAsync(count, c->fallbacks + 1, 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MHD_OK;
 }

@@ -359,3 +359,53 @@ def ensemble_spec(nbox=64, seed=4, sizes=ENSEMBLE_SIZES):
         beta = float(10 ** rng.uniform(-1.0, 1.0))
         spec.append((n, mach, beta, seed * 1000 + b))
     return spec
+
+
+# --------------------------------------------------------------------------
+# device-side generation (torch) for grids too large to build on the host
+# --------------------------------------------------------------------------
+
+def orszag_tang_phases(seed):
+    """random phase shifts (5 numbers in [0, 1)) of an Orszag-Tang-family
+    member; seed 0 gives the unshifted state"""
+    if seed == 0:
+        return np.zeros(5)
+    return np.random.default_rng(seed).uniform(0.0, 1.0, 5)
+
+
+def orszag_tang_torch(n, seed=0, dtype=None, device="cuda", gamma=GAMMA):
+    """The Orszag-Tang-type state of `orszag_tang`, with each sine shifted by
+    a seeded phase (b_x(y), b_y(x) keep depending only on the transverse
+    coordinate, so div b = 0 exactly), built directly in device memory as a
+    torch tensor of shape (8, nz, ny, nx)."""
+    import torch
+    dtype = dtype or torch.float32
+    nx, ny, nz = n
+    h = 1.0 / nx
+    ph = orszag_tang_phases(seed)
+    tp = 2.0 * np.pi
+    ar = lambda m, off: (torch.arange(m, device=device, dtype=torch.float64) + off) * h
+    xc = ar(nx, 0.5).view(1, 1, nx)
+    yc = ar(ny, 0.5).view(1, ny, 1)
+    zc = ar(nz, 0.5).view(nz, 1, 1)
+    rho = 25.0 / (36.0 * np.pi)
+    p = 5.0 / (12.0 * np.pi)
+    s4p = np.sqrt(4.0 * np.pi)
+    out = torch.empty((8, nz, ny, nx), dtype=dtype, device=device)
+    vx = -torch.sin(tp * (yc + ph[0]))
+    vy = torch.sin(tp * (xc + ph[1]))
+    vz = 0.1 * torch.sin(tp * (zc + ph[2]))
+    bx = -torch.sin(tp * (yc + ph[3])) / s4p          # on x-faces, function of y
+    by = torch.sin(2 * tp * (xc + ph[4])) / s4p       # on y-faces, function of x
+    # cell-centred field = mean of the two faces along each axis: b_x and b_y
+    # are constant along their own axis, so the mean equals the face value
+    out[0] = rho
+    out[1] = rho * vx
+    out[2] = rho * vy
+    out[3] = rho * vz
+    ke = 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    out[4] = p / (gamma - 1.0) + ke + 0.5 * (bx * bx + by * by)
+    out[5] = bx
+    out[6] = by
+    out[7] = 0.0
+    return out

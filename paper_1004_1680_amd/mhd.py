@@ -92,6 +92,9 @@ def load():
         "mhd_closure_train_step": (i, [vp, vp, vp, ctypes.c_float, dp]),
         "mhd_closure_step": (i, [vp, vp, d]),
         "mhd_closure_fallbacks": (i, [vp, ip]),
+        "mhd_closure_reduced": (i, [vp, ip]),
+        "mhd_closure_residual": (i, [vp, vp, vp, vp]),
+        "mhd_closure_stats": (i, [vp, vp, vp, dp]),
         "mhd_conv3d_forward": (i, [ip, i, i, vp, fp, fp, vp, vp]),
         "mhd_conv3d_dgrad": (i, [ip, i, i, vp, fp, vp, vp]),
         "mhd_conv3d_wgrad": (i, [ip, i, i, vp, vp, fp, fp, vp]),
@@ -118,7 +121,8 @@ def exported_symbols():
                         "mhd_closure_create", "mhd_closure_destroy", "mhd_closure_set_params",
                         "mhd_closure_get_params", "mhd_closure_set_scales", "mhd_closure_forward",
                         "mhd_closure_grad", "mhd_closure_train_step", "mhd_closure_step",
-                        "mhd_closure_fallbacks", "mhd_conv3d_forward", "mhd_conv3d_dgrad",
+                        "mhd_closure_fallbacks", "mhd_closure_reduced", "mhd_closure_residual", "mhd_closure_stats",
+                        "mhd_conv3d_forward", "mhd_conv3d_dgrad",
                         "mhd_conv3d_wgrad", "mhd_last_error")]
 
 
@@ -492,6 +496,25 @@ class Closure:
         v = ctypes.c_int(0)
         check(self.lib.mhd_closure_fallbacks(self.h, ctypes.byref(v)))
         return v.value
+
+    def reduced(self):
+        """learned steps whose correction was applied with theta < 1"""
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_closure_reduced(self.h, ctypes.byref(v)))
+        return v.value
+
+    def residual(self, u_ref, u_plain, out=None):
+        """target = u_ref - u_plain (device tensors, computed by the library)"""
+        import torch
+        out = torch.empty_like(u_plain) if out is None else out
+        check(self.lib.mhd_closure_residual(self.h, _dptr(u_ref), _dptr(u_plain), _dptr(out)))
+        return out
+
+    def stats(self, u, target):
+        """FP64 per-field sums: rows sum u, sum u^2, sum |u|, sum |target|"""
+        out = (ctypes.c_double * 32)()
+        check(self.lib.mhd_closure_stats(self.h, _dptr(u), _dptr(target), out))
+        return np.array(out[:]).reshape(4, 8)
 
 
 def conv3d_forward(n, x, w, bias, y, stream=None):

@@ -213,3 +213,76 @@ def test_closure_step_falls_back_on_unphysical_correction(env):
     B.step_auto(0.7)
     assert cl.fallbacks() == 1
     assert not np.array_equal(A.get_state(), B.get_state())
+
+
+def test_training_set_residual_and_statistics(env):
+    """target = u_ref - u_plain bit for bit (one FP32 subtraction per value);
+    the FP64 per-field sums against numpy's FP64 sums of the same values"""
+    torch, mhd = env
+    say("case: closure residual and statistics kernels")
+    rng = np.random.default_rng(11)
+    n = N3
+    shape = (8, n[2], n[1], n[0])
+    ur = rng.normal(1.0, 0.3, size=shape).astype(np.float32)
+    up = (ur + rng.normal(0.0, 1e-2, size=shape)).astype(np.float32)
+    cl = mhd.Closure(n)
+    t = cl.residual(torch.from_numpy(ur).cuda(), torch.from_numpy(up).cuda())
+    tn = t.cpu().numpy()
+    assert np.array_equal(tn, ur - up)
+    st = cl.stats(torch.from_numpy(up).cuda(), t)
+    u64 = up.astype(np.float64).reshape(8, -1)
+    t64 = tn.astype(np.float64).reshape(8, -1)
+    ref = np.stack([u64.sum(1), (u64 * u64).sum(1), np.abs(u64).sum(1), np.abs(t64).sum(1)])
+    assert np.allclose(st, ref, rtol=1e-12, atol=0.0)
+
+
+def _physical(u, gamma=5.0 / 3.0):
+    """per-cell rho > 0 and p >= 0 (cell-centred field = mean of the faces),
+    FP64, and the smallest pressure"""
+    b = [0.5 * (u[5] + np.roll(u[5], -1, 2)), 0.5 * (u[6] + np.roll(u[6], -1, 1)),
+         0.5 * (u[7] + np.roll(u[7], -1, 0))]
+    p = (gamma - 1.0) * (u[4] - 0.5 * (u[1] ** 2 + u[2] ** 2 + u[3] ** 2) / u[0]
+                         - 0.5 * (b[0] ** 2 + b[1] ** 2 + b[2] ** 2))
+    return bool((u[0] > 0).all() and (p >= 0).all()), float(p.min()), float(u[0].min())
+
+
+def test_closure_step_scales_a_correction_down_to_stay_physical(env):
+    """A correction that is non-physical at theta = 1 but clearly physical at
+    theta = 1/2 is applied at 1/2: u_plain + fl(0.5 * delta) bit for bit."""
+    torch, mhd = env
+    say("case: closure guard levels")
+    n = N3
+    s = I.random_smooth(n, seed=8)
+    prob = closure_problem(seed=2)
+    stream = torch.cuda.current_stream()
+    B = mhd.Solver(n, prec="f32", stream=stream)
+    B.set_state(s)
+    B.step_auto(0.7)
+    ub = B.get_state_tensor().clone()
+    plain = ub.cpu().numpy().astype(np.float64)
+    cl = mhd.Closure(n, stream=stream)
+    cl.set_params(C.flatten(C.init_params(3)).astype(np.float32))
+    cl.set_scales(prob[1], prob[2], np.ones(8, dtype=np.float32), np.ones(8))
+    d1 = cl.forward(ub).cpu().numpy().astype(np.float64)
+    # the smallest scale t at which u + t d1 leaves the physical range
+    lo, hi = 0.0, 1.0
+    while _physical(plain + hi * d1)[0]:
+        hi *= 2.0
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if _physical(plain + mid * d1)[0] else (lo, mid)
+    sigma = 1.6 * hi
+    ok1, pmin1, rmin1 = _physical(plain + sigma * d1)
+    ok2, pmin2, rmin2 = _physical(plain + 0.5 * sigma * d1)
+    say("t*", hi, "theta=1:", ok1, pmin1, rmin1, " theta=1/2:", ok2, pmin2, rmin2)
+    assert not ok1 and ok2
+    assert min(pmin1, rmin1) < -1e-3 and min(pmin2, rmin2) > 1e-3   # clear of FP32 rounding
+    cl.set_scales(prob[1], prob[2], np.full(8, sigma, dtype=np.float32), np.ones(8))
+    delta = cl.forward(ub).cpu().numpy()
+    A = mhd.Solver(n, prec="f32", stream=stream)
+    A.set_state(s)
+    cl.step(A)
+    got = A.get_state_tensor().cpu().numpy()
+    want = ub.cpu().numpy() + np.float32(0.5) * delta
+    assert cl.reduced() == 1 and cl.fallbacks() == 0
+    assert np.array_equal(got, want)
