@@ -6,7 +6,8 @@ conservative projection (mean-free fluid corrections, discrete curl of an
 edge potential for b) -> delta, and u = u_plain + delta.  Convolutions are
 periodic 3x3x3 with channel-last activations; the loss is the mean squared
 error of delta against the target correction, each channel divided by its
-target scale.  Everything here is plain FP64 (C loops in
+target scale.  With a roughness gate g(u) (gate()), the projection acts on
+g * o, cell by cell.  Everything here is plain FP64 (C loops in
 closure_oracle.c, composed in numpy).
 """
 import ctypes
@@ -68,6 +69,14 @@ def project_T(g, scale, n):
     return go
 
 
+def gate(u, R, n):
+    """u[8][cell] (field-major state), R[8] > 0 -> g[cell]"""
+    u, R = _c(u).reshape(8, -1), _c(R)
+    g = np.empty(u.shape[1])
+    load().oracle_closure_gate(n[0], n[1], n[2], _p(u), _p(R), _p(g))
+    return g
+
+
 def init_params(seed=0):
     """He-normal weights, zero biases (w[27][cin][cout] per layer)."""
     rng = np.random.default_rng(seed)
@@ -96,29 +105,31 @@ def normalize(u, mean, std):
     return ((u - mean[:, None]) / std[:, None]).T.copy()
 
 
-def forward(x, ps, scale, n, keep=False):
-    """x[cell][8] -> delta[8][cell]; with keep, also the activations"""
+def forward(x, ps, scale, n, keep=False, g=None):
+    """x[cell][8] -> delta[8][cell]; with keep, also the activations; g:
+    the roughness gate per cell (None: no gate)"""
     w1, b1, w2, b2, w3, b3 = ps
     z1 = conv3d(x, w1, b1, n)
     a1 = np.maximum(z1, 0.0)
     z2 = conv3d(a1, w2, b2, n)
     a2 = np.maximum(z2, 0.0)
     o = conv3d(a2, w3, b3, n)
-    d = project(o, scale, n)
+    d = project(o if g is None else o * g[:, None], scale, n)
     if keep:
         return d, (x, a1, a2, o)
     return d
 
 
-def loss_and_grad(x, ps, scale, target, tscale, n):
+def loss_and_grad(x, ps, scale, target, tscale, n, g=None):
     """L = mean over channels and cells of ((delta - target)/tscale)^2 and
-    its gradient with respect to every parameter"""
-    d, (x0, a1, a2, o) = forward(x, ps, scale, n, keep=True)
-    N = x.shape[0]
+    its gradient with respect to every parameter (g: roughness gate)"""
+    d, (x0, a1, a2, o) = forward(x, ps, scale, n, keep=True, g=g)
     r = (d - target) / tscale[:, None]
     L = float(np.mean(r * r))
-    g = 2.0 * r / tscale[:, None] / r.size
-    go = project_T(g, scale, n)
+    gd = 2.0 * r / tscale[:, None] / r.size
+    go = project_T(gd, scale, n)
+    if g is not None:
+        go = go * g[:, None]
     w1, b1, w2, b2, w3, b3 = ps
     dw3, db3 = conv3d_wgrad(a2, go, n, 32, 8)
     g2 = conv3d_dgrad(go, w3, n) * (a2 > 0)

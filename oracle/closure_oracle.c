@@ -19,7 +19,15 @@
  *                so the discrete div of delta_b vanishes in every cell.
  * project_T applies the adjoint map (gradient of a scalar through the
  * projection).
+ *
+ * Roughness gate (optional): with R[8] > 0 (training-set means),
+ *   r_f(c) = sum over the three axes a of |u_f(c+a) - 2 u_f(c) + u_f(c-a)|,
+ *   g0(c)  = (1/8) sum_f r_f(c) / R_f,
+ *   g(c)   = max of g0 over c and its six face neighbours,
+ * and the projection acts on g(c) o(c) instead of o(c): corrections vanish
+ * where the state is locally linear, whatever the network outputs.
  */
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -161,4 +169,41 @@ void oracle_closure_project_T(int nx, int ny, int nz, const double *g, const dou
                 /* A_x enters by[c - z] (+), by[c] (-), bz[c - y] (-), bz[c] (+) */
                 go[c * 8 + 5] += scale[5] * ((g[6 * N + czm] - g[6 * N + c]) - (g[7 * N + cym] - g[7 * N + c]));
             }
+}
+
+/* u[f][cell] (field-major) -> g[cell] */
+void oracle_closure_gate(int nx, int ny, int nz, const double *u, const double *R, double *g)
+{
+    size_t N = (size_t)nx * ny * nz;
+    double *g0 = (double *)malloc(N * sizeof(double));
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                size_t c = cidx(nx, ny, nz, i, j, k);
+                size_t nb[6] = { cidx(nx, ny, nz, i + 1, j, k), cidx(nx, ny, nz, i - 1, j, k),
+                                 cidx(nx, ny, nz, i, j + 1, k), cidx(nx, ny, nz, i, j - 1, k),
+                                 cidx(nx, ny, nz, i, j, k + 1), cidx(nx, ny, nz, i, j, k - 1) };
+                double acc = 0.0;
+                for (int f = 0; f < 8; f++) {
+                    const double *uf = u + (size_t)f * N;
+                    double r = 0.0;
+                    for (int a = 0; a < 3; a++)
+                        r += fabs(uf[nb[2 * a]] - 2.0 * uf[c] + uf[nb[2 * a + 1]]);
+                    acc += r / R[f];
+                }
+                g0[c] = acc / 8.0;
+            }
+    for (int k = 0; k < nz; k++)
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                size_t c = cidx(nx, ny, nz, i, j, k);
+                double m = g0[c];
+                size_t nb[6] = { cidx(nx, ny, nz, i + 1, j, k), cidx(nx, ny, nz, i - 1, j, k),
+                                 cidx(nx, ny, nz, i, j + 1, k), cidx(nx, ny, nz, i, j - 1, k),
+                                 cidx(nx, ny, nz, i, j, k + 1), cidx(nx, ny, nz, i, j, k - 1) };
+                for (int q = 0; q < 6; q++)
+                    if (g0[nb[q]] > m) m = g0[nb[q]];
+                g[c] = m;
+            }
+    free(g0);
 }

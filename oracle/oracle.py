@@ -57,8 +57,9 @@ def load():
     lib.oracle_conv3d_wgrad.argtypes = [i, i, i, i, i, dp, dp, dp, dp]
     lib.oracle_closure_project.argtypes = [i, i, i, dp, dp, dp]
     lib.oracle_closure_project_T.argtypes = [i, i, i, dp, dp, dp]
+    lib.oracle_closure_gate.argtypes = [i, i, i, dp, dp, dp]
     for fn in ("oracle_conv3d", "oracle_conv3d_dgrad", "oracle_conv3d_wgrad",
-               "oracle_closure_project", "oracle_closure_project_T"):
+               "oracle_closure_project", "oracle_closure_project_T", "oracle_closure_gate"):
         getattr(lib, fn).restype = None
     for fn in ("oracle_fluid_sweep", "oracle_mag_sweep", "oracle_sweep",
                "oracle_step", "oracle_cfl", "oracle_restrict"):

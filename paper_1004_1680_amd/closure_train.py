@@ -239,18 +239,33 @@ def _timed_auto(S, u0, k, cfl, torch):
     return time.perf_counter() - t0
 
 
-def evaluate(cl, nf, r, seed, nsteps, torch, stream, cfl=0.7, log=print):
+def _equal_l1_wall(plains, L):
+    """plain wall time at L1 = L, log-log interpolated between the two plain
+    resolutions whose L1 brackets L (None outside their range)"""
+    for (l0, w0), (l1, w1) in zip(plains, plains[1:]):
+        if l1 <= L <= l0 and l0 > l1:
+            a = (np.log(l0) - np.log(L)) / (np.log(l0) - np.log(l1))
+            return float(np.exp((1 - a) * np.log(w0) + a * np.log(w1)))
+    return None
+
+
+def evaluate(cl, nf, r, seed, nsteps, torch, stream, cfl=0.7, log=print, checkpoints=None):
     """learned vs plain coarse solvers against the restricted fine truth.
 
-    The learned solver takes nsteps closure steps (device dt), which fixes
-    the final time T.  The fine solver and the plain solvers at nc, 2nc, 4nc
-    (below the fine size) reach exactly T with host-chosen dt (last step
-    shortened); each solution is restricted to nc and compared with the
-    restricted fine solution.  Every wall time is that of device-dt steps
-    with one synchronisation at the end: the learned run as timed, a plain
-    run as the same number of plain steps it needed to reach T."""
+    The learned solver takes nsteps closure steps (device dt); the times it
+    reaches after the checkpoint step counts (default: nsteps only) are the
+    comparison times.  The fine solver and the plain solvers at nc, 2nc, 4nc
+    (below the fine size) advance through those times exactly (host dt, the
+    step before each time shortened); each solution is restricted to nc and
+    compared with the restricted fine solution (relative L1 over the 8
+    fields).  Should the fine run leave the physical range, the comparison
+    ends at the last time it reached.  Wall times are those of device-dt
+    steps with one synchronisation at the end: the learned run as timed
+    between checkpoints, a plain run as the same number of plain steps it
+    needed to reach the last compared time.  Returns a dict with one entry
+    per checkpoint and the summary of the last one at top level."""
     nc = nf // r
-    res = {}
+    checkpoints = sorted(set(checkpoints or [nsteps]) | {nsteps})
     levels = []
     m = 1
     while nc * m < nf and m <= 4:
@@ -265,63 +280,98 @@ def evaluate(cl, nf, r, seed, nsteps, torch, stream, cfl=0.7, log=print):
         ics[n] = P.get_state_tensor().clone()
         P.close()
 
+    # learned rollout, states kept at the checkpoints
     C = mhd.Solver((nc,) * 3, prec="f32", stream=stream)
-    t_learned = _timed_auto_closure(cl, C, ics[nc], nsteps, cfl, torch)
-    T = C.time()
-    learned = C.get_state()
-    fallbacks = cl.fallbacks()
-    reduced = cl.reduced()
+    C.set_state_tensor(ics[nc])
+    learned, times, walls = [], [], []
+    done, wall = 0, 0.0
+    for ck in checkpoints:
+        _sync(torch)
+        t0 = time.perf_counter()
+        try:
+            for _ in range(ck - done):
+                cl.step(C, cfl)
+            C.status()
+        except mhd.NonPhysicalState as e:
+            log(f"[closure] learned run left the physical range before step {ck}: {e}")
+            break
+        _sync(torch)
+        wall += time.perf_counter() - t0
+        done = ck
+        learned.append(C.get_state())
+        times.append(C.time())
+        walls.append(wall)
+    if not times:
+        C.close()
+        F.close()
+        raise mhd.MHDError(mhd.MHD_ENONPHYS, "learned run failed before the first comparison time")
+    checkpoints = checkpoints[:len(times)]
+    fallbacks, reduced = cl.fallbacks(), cl.reduced()
+    log(f"[closure] learned {nc}^3: {done} steps to t = {times[-1]:.4f} in {wall:.4f} s "
+        f"({reduced} reduced, {fallbacks} dropped corrections)")
 
-    nfine = advance_to(F, T, cfl, log=log)
-    F.restrict_to(C)
-    truth = C.get_state()
+    # fine truth through the checkpoint times
+    truth, nfine, t = [], 0, 0.0
+    try:
+        for T in times:
+            nfine += advance_to(F, T, cfl, t0=t, log=log)
+            t = T
+            F.restrict_to(C)
+            truth.append(C.get_state())
+    except mhd.NonPhysicalState as e:
+        log(f"[closure] fine run left the physical range after t = {t:.4f}: {e}")
     F.close()
-    res["T"] = T
-    res["fine"] = {"n": nf, "steps": nfine}
-    res["learned"] = {"n": nc, "L1": l1_rel(learned, truth), "wall_s": t_learned, "steps": nsteps,
-                      "fallbacks": fallbacks, "reduced": reduced}
+    ncmp = len(truth)
+    if ncmp == 0:
+        C.close()
+        raise mhd.MHDError(mhd.MHD_ENONPHYS, "fine run failed before the first comparison time")
 
+    per = [{"steps": checkpoints[i], "t": times[i], "learned_L1": l1_rel(learned[i], truth[i]),
+            "learned_wall_s": walls[i]} for i in range(ncmp)]
+    plain_summary = {}
     for n in levels:
         P = mhd.Solver((n,) * 3, prec="f32", stream=stream)
         P.set_state_tensor(ics[n])
-        k = advance_to(P, T, cfl, log=log)
-        if n != nc:
-            P.restrict_to(C)
-            st = C.get_state()
-        else:
-            st = P.get_state()
-        wall = _timed_auto(P, ics[n], k, cfl, torch)
+        k, t = 0, 0.0
+        try:
+            for i in range(ncmp):
+                k += advance_to(P, times[i], cfl, t0=t, log=log)
+                t = times[i]
+                if n != nc:
+                    P.restrict_to(C)
+                    st = C.get_state()
+                else:
+                    st = P.get_state()
+                per[i][f"plain_{n}_L1"] = l1_rel(st, truth[i])
+                per[i][f"plain_{n}_steps"] = k
+        except mhd.NonPhysicalState as e:
+            log(f"[closure] plain {n}^3 left the physical range after t = {t:.4f}: {e}")
+        wall_n = _timed_auto(P, ics[n], k, cfl, torch) if k else None
         P.close()
-        res[f"plain_{n}"] = {"n": n, "L1": l1_rel(st, truth), "wall_s": wall, "steps": k}
-        log(f"[closure] plain {n}^3: L1 {res[f'plain_{n}']['L1']:.4e}, {k} steps in {wall:.4f} s")
+        plain_summary[n] = (k, wall_n)
+        last = per[ncmp - 1].get(f"plain_{n}_L1")
+        log(f"[closure] plain {n}^3: L1 {last if last is None else f'{last:.4e}'}, {k} steps in "
+            f"{wall_n if wall_n is None else f'{wall_n:.4f}'} s")
     C.close()
-    log(f"[closure] learned {nc}^3: L1 {res['learned']['L1']:.4e}, {nsteps} steps in {t_learned:.4f} s "
-        f"({reduced} reduced, {fallbacks} dropped corrections)")
+    for i in range(ncmp):
+        log(f"[closure] t = {per[i]['t']:.4f} ({per[i]['steps']} steps): learned L1 {per[i]['learned_L1']:.4e}, "
+            + ", ".join(f"plain {n}^3 {per[i][f'plain_{n}_L1']:.4e}" for n in levels
+                        if f"plain_{n}_L1" in per[i]))
 
-    # plain wall time at the learned L1 (log-log interpolation between the
-    # plain resolutions that bracket it)
-    plains = [(res[f"plain_{n}"]["L1"], res[f"plain_{n}"]["wall_s"]) for n in levels]
-    L = res["learned"]["L1"]
-    eq = None
-    for (l0, w0), (l1, w1) in zip(plains, plains[1:]):
-        if l1 <= L <= l0 and l0 > l1:
-            a = (np.log(l0) - np.log(L)) / (np.log(l0) - np.log(l1))
-            eq = float(np.exp((1 - a) * np.log(w0) + a * np.log(w1)))
-            break
+    fin = per[ncmp - 1]
+    res = {"T": fin["t"], "compared_steps": fin["steps"], "checkpoints": per,
+           "fine": {"n": nf, "steps": nfine},
+           "learned": {"n": nc, "L1": fin["learned_L1"], "wall_s": fin["learned_wall_s"], "steps": fin["steps"],
+                       "fallbacks": fallbacks, "reduced": reduced}}
+    for n in levels:
+        k, w = plain_summary[n]
+        if f"plain_{n}_L1" in fin:
+            res[f"plain_{n}"] = {"n": n, "L1": fin[f"plain_{n}_L1"], "wall_s": w, "steps": k}
+    plains = [(res[f"plain_{n}"]["L1"], res[f"plain_{n}"]["wall_s"]) for n in levels if f"plain_{n}" in res]
+    eq = _equal_l1_wall(plains, res["learned"]["L1"])
     res["plain_wall_at_equal_L1_s"] = eq
-    res["speedup_at_equal_L1"] = (eq / t_learned) if eq else None
+    res["speedup_at_equal_L1"] = (eq / res["learned"]["wall_s"]) if eq else None
     return res
-
-
-def _timed_auto_closure(cl, C, u0, k, cfl, torch):
-    C.set_state_tensor(u0)
-    _sync(torch)
-    t0 = time.perf_counter()
-    for _ in range(k):
-        cl.step(C, cfl)
-    C.status()
-    _sync(torch)
-    return time.perf_counter() - t0
 
 
 def save(path, cl, scales, meta=None):
@@ -404,6 +454,7 @@ if __name__ == "__main__":
     e.add_argument("--weights", required=True)
     e.add_argument("--steps", type=int, default=200, help="learned coarse steps of the rollout")
     e.add_argument("--seed", type=int, default=200, help="held-out initial state")
+    e.add_argument("--checkpoints", type=str, default="", help="comma-separated step counts")
     args = ap.parse_args()
     say = lambda m: print(m, flush=True)
     import torch
@@ -420,7 +471,8 @@ if __name__ == "__main__":
         meta = json.loads(str(z["meta"]))
         nf, r = meta["nf"], meta["ratio"]
         cl, scales, meta = load(args.weights, (nf // r,) * 3, stream)
-        res = evaluate(cl, nf, r, args.seed, args.steps, torch, stream, log=say)
+        cks = [int(v) for v in args.checkpoints.split(",") if v] or None
+        res = evaluate(cl, nf, r, args.seed, args.steps, torch, stream, log=say, checkpoints=cks)
         res["training"] = {k: meta[k] for k in ("pairs", "epochs", "train_steps", "data_s", "train_s")
                            if k in meta}
         print(json.dumps(res))

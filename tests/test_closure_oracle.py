@@ -86,3 +86,85 @@ def test_gradient_matches_finite_differences():
         Lm, _ = C.loss_and_grad(x, C.unflatten(vm), sc, t, ts, n)
         fd = (Lp - Lm) / (2 * e)
         assert gv[idx] == pytest.approx(fd, rel=1e-5, abs=1e-11), idx
+
+
+def test_gate_vanishes_on_linear_and_uniform_states():
+    """second differences of a uniform state are zero; along a periodic axis
+    a linear profile is impossible, but a profile linear within the interior
+    gives nonzero r only next to its wrap-around jump"""
+    n = (8, 6, 4)
+    N = np.prod(n)
+    u = np.ones((8, N)) * np.arange(1, 9)[:, None]
+    assert np.all(C.gate(u, np.ones(8), n) == 0.0)
+    # u_0 = i (x index): r_0 = |jump terms| only at i = 0 and i = nx - 1
+    i = np.arange(N) % n[0]
+    u = np.zeros((8, N))
+    u[0] = i
+    g = C.gate(u, np.ones(8), n).reshape(n[2], n[1], n[0])
+    # g0 at i = 0: |1 - 0 + (nx - 1)| ... = |u(1) - 2u(0) + u(nx-1)| = nx;
+    # at i = nx - 1: |u(0) - 2(nx-1) + u(nx-2)| = nx; elsewhere 0; / 8
+    g0 = np.zeros(n[0])
+    g0[0] = g0[-1] = n[0] / 8.0
+    want = np.maximum.reduce([g0, np.roll(g0, 1), np.roll(g0, -1)])
+    assert np.array_equal(g, np.broadcast_to(want, g.shape))
+
+
+def test_gate_of_a_sine_matches_its_closed_form():
+    """u_f = sin(2 pi k x_i / nx): second difference = -4 sin^2(pi k / nx) u;
+    g0 = (1/8) sum_f r_f / R_f, then the max over the 7-point stencil"""
+    n = (16, 4, 4)
+    N = np.prod(n)
+    i = np.arange(N) % n[0]
+    k = 3
+    u = np.zeros((8, N))
+    R = np.arange(1.0, 9.0)
+    for f in (1, 4, 6):
+        u[f] = (f + 1) * np.sin(2 * np.pi * k * i / n[0])
+    s2 = 4 * np.sin(np.pi * k / n[0]) ** 2
+    g0 = sum((f + 1) * s2 * np.abs(np.sin(2 * np.pi * k * np.arange(n[0]) / n[0])) / R[f]
+             for f in (1, 4, 6)) / 8.0
+    want = np.maximum.reduce([g0, np.roll(g0, 1), np.roll(g0, -1)])
+    g = C.gate(u, R, n).reshape(n[2], n[1], n[0])
+    assert np.allclose(g, np.broadcast_to(want, g.shape), rtol=1e-12, atol=1e-14)
+
+
+def test_gate_spreads_one_point_to_its_face_neighbours():
+    n = (6, 5, 7)
+    N = np.prod(n)
+    u = np.zeros((8, N))
+    u[3].reshape(n[2], n[1], n[0])[2, 2, 2] = 1.0
+    g = C.gate(u, np.ones(8), n).reshape(n[2], n[1], n[0])
+    # g0: 6/8 at the point (three axes, |-2| each), 1/8 at its 6 neighbours
+    assert g[2, 2, 2] == 6 / 8
+    for d in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+        assert g[2 + d[0], 2 + d[1], 2 + d[2]] == 6 / 8
+    # cells two faces away and the 12 edge-diagonal cells see a neighbour's 1/8
+    assert g[2, 2, 4] == 1 / 8 and g[2, 3, 3] == 1 / 8
+    assert g[5, 2, 2] == 0.0
+    assert np.count_nonzero(g) == 1 + 6 + 6 + 12
+
+
+def test_gated_gradient_matches_finite_differences():
+    n = (8, 8, 4)
+    N = np.prod(n)
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(N, 8))
+    ps = C.init_params(2)
+    sc = rng.uniform(0.5, 1.5, 8)
+    t = rng.normal(size=(8, N))
+    ts = rng.uniform(0.5, 2.0, 8)
+    g = rng.uniform(0.0, 2.0, N)
+    L, gr = C.loss_and_grad(x, ps, sc, t, ts, n, g=g)
+    v, gv = C.flatten(ps), C.flatten(gr)
+    for idx in (3, 6950, 20000, 41000, 41540):
+        e = 1e-6
+        vp, vm = v.copy(), v.copy()
+        vp[idx] += e
+        vm[idx] -= e
+        Lp, _ = C.loss_and_grad(x, C.unflatten(vp), sc, t, ts, n, g=g)
+        Lm, _ = C.loss_and_grad(x, C.unflatten(vm), sc, t, ts, n, g=g)
+        assert gv[idx] == pytest.approx((Lp - Lm) / (2 * e), rel=1e-5, abs=1e-11), idx
+    # the gate multiplies the network output before the projection
+    d = C.forward(x, ps, sc, n, g=g)
+    _, (_, _, _, o) = C.forward(x, ps, sc, n, keep=True)
+    assert np.allclose(d, C.project(o * g[:, None], sc, n), rtol=1e-13, atol=1e-15)
