@@ -14,8 +14,15 @@ Also reported:
  * cpu_baseline: the FP64 CPU oracle on one full step of the same workload
    on the host cores (a bounded sample), scaled to Mcell-updates/s.
 
+The closure128 workload times the learned coarse step on a 128^3 grid (plain
+step + BF16 MFMA network + gate + projection + guard) and a training step,
+with the MFMA roofline of the network's forward pass; with --closure-eval it
+also rolls out trained weights against the restricted 1024^3 solution and
+plain 128^3 / 256^3 / 512^3 runs (learned vs plain at equal L1).
+
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload turb256|ot512|ot1024|turb256-f64] [--no-cpu]
+                       [--workload turb256|ot512|ot1024|turb256-f64|ensemble64|closure128]
+                       [--no-cpu] [--closure-weights W.npz [--closure-eval]]
 """
 import argparse
 import json
@@ -30,6 +37,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mcell-updates/s/GPU + %HBM roofline; learned-coarse vs plain at equal L1"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0          # dense MFMA, MI355X
+# closure network: 27 offsets x (8*32 + 32*32 + 32*8) multiply-adds per cell
+CLOSURE_FLOP_PER_CELL = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 8)
 
 # algorithmic bytes per cell of one launch, in units of the element size:
 # fluid reads rho, m (3), e and the three face fields it averages into the
@@ -48,6 +58,11 @@ WORKLOADS = {
                   desc="3D Orszag-Tang-type 512^3, FP32 state"),
     "ot1024": dict(n=1024, prec="f32", ic="orszag_tang",
                    desc="3D Orszag-Tang-type 1024^3, FP32 state (2 x 34.4 GB)"),
+    "closure128": dict(n=128, prec="f32", ic="closure",
+                       desc="learned coarse step on 128^3 (8x restriction of 1024^3): plain FP32 "
+                            "step + 3-layer 3^3 conv net 8->32->32->8 (BF16 MFMA, FP32 accumulate), "
+                            "roughness gate, conservative projection, guard; Orszag-Tang-type "
+                            "state (seed 200)"),
     "ensemble64": dict(n=0, prec="f32", ic="ensemble",
                        desc="64 periodic boxes, sizes drawn from {32,48,64,96,128,192,256}^3 "
                             "(seed 4), per-box turbulence with Mach in [0.5,3], beta in "
@@ -157,6 +172,141 @@ def run_ensemble(args, wl, torch, mhd):
     print(json.dumps(out), flush=True)
 
 
+def run_closure(args, wl, torch, mhd):
+    from paper_1004_1680_amd import closure_train as CT
+    from paper_1004_1680_amd import inputs as I
+    n = wl["n"]
+    ncell = n ** 3
+    stream = torch.cuda.current_stream()
+    C = mhd.Solver((n, n, n), prec="f32", stream=stream)
+    u0 = I.orszag_tang_torch((n, n, n), seed=200)
+    C.set_state_tensor(u0)
+    if args.closure_weights:
+        cl, scales, meta = CT.load(args.closure_weights, (n, n, n), stream)
+        wdesc = f"trained weights {os.path.basename(args.closure_weights)}"
+    else:
+        # untrained network with the scales of the state itself: the cost of a
+        # step does not depend on the weights
+        cl = mhd.Closure((n, n, n), stream=stream)
+        cl.set_params(CT.init_params(0))
+        st = cl.stats(u0, u0)
+        mean = st[0] / ncell
+        std = np.sqrt(np.maximum(st[1] / ncell - mean ** 2, 0.0)) + 1e-6
+        cl.set_scales(mean, std, np.full(8, 1e-4), np.full(8, 1e-4))
+        R = st[4] / ncell
+        cl.set_gate(np.maximum(R, 1e-6 * max(R.max(), 1e-30)))
+        wdesc = "untrained weights (timing only)"
+    log(f"[bench] closure {n}^3, {wdesc}; warm-up")
+    for _ in range(args.warmup):
+        cl.step(C, args.cfl)
+    C.status()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} learned steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cl.step(C, args.cfl)
+    C.status()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_learned = el * 1e3 / args.steps
+    value = ncell * args.steps / el / 1e6
+    # plain step at the same size, same state
+    C.set_state_tensor(u0)
+    for _ in range(args.warmup):
+        C.step_auto(args.cfl)
+    C.status()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        C.step_auto(args.cfl)
+    C.status()
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) * 1e3 / args.steps
+    # network forward pass (3 MFMA convolutions + gate + projection), HIP
+    # events on the closure's stream
+    u = C.get_state_tensor()
+    out = torch.empty_like(u)
+    cl.forward(u, out)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.kernel_reps):
+        cl.forward(u, out)
+    e1.record(stream)
+    e1.synchronize()
+    ms_fwd = e0.elapsed_time(e1) / args.kernel_reps
+    # training step (forward, loss, backward, Adam), no host synchronisation
+    tgt = torch.zeros_like(u)
+    saved = cl.params()
+    cl.train_step(u, tgt, 1e-6, want_loss=False)
+    e0.record(stream)
+    for _ in range(args.kernel_reps):
+        cl.train_step(u, tgt, 1e-6, want_loss=False)
+    e1.record(stream)
+    e1.synchronize()
+    ms_train = e0.elapsed_time(e1) / args.kernel_reps
+    cl.set_params(saved)
+    tflops = CLOSURE_FLOP_PER_CELL * ncell / (ms_fwd * 1e-3) / 1e12
+    out_line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_learned, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f32",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "grid": [n, n, n], "cfl": args.cfl, "weights": wdesc,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "kernel": "closure forward (conv 8->32, 32->32, 32->8 + gate + projection)",
+                     "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tflops / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                     "alg_flop_per_cell": CLOSURE_FLOP_PER_CELL},
+        "plain_ms_per_step": round(ms_plain, 4),
+        "forward_ms": round(ms_fwd, 4),
+        "train_step_ms": round(ms_train, 4),
+        "train_tflops": round(3 * CLOSURE_FLOP_PER_CELL * ncell / (ms_train * 1e-3) / 1e12, 1),
+        "fallbacks": cl.fallbacks(), "reduced": cl.reduced(),
+    }
+    C.close()
+    if args.closure_eval:
+        if not args.closure_weights:
+            raise SystemExit("--closure-eval needs --closure-weights")
+        log("[bench] learned vs plain rollout against the restricted 1024^3 solution")
+        res = CT.evaluate(cl, 1024, 8, 200, 200, torch, stream, args.cfl,
+                          log=lambda m: log(m), checkpoints=[10, 25, 50, 100, 150, 200])
+        out_line["learned_vs_plain"] = {k: res[k] for k in ("T", "compared_steps", "learned", "plain_128",
+                                                             "plain_256", "plain_512", "plain_wall_at_equal_L1_s",
+                                                             "speedup_at_equal_L1", "checkpoints") if k in res}
+    cl.close()
+    if not args.no_cpu:
+        log("[bench] cpu baseline (oracle)")
+        out_line["cpu_baseline"] = cpu_baseline_closure()
+    print(json.dumps(out_line), flush=True)
+
+
+def cpu_baseline_closure():
+    """the oracle's plain step and FP64 network forward (with gate and
+    projection) on a 64^3 sample"""
+    import oracle
+    from oracle import closure as OC
+    from paper_1004_1680_amd import inputs as I
+    n = 64
+    s = I.orszag_tang((n, n, n))
+    oracle.load()
+    ps = OC.init_params(0)
+    u = s.reshape(8, -1)
+    mean, std = u.mean(axis=1), u.std(axis=1) + 1e-6
+    t0 = time.perf_counter()
+    dt, vmax = oracle.cfl(s)
+    s1 = oracle.step(s, dt, vmax)
+    u1 = s1.reshape(8, -1)
+    g = OC.gate(u1, np.ones(8), (n, n, n))
+    OC.forward(OC.normalize(u1, mean, std), ps, np.full(8, 1e-4), (n, n, n), g=g)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": round(n ** 3 / el / 1e6, 4), "unit": "Mcell-updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"1 learned step at {n}^3 (plain FP64 step + FP64 network forward, gate, "
+                      f"projection); {el:.2f} s wall"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +316,9 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.7)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--closure-weights", default=None, help="trained closure (.npz) for closure128")
+    ap.add_argument("--closure-eval", action="store_true",
+                    help="closure128: also evaluate learned vs plain against the 1024^3 solution")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -180,6 +333,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if wl["ic"] == "ensemble":
         return run_ensemble(args, wl, torch, mhd)
+    if wl["ic"] == "closure":
+        return run_closure(args, wl, torch, mhd)
     n = wl["n"]
     ncell = n ** 3
     esize = 8 if wl["prec"] == "f64" else 4

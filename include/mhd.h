@@ -263,12 +263,23 @@ int mhd_closure_reduced(mhd_closure *c, int *count);
  * the state layout, 8 * nx * ny * nz values each):
  * residual: target = u_ref - u_plain, the correction that takes the plain
  *   coarse step u_plain to the restricted fine state u_ref (asynchronous);
- * stats: FP64 per-field sums over the cells, out[32] = { sum u_f, sum u_f^2,
- *   sum |u_f|, sum |target_f| } with f = 0..7 fastest (synchronous), from
- *   which the normalisation of mhd_closure_set_scales is formed. */
+ * stats: FP64 per-field sums over the cells, out[40] = { sum u_f, sum u_f^2,
+ *   sum |u_f|, sum |target_f|, sum r_f } with f = 0..7 fastest and r_f the
+ *   roughness below (synchronous), from which the normalisation of
+ *   mhd_closure_set_scales and mhd_closure_set_gate is formed. */
 int mhd_closure_residual(mhd_closure *c, const float *u_ref_dev, const float *u_plain_dev,
                          float *target_dev);
 int mhd_closure_stats(mhd_closure *c, const float *u_dev, const float *target_dev, double *out);
+/* Roughness gate of the correction (off after create).  With mean
+ * roughness R[8] > 0 (host): r_f(c) = sum over the three axes of
+ * |u_f(c+a) - 2 u_f(c) + u_f(c-a)| on the network input u, g0(c) =
+ * (1/8) sum_f r_f(c) / R_f, g(c) = max of g0 over c and its six face
+ * neighbours, and the projection acts on g(c) o(c): the correction (and its
+ * gradient) vanishes where the state is locally linear.  R = NULL turns the
+ * gate off.  get_gate copies the gate of the last forward pass (device,
+ * nx*ny*nz floats). */
+int mhd_closure_set_gate(mhd_closure *c, const float *mean_roughness);
+int mhd_closure_get_gate(mhd_closure *c, float *gate_dev);
 
 /* Single periodic 3x3x3 convolution layers on MFMA (BF16 inputs rounded to
  * nearest even, FP32 accumulate), synchronous on `stream`: n[3] grid

@@ -110,7 +110,7 @@ def fit_scales(cl, pairs, mode="family"):
       "state":  mean |u| pooled over the family, i.e. the loss measures the
                 error relative to the size of the field, as the relative L1
                 error of the evaluation does."""
-    tot = np.zeros((4, 8))
+    tot = np.zeros((5, 8))
     n = 0
     for u, t in pairs:
         tot += cl.stats(u, t)
@@ -132,6 +132,18 @@ def fit_scales(cl, pairs, mode="family"):
     else:
         raise ValueError(f"unknown scale mode {mode!r}")
     return mean, in_std, out_scale, target_scale
+
+
+def fit_gate(cl, pairs):
+    """training-set mean roughness per field (floored at 1e-6 of the
+    largest, so a field that stays flat does not dominate the gate)"""
+    tot = np.zeros(8)
+    n = 0
+    for u, t in pairs:
+        tot += cl.stats(u, t)[4]
+        n += u[0].numel()
+    R = tot / n
+    return np.maximum(R, 1e-6 * max(R.max(), 1e-30))
 
 
 def init_params(seed=0):
@@ -374,11 +386,12 @@ def evaluate(cl, nf, r, seed, nsteps, torch, stream, cfl=0.7, log=print, checkpo
     return res
 
 
-def save(path, cl, scales, meta=None):
-    """trained closure -> .npz (parameters, the four scale vectors, metadata
-    as a JSON string)"""
+def save(path, cl, scales, meta=None, gate=None):
+    """trained closure -> .npz (parameters, the four scale vectors, the mean
+    roughness of the gate (empty: no gate), metadata as a JSON string)"""
     np.savez(path, params=cl.params(), in_mean=np.asarray(scales[0]), in_std=np.asarray(scales[1]),
              out_scale=np.asarray(scales[2]), target_scale=np.asarray(scales[3]),
+             gate=np.asarray(gate if gate is not None else [], dtype=np.float64),
              meta=np.array(json.dumps(meta or {})))
 
 
@@ -389,25 +402,33 @@ def load(path, n, stream=None):
     cl.set_params(z["params"])
     scales = (z["in_mean"], z["in_std"], z["out_scale"], z["target_scale"])
     cl.set_scales(*scales)
+    if "gate" in z.files and z["gate"].size == 8:
+        cl.set_gate(z["gate"])
     return cl, scales, json.loads(str(z["meta"]))
 
 
 def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, steps_per_traj=24,
                   val_steps=None, epochs=10, lr=1e-3, cfl=0.7, scale_mode="family", log=print,
-                  weighting="global"):
-    """data generation and training; returns (closure, scales, info)"""
+                  weighting="global", gate=False, short_seeds=(), short_steps=0):
+    """data generation and training; returns (closure, scales, info).
+    short_seeds / short_steps: further trajectories of short_steps pairs
+    each, which weight the early, smooth part of the flow more."""
     import torch
     stream = torch.cuda.current_stream()
     nc = nf // r
     cl = mhd.Closure((nc,) * 3, stream=stream)
     t0 = time.perf_counter()
     pairs = generate_pairs(cl, nf, r, train_seeds, steps_per_traj, stream, cfl, log)
+    if short_seeds and short_steps:
+        pairs += generate_pairs(cl, nf, r, short_seeds, short_steps, stream, cfl, log)
     val = generate_pairs(cl, nf, r, (val_seed,), val_steps or steps_per_traj, stream, cfl, log)
     _sync(torch)
     t_data = time.perf_counter() - t0
     scales = fit_scales(cl, pairs, scale_mode)
+    R = fit_gate(cl, pairs) if gate else None
     cl.set_params(init_params(0))
     cl.set_scales(*scales)
+    cl.set_gate(R)
     val_loss0 = float(np.mean([cl.grad(u, t)[0] for u, t in val]))
     t0 = time.perf_counter()
     hist = train(cl, pairs, val, epochs, lr, log, scales=scales, weighting=weighting)
@@ -416,20 +437,23 @@ def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, st
     fe = field_errors(cl, val)
     log("[closure] validation one-step residual ratio per field: " + " ".join(f"{v:.3f}" for v in fe))
     info = {"nf": nf, "ratio": r, "train_seeds": list(train_seeds), "steps_per_traj": steps_per_traj,
+            "short_seeds": list(short_seeds), "short_steps": short_steps,
             "pairs": len(pairs), "data_s": t_data, "train_s": t_train, "epochs": epochs, "lr": lr,
             "train_steps": epochs * len(pairs), "val_loss_untrained": val_loss0, "history": hist,
-            "val_field_residual": fe.tolist(), "scale_mode": scale_mode, "weighting": weighting}
+            "val_field_residual": fe.tolist(), "scale_mode": scale_mode, "weighting": weighting,
+            "gate": None if R is None else R.tolist()}
     del pairs, val
     return cl, scales, info
 
 
 def run(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, test_seed=200, steps_per_traj=24,
-        epochs=10, lr=1e-3, eval_steps=24, cfl=0.7, scale_mode="family", log=print, weighting="global"):
+        epochs=10, lr=1e-3, eval_steps=24, cfl=0.7, scale_mode="family", log=print, weighting="global",
+        gate=False):
     """train then evaluate; returns (result dict, closure)"""
     import torch
     stream = torch.cuda.current_stream()
     cl, scales, info = train_closure(nf, r, train_seeds, val_seed, steps_per_traj, None, epochs, lr, cfl,
-                                     scale_mode, log, weighting)
+                                     scale_mode, log, weighting, gate)
     res = evaluate(cl, nf, r, test_seed, eval_steps, torch, stream, cfl, log)
     res.update(info)
     res["scales"] = [np.asarray(v).tolist() for v in scales]
@@ -449,6 +473,9 @@ if __name__ == "__main__":
     t.add_argument("--epochs", type=int, default=10)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--weighting", default="global", choices=("global", "pair", "sqrt"))
+    t.add_argument("--gate", action="store_true", help="roughness gate on the correction")
+    t.add_argument("--short-seeds", type=int, default=0, help="extra short trajectories")
+    t.add_argument("--short-steps", type=int, default=0)
     t.add_argument("--out", required=True, help=".npz file for the trained closure")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
@@ -463,8 +490,10 @@ if __name__ == "__main__":
         cl, scales, info = train_closure(args.nf, args.ratio, tuple(range(1, args.seeds + 1)),
                                          steps_per_traj=args.steps, val_steps=args.val_steps,
                                          epochs=args.epochs, lr=args.lr, log=say,
-                                         weighting=args.weighting)
-        save(args.out, cl, scales, info)
+                                         weighting=args.weighting, gate=args.gate,
+                                         short_seeds=tuple(range(args.seeds + 1, args.seeds + 1 + args.short_seeds)),
+                                         short_steps=args.short_steps)
+        save(args.out, cl, scales, info, info["gate"])
         print(json.dumps(info))
     else:
         z = np.load(args.weights, allow_pickle=False)

@@ -42,7 +42,8 @@ hipError_t launch_pack_weights(const float* w, int cin, int cout, int flip, uint
 hipError_t launch_conv3d(const ConvArgs& A, int cin, int cout, int epi, hipStream_t s);
 int wgrad_blocks(const int n[3], int& rows_per_wg);
 hipError_t launch_conv3d_wgrad(const WgradArgs& A, int cin, int cout, float* dw, hipStream_t s);
-hipError_t launch_bias_grad(const uint16_t* dyT, size_t N, int cout, float* dbias, hipStream_t s);
+constexpr int BG_BLOCKS = 64;      // partial sums per channel of the bias gradient (needs BG_BLOCKS * cout doubles)
+hipError_t launch_bias_grad(const uint16_t* dyT, size_t N, int cout, float* dbias, double* partial, hipStream_t s);
 hipError_t launch_to_bf16(const float* src, size_t N, int c, uint16_t* dst, uint16_t* dstT, hipStream_t s);
 
 // per-channel input normalisation, output and target scales of the closure
@@ -67,7 +68,12 @@ hipError_t launch_apply_level(float* u, const float* delta, size_t n, const int*
 hipError_t launch_zero_int(int* p, hipStream_t s);
 constexpr int STATS_BLOCKS = 256;
 hipError_t launch_residual(const float* ref, const float* plain, size_t n, float* out, hipStream_t s);
-hipError_t launch_stats(const float* u, const float* t, size_t N, double* partial, double* out, hipStream_t s);
+hipError_t launch_stats(const float* u, const float* t, const int n[3], double* partial, double* out, hipStream_t s);
+struct GateScales {
+    float inv_r[8];     // 1 / (training-set mean roughness) per field
+};
+hipError_t launch_gate(const float* u, const int n[3], const GateScales& gs, float* g0, float* g, hipStream_t s);
+hipError_t launch_row_scale(float* a, const float* g, size_t N, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
 

@@ -11,8 +11,8 @@
 //  * B: activations, channel-last x[cell][CIN]: the 8 K values of a lane are
 //    8 consecutive channels of one shifted cell (one 16-byte load);
 //  * D: 4 consecutive output channels of one cell per lane.
-// Each wave computes 64 consecutive cells (4 blocks of 16) x all output
-// channels.  dgrad is the same kernel on the gradient with the weights
+// A workgroup computes a 16 x 4 x 4 tile of cells x all output channels from
+// an LDS copy of its input halo; each wave one z plane (4 rows of 16 cells).  dgrad is the same kernel on the gradient with the weights
 // flipped (o -> 26 - o) and transposed (ci <-> co), with the ReLU mask of
 // the forward activation fused in the epilogue.
 //
@@ -83,35 +83,57 @@ hipError_t launch_pack_weights(const float* w, int cin, int cout, int flip, uint
 // forward / dgrad convolution
 // ---------------------------------------------------------------------------
 
+// Output tile of a workgroup: 16 (x) x 4 (y) x 4 (z) cells; wave w takes
+// the z plane w, its 4 MFMA column blocks the 4 rows y, lane r the cell x.
+// The input halo (18 x 6 x 6 cells, periodic) is staged once in LDS with a
+// cell stride of CIN + 8 bf16 for CIN = 32 (80 bytes: the 16-byte reads of
+// 16 consecutive cells then spread over all banks), and every one of the 27
+// offsets reads its B fragments from there.
+constexpr int CT_X = 16, CT_Y = 4, CT_Z = 4;
+constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2, CH_CELLS = CH_X * CH_Y * CH_Z;
+
+template <int CIN>
+__host__ __device__ constexpr int conv_cell_stride() { return CIN == 8 ? 8 : CIN + 8; }
+
 template <int CIN, int COUT, int EPI>
 __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
 {
     constexpr int KS = (27 * CIN + 31) / 32;
     constexpr int MB = (COUT + 15) / 16;
-    constexpr int NB = 4;
+    constexpr int NB = CT_Y;
+    constexpr int CS = conv_cell_stride<CIN>();
+    constexpr int PARTS = CIN / 8;                         // 16-byte pieces per cell
+    __shared__ __align__(16) uint16_t tile[CH_CELLS * CS];
+
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int nx = A.n[0], ny = A.n[1], nz = A.n[2];
     const long N = (long)nx * ny * nz;
-    const long cell0 = ((long)blockIdx.x * 4 + wave) * 64;
-    if (cell0 >= N) return;
+    const int tx = nx / CT_X, ty = ny / CT_Y;
+    const int b = blockIdx.x;
+    const int x0 = (b % tx) * CT_X, y0 = ((b / tx) % ty) * CT_Y, z0 = (b / (tx * ty)) * CT_Z;
     const uint16_t* __restrict__ x = A.x;
     const uint4* __restrict__ wp = reinterpret_cast<const uint4*>(A.wp);
 
-    int ci_[NB], cj_[NB], ck_[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const long c = cell0 + 16 * nb + r;
-        ci_[nb] = (int)(c % nx);
-        cj_[nb] = (int)((c / nx) % ny);
-        ck_[nb] = (int)(c / ((long)nx * ny));
+    // stage the halo: piece q of halo cell h, consecutive threads on
+    // consecutive pieces (contiguous along x in global memory)
+    for (int t = threadIdx.x; t < CH_CELLS * PARTS; t += 256) {
+        const int h = t / PARTS, q = t % PARTS;
+        const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
+        const unsigned src = (unsigned)wrap1(x0 - 1 + hx, nx) +
+                             (unsigned)nx * ((unsigned)wrap1(y0 - 1 + hy, ny) +
+                                             (unsigned)ny * (unsigned)wrap1(z0 - 1 + hz, nz));
+        *reinterpret_cast<uint4*>(tile + h * CS + 8 * q) = ld16(x + (size_t)src * CIN + 8 * q);
     }
+    __syncthreads();
+
     f4 acc[MB][NB];
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f4{ 0.f, 0.f, 0.f, 0.f };
 
+#pragma unroll 3
     for (int s = 0; s < KS; ++s) {
         const int K = 32 * s + 8 * g;
         const int o = K / CIN, c0 = K % CIN;
@@ -121,10 +143,8 @@ __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
         for (int nb = 0; nb < NB; ++nb) {
             uint4 v = make_uint4(0, 0, 0, 0);
             if (o < 27) {
-                const unsigned src = (unsigned)wrap1(ci_[nb] + dx, nx) +
-                                     (unsigned)nx * ((unsigned)wrap1(cj_[nb] + dy, ny) +
-                                                     (unsigned)ny * (unsigned)wrap1(ck_[nb] + dz, nz));
-                v = ld16(x + (size_t)src * CIN + c0);
+                const int h = (wave + 1 + dz) * (CH_X * CH_Y) + (nb + 1 + dy) * CH_X + (r + 1 + dx);
+                v = *reinterpret_cast<const uint4*>(tile + h * CS + c0);
             }
             bf[nb] = as_bf8(v);
         }
@@ -137,14 +157,14 @@ __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
         }
     }
 
-    // epilogue: lane holds channels co = 16 m + 4 g + e of cell cell0 + 16 nb + r
+    // epilogue: lane holds channels co = 16 m + 4 g + e of cell (x0 + r, y0 + nb, z0 + wave)
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
         const int co0 = 16 * m + 4 * g;
         if (co0 >= COUT) continue;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const long c = cell0 + 16 * nb + r;
+            const long c = (long)(x0 + r) + (long)nx * ((long)(y0 + nb) + (long)ny * (z0 + wave));
             float v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -163,14 +183,14 @@ __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
             if (EPI == EPI_BIAS_F32 || EPI == EPI_F32) {
                 *reinterpret_cast<float4*>(A.yf + (size_t)c * COUT + co0) = make_float4(v[0], v[1], v[2], v[3]);
             } else {
-                uint16_t b[4];
+                uint16_t bb[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) b[e] = f2bf(v[e]);
+                for (int e = 0; e < 4; ++e) bb[e] = f2bf(v[e]);
                 *reinterpret_cast<uint2*>(A.yb + (size_t)c * COUT + co0) =
-                    make_uint2((uint32_t)b[0] | ((uint32_t)b[1] << 16), (uint32_t)b[2] | ((uint32_t)b[3] << 16));
+                    make_uint2((uint32_t)bb[0] | ((uint32_t)bb[1] << 16), (uint32_t)bb[2] | ((uint32_t)bb[3] << 16));
                 if (A.ybT)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) A.ybT[(size_t)(co0 + e) * N + c] = b[e];
+                    for (int e = 0; e < 4; ++e) A.ybT[(size_t)(co0 + e) * N + c] = bb[e];
             }
         }
     }
@@ -179,8 +199,7 @@ __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
 template <int CIN, int COUT>
 static hipError_t conv_dispatch_epi(const ConvArgs& A, int epi, hipStream_t s)
 {
-    const long N = (long)A.n[0] * A.n[1] * A.n[2];
-    const unsigned grid = (unsigned)((N + 255) / 256);
+    const unsigned grid = (unsigned)((A.n[0] / CT_X) * (A.n[1] / CT_Y) * (A.n[2] / CT_Z));
     switch (epi) {
     case EPI_BIAS_RELU: hipLaunchKernelGGL((conv3d_kernel<CIN, COUT, EPI_BIAS_RELU>), dim3(grid), dim3(256), 0, s, A); break;
     case EPI_BIAS_F32: hipLaunchKernelGGL((conv3d_kernel<CIN, COUT, EPI_BIAS_F32>), dim3(grid), dim3(256), 0, s, A); break;
@@ -301,12 +320,24 @@ __global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int nwg, 
     dw[i] = acc;
 }
 
-// dbias[co] = sum_cell dyT[co][cell]; one workgroup per channel, fixed tree
-__global__ void __launch_bounds__(256) bias_grad_kernel(const uint16_t* __restrict__ dyT, size_t N, float* dbias)
+// dbias[co] = sum_cell dyT[co][cell]: BG_BLOCKS workgroups per channel
+// (blockIdx.y = channel) write FP64 partials, a final pass adds them in
+// block order (deterministic)
+__global__ void __launch_bounds__(256) bias_grad_partial_kernel(const uint16_t* __restrict__ dyT, size_t N,
+                                                                double* __restrict__ partial)
 {
-    const int co = blockIdx.x;
+    const int co = blockIdx.y;
+    const uint16_t* row = dyT + (size_t)co * N;
     double acc = 0.0;
-    for (size_t c = threadIdx.x; c < N; c += 256) acc += (double)bf2f(dyT[(size_t)co * N + c]);
+    // 8 values per thread per iteration (one 16-byte load; N is a multiple of 8)
+    for (size_t c = ((size_t)blockIdx.x * 256 + threadIdx.x) * 8; c < N; c += (size_t)gridDim.x * 256 * 8) {
+        const uint4 v = ld16(row + c);
+        const uint32_t w[4] = { v.x, v.y, v.z, v.w };
+        float part = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part += bf2f((uint16_t)(w[q] & 0xffff)) + bf2f((uint16_t)(w[q] >> 16));
+        acc += (double)part;
+    }
     __shared__ double sh[256];
     sh[threadIdx.x] = acc;
     __syncthreads();
@@ -314,7 +345,16 @@ __global__ void __launch_bounds__(256) bias_grad_kernel(const uint16_t* __restri
         if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) dbias[co] = (float)sh[0];
+    if (threadIdx.x == 0) partial[(size_t)co * gridDim.x + blockIdx.x] = sh[0];
+}
+
+__global__ void bias_grad_final_kernel(const double* __restrict__ partial, int nblk, int cout, float* dbias)
+{
+    const int co = threadIdx.x;
+    if (co >= cout) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblk; ++b) acc += partial[(size_t)co * nblk + b];
+    dbias[co] = (float)acc;
 }
 
 int wgrad_blocks(const int n[3], int& rows_per_wg)
@@ -342,9 +382,10 @@ hipError_t launch_conv3d_wgrad(const WgradArgs& A, int cin, int cout, float* dw,
     return hipGetLastError();
 }
 
-hipError_t launch_bias_grad(const uint16_t* dyT, size_t N, int cout, float* dbias, hipStream_t s)
+hipError_t launch_bias_grad(const uint16_t* dyT, size_t N, int cout, float* dbias, double* partial, hipStream_t s)
 {
-    hipLaunchKernelGGL(bias_grad_kernel, dim3(cout), dim3(256), 0, s, dyT, N, dbias);
+    hipLaunchKernelGGL(bias_grad_partial_kernel, dim3(BG_BLOCKS, cout), dim3(256), 0, s, dyT, N, partial);
+    hipLaunchKernelGGL(bias_grad_final_kernel, dim3(1), dim3(64), 0, s, partial, BG_BLOCKS, cout, dbias);
     return hipGetLastError();
 }
 
@@ -641,48 +682,130 @@ hipError_t launch_residual(const float* ref, const float* plain, size_t n, float
 }
 
 // Per-field sums of a field-major pair (u, t), blockIdx.y = field:
-// partial[(b * 8 + f) * 4 + {0,1,2,3}] = sum u, sum u^2, sum |u|, sum |t|
+// partial[(b * 8 + f) * 5 + q], q = sum u, sum u^2, sum |u|, sum |t|, and
+// sum of the roughness r = sum over axes |u(c+a) - 2 u(c) + u(c-a)|
 __global__ void __launch_bounds__(256) stats_partial_kernel(const float* __restrict__ u,
-                                                            const float* __restrict__ t, size_t N,
+                                                            const float* __restrict__ t, int nx, int ny, int nz,
                                                             double* __restrict__ partial)
 {
+    const size_t N = (size_t)nx * ny * nz;
     const int f = blockIdx.y;
     const float* uf = u + (size_t)f * N;
     const float* tf = t + (size_t)f * N;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double a[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 };
     for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < N; c += (size_t)gridDim.x * 256) {
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
         const double x = uf[c];
-        a0 += x;
-        a1 += x * x;
-        a2 += fabs(x);
-        a3 += fabs((double)tf[c]);
+        a[0] += x;
+        a[1] += x * x;
+        a[2] += fabs(x);
+        a[3] += fabs((double)tf[c]);
+        const size_t row = (size_t)nx * (j + (size_t)ny * k);
+        const double xp = uf[row + wrap1(i + 1, nx)], xm = uf[row + wrap1(i - 1, nx)];
+        const double yp = uf[(size_t)i + (size_t)nx * (wrap1(j + 1, ny) + (size_t)ny * k)];
+        const double ym = uf[(size_t)i + (size_t)nx * (wrap1(j - 1, ny) + (size_t)ny * k)];
+        const double zp = uf[(size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k + 1, nz))];
+        const double zm = uf[(size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k - 1, nz))];
+        a[4] += fabs(xp - 2.0 * x + xm) + fabs(yp - 2.0 * x + ym) + fabs(zp - 2.0 * x + zm);
     }
-    __shared__ double sh[4][256];
-    sh[0][threadIdx.x] = a0; sh[1][threadIdx.x] = a1; sh[2][threadIdx.x] = a2; sh[3][threadIdx.x] = a3;
+    __shared__ double sh[5][256];
+    for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] = a[q];
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
         if (threadIdx.x < st)
-            for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
+            for (int q = 0; q < 5; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x < 4) partial[((size_t)blockIdx.x * 8 + f) * 4 + threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x < 5) partial[((size_t)blockIdx.x * 8 + f) * 5 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// out[q * 8 + f] = sum over blocks of partial[(b * 8 + f) * 4 + q]
+// out[q * 8 + f] = sum over blocks of partial[(b * 8 + f) * 5 + q]
 __global__ void stats_final_kernel(const double* __restrict__ partial, int nblk, double* __restrict__ out)
 {
     const int k = threadIdx.x;
-    if (k >= 32) return;
+    if (k >= 40) return;
     const int q = k / 8, f = k % 8;
     double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += partial[((size_t)b * 8 + f) * 4 + q];
+    for (int b = 0; b < nblk; ++b) acc += partial[((size_t)b * 8 + f) * 5 + q];
     out[k] = acc;
 }
 
-hipError_t launch_stats(const float* u, const float* t, size_t N, double* partial, double* out, hipStream_t s)
+hipError_t launch_stats(const float* u, const float* t, const int n[3], double* partial, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(stats_partial_kernel, dim3(STATS_BLOCKS, 8), dim3(256), 0, s, u, t, N, partial);
+    hipLaunchKernelGGL(stats_partial_kernel, dim3(STATS_BLOCKS, 8), dim3(256), 0, s, u, t, n[0], n[1], n[2], partial);
     hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(64), 0, s, partial, STATS_BLOCKS, out);
+    return hipGetLastError();
+}
+
+// Roughness gate: g0(c) = (1/8) sum_f inv_R[f] * sum over axes
+// |u_f(c+a) - 2 u_f(c) + u_f(c-a)| (u field-major FP32)
+__global__ void __launch_bounds__(256) gate_rough_kernel(const float* __restrict__ u, int nx, int ny, int nz,
+                                                         GateScales gs, float* __restrict__ g0)
+{
+    const size_t N = (size_t)nx * ny * nz;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        const size_t row = (size_t)nx * (j + (size_t)ny * k);
+        const size_t nb[6] = { row + wrap1(i + 1, nx), row + wrap1(i - 1, nx),
+                               (size_t)i + (size_t)nx * (wrap1(j + 1, ny) + (size_t)ny * k),
+                               (size_t)i + (size_t)nx * (wrap1(j - 1, ny) + (size_t)ny * k),
+                               (size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k + 1, nz)),
+                               (size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k - 1, nz)) };
+        float acc = 0.0f;
+        for (int f = 0; f < 8; ++f) {
+            const float* uf = u + (size_t)f * N;
+            const float x2 = 2.0f * uf[c];
+            float r = 0.0f;
+            for (int a = 0; a < 3; ++a) r += fabsf((uf[nb[2 * a]] - x2) + uf[nb[2 * a + 1]]);
+            acc += r * gs.inv_r[f];
+        }
+        g0[c] = 0.125f * acc;
+    }
+}
+
+// g(c) = max of g0 over c and its six face neighbours
+__global__ void __launch_bounds__(256) gate_max_kernel(const float* __restrict__ g0, int nx, int ny, int nz,
+                                                       float* __restrict__ g)
+{
+    const size_t N = (size_t)nx * ny * nz;
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        const size_t row = (size_t)nx * (j + (size_t)ny * k);
+        float m = g0[c];
+        m = fmaxf(m, g0[row + wrap1(i + 1, nx)]);
+        m = fmaxf(m, g0[row + wrap1(i - 1, nx)]);
+        m = fmaxf(m, g0[(size_t)i + (size_t)nx * (wrap1(j + 1, ny) + (size_t)ny * k)]);
+        m = fmaxf(m, g0[(size_t)i + (size_t)nx * (wrap1(j - 1, ny) + (size_t)ny * k)]);
+        m = fmaxf(m, g0[(size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k + 1, nz))]);
+        m = fmaxf(m, g0[(size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k - 1, nz))]);
+        g[c] = m;
+    }
+}
+
+hipError_t launch_gate(const float* u, const int n[3], const GateScales& gs, float* g0, float* g, hipStream_t s)
+{
+    hipLaunchKernelGGL(gate_rough_kernel, dim3(2048), dim3(256), 0, s, u, n[0], n[1], n[2], gs, g0);
+    hipLaunchKernelGGL(gate_max_kernel, dim3(2048), dim3(256), 0, s, g0, n[0], n[1], n[2], g);
+    return hipGetLastError();
+}
+
+// a[c][f] *= g[c], channel-last rows of 8
+__global__ void row_scale_kernel(float* __restrict__ a, const float* __restrict__ g, size_t N)
+{
+    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const float s = g[c];
+        float4* p = reinterpret_cast<float4*>(a + c * 8);
+        float4 v0 = p[0], v1 = p[1];
+        v0.x *= s; v0.y *= s; v0.z *= s; v0.w *= s;
+        v1.x *= s; v1.y *= s; v1.z *= s; v1.w *= s;
+        p[0] = v0;
+        p[1] = v1;
+    }
+}
+
+hipError_t launch_row_scale(float* a, const float* g, size_t N, hipStream_t s)
+{
+    hipLaunchKernelGGL(row_scale_kernel, dim3(2048), dim3(256), 0, s, a, g, N);
     return hipGetLastError();
 }
 

@@ -48,6 +48,9 @@ struct mhd_closure {
     float *o, *delta, *g, *go;
     float* wpart;          // wgrad partials
     double *chpart, *chout, *loss, *stpart, *stout;
+    bool gate_on;           // roughness gate of the output (mhd_closure_set_gate)
+    GateScales gs;
+    float *gate0, *gate;
     int *bad, *fallbacks;
     int rows_per_wg, nwg;
 };
@@ -66,7 +69,8 @@ extern "C" void mhd_closure_destroy(mhd_closure* c)
     void* ptrs[] = { c->params, c->grads, c->adam_m, c->adam_v, c->wp[0], c->wp[1], c->wp[2], c->wpT[0],
                      c->wpT[1], c->wpT[2], c->x0, c->x0T, c->a1, c->a1T, c->a2, c->a2T, c->gob, c->gobT,
                      c->g2, c->g2T, c->g1, c->g1T, c->o, c->delta, c->g, c->go, c->wpart,
-                     c->chpart, c->chout, c->loss, c->stpart, c->stout, c->bad, c->fallbacks };
+                     c->chpart, c->chout, c->loss, c->stpart, c->stout, c->bad, c->fallbacks,
+                     c->gate0, c->gate };
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete c;
@@ -109,7 +113,8 @@ extern "C" mhd_closure* mhd_closure_create(int nx, int ny, int nz, void* hip_str
     A((void**)&c->wpart, (size_t)c->nwg * 27 * 32 * 32 * 4);
     A((void**)&c->chpart, (size_t)CHSUM_BLOCKS * 8 * 8); A((void**)&c->chout, 16 * 8);
     A((void**)&c->loss, 8); A((void**)&c->bad, 4); A((void**)&c->fallbacks, 8);
-    A((void**)&c->stpart, (size_t)STATS_BLOCKS * 8 * 4 * 8); A((void**)&c->stout, 32 * 8);
+    A((void**)&c->stpart, (size_t)STATS_BLOCKS * 8 * 5 * 8); A((void**)&c->stout, 40 * 8);
+    A((void**)&c->gate0, N * 4); A((void**)&c->gate, N * 4);
     if (!ok) {
         (void)hipGetLastError();
         mhd_fail(MHD_ENOMEM, "closure allocation failed");
@@ -166,6 +171,32 @@ extern "C" int mhd_closure_set_scales(mhd_closure* c, const float* in_mean, cons
     return MHD_OK;
 }
 
+extern "C" int mhd_closure_set_gate(mhd_closure* c, const float* mean_roughness)
+{
+    int r = check_cl(c);
+    if (r) return r;
+    if (!mean_roughness) {
+        c->gate_on = false;
+        return MHD_OK;
+    }
+    for (int f = 0; f < 8; ++f)
+        if (!(mean_roughness[f] > 0.0f) || !isfinite(mean_roughness[f]))
+            return mhd_fail(MHD_EINVAL, "mean roughness must be positive and finite");
+    for (int f = 0; f < 8; ++f) c->gs.inv_r[f] = 1.0f / mean_roughness[f];
+    c->gate_on = true;
+    return MHD_OK;
+}
+
+extern "C" int mhd_closure_get_gate(mhd_closure* c, float* gate_dev)
+{
+    int r = check_cl(c);
+    if (r) return r;
+    if (!gate_dev) return mhd_fail(MHD_EINVAL, "null device pointer");
+    if (!c->gate_on) return mhd_fail(MHD_ESTATE, "no gate set");
+    HIP_TRY(c, hipMemcpyAsync(gate_dev, c->gate, c->N * 4, hipMemcpyDeviceToDevice, c->stream));
+    return MHD_OK;
+}
+
 static int pack_all(mhd_closure* c)
 {
     if (c->packed) return MHD_OK;
@@ -193,6 +224,10 @@ static int forward(mhd_closure* c, const float* u)
     HIP_TRY(c, launch_conv3d(A, 32, 32, EPI_BIAS_RELU, c->stream));
     A.x = c->a2; A.wp = c->wp[2]; A.bias = c->params + boff(2); A.yb = nullptr; A.ybT = nullptr; A.yf = c->o;
     HIP_TRY(c, launch_conv3d(A, 32, 8, EPI_BIAS_F32, c->stream));
+    if (c->gate_on) {
+        HIP_TRY(c, launch_gate(u, c->n, c->gs, c->gate0, c->gate, c->stream));
+        HIP_TRY(c, launch_row_scale(c->o, c->gate, c->N, c->stream));
+    }
     // projection: means of the 5 fluid outputs over the box
     HIP_TRY(c, launch_chsum(c->o, c->N, 8, 1, 5, 1.0 / (double)c->N, c->chpart, c->chout, c->stream));
     HIP_TRY(c, launch_project(c->o, c->chout, c->n, c->sc, c->delta, c->stream));
@@ -206,6 +241,7 @@ static int backward(mhd_closure* c, const float* target)
     HIP_TRY(c, launch_loss(c->delta, target, N, c->sc, c->g, c->chpart, c->loss, c->stream));
     HIP_TRY(c, launch_chsum(c->g, N, 1, N, 5, 1.0 / (double)N, c->chpart, c->chout + 8, c->stream));
     HIP_TRY(c, launch_project_T(c->g, c->chout + 8, c->n, c->sc, c->go, c->stream));
+    if (c->gate_on) HIP_TRY(c, launch_row_scale(c->go, c->gate, N, c->stream));
     HIP_TRY(c, launch_to_bf16(c->go, N, 8, c->gob, c->gobT, c->stream));
     WgradArgs W;
     W.n[0] = c->n[0]; W.n[1] = c->n[1]; W.n[2] = c->n[2];
@@ -214,7 +250,7 @@ static int backward(mhd_closure* c, const float* target)
     // layer 3
     W.xT = c->a2T; W.dyT = c->gobT;
     HIP_TRY(c, launch_conv3d_wgrad(W, 32, 8, c->grads + woff(2), c->stream));
-    HIP_TRY(c, launch_bias_grad(c->gobT, N, 8, c->grads + boff(2), c->stream));
+    HIP_TRY(c, launch_bias_grad(c->gobT, N, 8, c->grads + boff(2), c->chpart, c->stream));
     ConvArgs A;
     memset(&A, 0, sizeof A);
     A.n[0] = c->n[0]; A.n[1] = c->n[1]; A.n[2] = c->n[2];
@@ -223,13 +259,13 @@ static int backward(mhd_closure* c, const float* target)
     // layer 2
     W.xT = c->a1T; W.dyT = c->g2T;
     HIP_TRY(c, launch_conv3d_wgrad(W, 32, 32, c->grads + woff(1), c->stream));
-    HIP_TRY(c, launch_bias_grad(c->g2T, N, 32, c->grads + boff(1), c->stream));
+    HIP_TRY(c, launch_bias_grad(c->g2T, N, 32, c->grads + boff(1), c->chpart, c->stream));
     A.x = c->g2; A.wp = c->wpT[1]; A.mask = c->a1; A.yb = c->g1; A.ybT = c->g1T;
     HIP_TRY(c, launch_conv3d(A, 32, 32, EPI_MASK, c->stream));
     // layer 1
     W.xT = c->x0T; W.dyT = c->g1T;
     HIP_TRY(c, launch_conv3d_wgrad(W, 8, 32, c->grads + woff(0), c->stream));
-    HIP_TRY(c, launch_bias_grad(c->g1T, N, 32, c->grads + boff(0), c->stream));
+    HIP_TRY(c, launch_bias_grad(c->g1T, N, 32, c->grads + boff(0), c->chpart, c->stream));
     return MHD_OK;
 }
 
@@ -316,8 +352,8 @@ extern "C" int mhd_closure_stats(mhd_closure* c, const float* u_dev, const float
     int r = check_cl(c);
     if (r) return r;
     if (!u_dev || !target_dev || !out) return mhd_fail(MHD_EINVAL, "null pointer");
-    HIP_TRY(c, launch_stats(u_dev, target_dev, c->N, c->stpart, c->stout, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(out, c->stout, 32 * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, launch_stats(u_dev, target_dev, c->n, c->stpart, c->stout, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(out, c->stout, 40 * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MHD_OK;
 }
@@ -429,7 +465,8 @@ extern "C" int mhd_conv3d_wgrad(const int* n, int cin, int cout, const void* xT,
     HIP_TRY(&h, hipMalloc(&db, cout * 4));
     W.partial = part;
     HIP_TRY(&h, launch_conv3d_wgrad(W, cin, cout, dw, s));
-    HIP_TRY(&h, launch_bias_grad((const uint16_t*)dyT, (size_t)n[0] * n[1] * n[2], cout, db, s));
+    // the wgrad partials are consumed by then (same stream): reuse them
+    HIP_TRY(&h, launch_bias_grad((const uint16_t*)dyT, (size_t)n[0] * n[1] * n[2], cout, db, (double*)part, s));
     HIP_TRY(&h, hipMemcpyAsync(dw_host, dw, nw * 4, hipMemcpyDeviceToHost, s));
     if (dbias_host) HIP_TRY(&h, hipMemcpyAsync(dbias_host, db, cout * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(&h, hipStreamSynchronize(s));

@@ -95,6 +95,8 @@ def load():
         "mhd_closure_reduced": (i, [vp, ip]),
         "mhd_closure_residual": (i, [vp, vp, vp, vp]),
         "mhd_closure_stats": (i, [vp, vp, vp, dp]),
+        "mhd_closure_set_gate": (i, [vp, fp]),
+        "mhd_closure_get_gate": (i, [vp, vp]),
         "mhd_conv3d_forward": (i, [ip, i, i, vp, fp, fp, vp, vp]),
         "mhd_conv3d_dgrad": (i, [ip, i, i, vp, fp, vp, vp]),
         "mhd_conv3d_wgrad": (i, [ip, i, i, vp, vp, fp, fp, vp]),
@@ -122,6 +124,7 @@ def exported_symbols():
                         "mhd_closure_get_params", "mhd_closure_set_scales", "mhd_closure_forward",
                         "mhd_closure_grad", "mhd_closure_train_step", "mhd_closure_step",
                         "mhd_closure_fallbacks", "mhd_closure_reduced", "mhd_closure_residual", "mhd_closure_stats",
+                        "mhd_closure_set_gate", "mhd_closure_get_gate",
                         "mhd_conv3d_forward", "mhd_conv3d_dgrad",
                         "mhd_conv3d_wgrad", "mhd_last_error")]
 
@@ -511,10 +514,27 @@ class Closure:
         return out
 
     def stats(self, u, target):
-        """FP64 per-field sums: rows sum u, sum u^2, sum |u|, sum |target|"""
-        out = (ctypes.c_double * 32)()
+        """FP64 per-field sums: rows sum u, sum u^2, sum |u|, sum |target|,
+        sum of the roughness of u"""
+        out = (ctypes.c_double * 40)()
         check(self.lib.mhd_closure_stats(self.h, _dptr(u), _dptr(target), out))
-        return np.array(out[:]).reshape(4, 8)
+        return np.array(out[:]).reshape(5, 8)
+
+    def set_gate(self, mean_roughness):
+        """roughness gate with the training-set mean roughness per field
+        (None: no gate)"""
+        if mean_roughness is None:
+            check(self.lib.mhd_closure_set_gate(self.h, None))
+            return
+        r = np.ascontiguousarray(mean_roughness, dtype=np.float32)
+        check(self.lib.mhd_closure_set_gate(self.h, _fptr(r)))
+
+    def gate(self):
+        """gate of the last forward pass (torch CUDA tensor of nx*ny*nz)"""
+        import torch
+        out = torch.empty(self.n[0] * self.n[1] * self.n[2], dtype=torch.float32, device="cuda")
+        check(self.lib.mhd_closure_get_gate(self.h, _dptr(out)))
+        return out
 
 
 def conv3d_forward(n, x, w, bias, y, stream=None):

@@ -233,7 +233,7 @@ def test_training_set_residual_and_statistics(env):
     u64 = up.astype(np.float64).reshape(8, -1)
     t64 = tn.astype(np.float64).reshape(8, -1)
     ref = np.stack([u64.sum(1), (u64 * u64).sum(1), np.abs(u64).sum(1), np.abs(t64).sum(1)])
-    assert np.allclose(st, ref, rtol=1e-12, atol=0.0)
+    assert np.allclose(st[:4], ref, rtol=1e-12, atol=0.0)
 
 
 def _physical(u, gamma=5.0 / 3.0):
@@ -286,3 +286,64 @@ def test_closure_step_scales_a_correction_down_to_stay_physical(env):
     want = ub.cpu().numpy() + np.float32(0.5) * delta
     assert cl.reduced() == 1 and cl.fallbacks() == 0
     assert np.array_equal(got, want)
+
+
+def _roughness_means(u):
+    """per-field mean of r_f = sum over axes |second difference| (numpy, FP64)"""
+    U = u.reshape(8, N3[2], N3[1], N3[0])
+    r = sum(np.abs(np.roll(U, -1, ax) - 2 * U + np.roll(U, 1, ax)) for ax in (1, 2, 3))
+    return r.reshape(8, -1).mean(axis=1)
+
+
+def test_gate_parity_and_roughness_statistics(env):
+    """gate of the last forward against the oracle gate of the same FP32
+    state (FP32 vs FP64 arithmetic: 1e-5 of the largest gate); the roughness
+    row of the statistics kernel against numpy"""
+    torch, mhd = env
+    say("case: closure roughness gate")
+    prob = closure_problem(seed=6)
+    u = prob[0]
+    R = _roughness_means(u) * np.linspace(0.5, 1.5, 8)
+    cl = setup_closure(torch, mhd, prob)
+    cl.set_gate(R)
+    ud = torch.from_numpy(u.astype(np.float32)).cuda()
+    cl.forward(ud)
+    g = cl.gate().cpu().numpy().astype(np.float64)
+    gr = C.gate(u.reshape(8, -1), R.astype(np.float32).astype(np.float64), N3)
+    err = np.abs(g - gr).max() / gr.max()
+    say("gate max rel err", err, "range", gr.min(), gr.max())
+    assert err < 1e-5
+    st = cl.stats(ud, ud)
+    rsum = _roughness_means(u) * np.prod(N3)
+    assert np.allclose(st[4], rsum, rtol=1e-12, atol=0.0)
+
+
+def test_gated_network_forward_and_gradient_parity(env):
+    torch, mhd = env
+    say("case: gated closure network forward + gradient")
+    prob = closure_problem(seed=7)
+    u, mean, std, ps, out_scale, target, tscale = prob
+    R = _roughness_means(u)
+    cl = setup_closure(torch, mhd, prob)
+    cl.set_gate(R)
+    ud = torch.from_numpy(u.astype(np.float32)).cuda()
+    td = torch.from_numpy(target.astype(np.float32).reshape(u.shape)).cuda()
+    delta = cl.forward(ud).cpu().numpy().reshape(8, -1)
+    gt = C.gate(u.reshape(8, -1), R.astype(np.float32).astype(np.float64), N3)
+    x, psr, osc, tgt, ts = oracle_inputs(prob)
+    ref = C.forward(x, psr, osc, N3, g=gt)
+    e_fwd = np.linalg.norm(delta - ref) / np.linalg.norm(ref)
+    L, g = cl.grad(ud, td)
+    Lr, gr = C.loss_and_grad(x, psr, osc, tgt.astype(np.float64), ts, N3, g=gt)
+    gr = C.flatten(gr)
+    e_g = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    cos = float(np.dot(g, gr) / np.linalg.norm(g) / np.linalg.norm(gr))
+    say("forward rel L2", e_fwd, "loss", L, Lr, "grad rel L2", e_g, "cos", cos)
+    assert e_fwd < 3e-2
+    assert L == pytest.approx(Lr, rel=1e-3)
+    assert e_g < 3e-2 and cos > 0.999
+    # switching the gate off restores the ungated correction
+    cl.set_gate(None)
+    d0 = cl.forward(ud).cpu().numpy().reshape(8, -1)
+    ref0 = C.forward(x, psr, osc, N3)
+    assert np.linalg.norm(d0 - ref0) / np.linalg.norm(ref0) < 3e-2
