@@ -28,9 +28,10 @@ struct WgradArgs {
     int n[3];
     const uint16_t* xT;     // bf16 [cin][cell]
     const uint16_t* dyT;    // bf16 [cout][cell]
-    float* partial;         // [workgroups][27][cin][cout]
-    int rows_per_wg;
+    float* partial;         // [workgroups + 16][27][cin][cout] (partial sums, then the reduction's)
+    int tiles_per_wg;
 };
+constexpr int WGRAD_MAX_WG = 512;   // persistent workgroups of wgrad (bounds the partial sums)
 
 // packed size (bf16 elements) of a layer's weights
 inline size_t packed_weight_elems(int cin, int cout)
@@ -40,7 +41,7 @@ inline size_t packed_weight_elems(int cin, int cout)
 
 hipError_t launch_pack_weights(const float* w, int cin, int cout, int flip, uint16_t* wp, hipStream_t s);
 hipError_t launch_conv3d(const ConvArgs& A, int cin, int cout, int epi, hipStream_t s);
-int wgrad_blocks(const int n[3], int& rows_per_wg);
+int wgrad_blocks(const int n[3], int& tiles_per_wg);   // workgroups of a wgrad launch
 hipError_t launch_conv3d_wgrad(const WgradArgs& A, int cin, int cout, float* dw, hipStream_t s);
 constexpr int BG_BLOCKS = 64;      // partial sums per channel of the bias gradient (needs BG_BLOCKS * cout doubles)
 hipError_t launch_bias_grad(const uint16_t* dyT, size_t N, int cout, float* dbias, double* partial, hipStream_t s);

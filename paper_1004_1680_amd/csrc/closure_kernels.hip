@@ -19,13 +19,13 @@
 // wgrad, dW[o][ci][co] = sum_cell x[cell + d(o)][ci] dy[cell][co], has K =
 // cells: it reads channel-major copies xT[ci][cell], dyT[co][cell] written
 // by the producing kernels, so a lane's 8 K values are 8 consecutive cells
-// of one channel; the x shift of an offset is built from two aligned
-// 16-byte loads.  Each workgroup accumulates a slab of rows for all 27
-// offsets (wave w takes offsets w, w+4, ...) and writes partial sums; a
-// second kernel adds the partials in a fixed order (deterministic).
+// of one channel.  A workgroup stages a tile of x with its halo in LDS; each
+// of its 9 waves owns one (dy, dz) pair and builds the dx = -1, 0, +1
+// fragments from three aligned 16-byte reads.  Persistent workgroups write
+// partial sums, which two passes add in a fixed order (deterministic).
 //
-// Requirements: nx, ny, nz multiples of 32 (nx for the 32-cell K steps of
-// wgrad), fewer than 2^31 cells.
+// Requirements: nx, ny, nz multiples of 32 (the tiles: 16 x 4 x 4 cells for
+// forward / dgrad, 32 x 4 x 2 for wgrad), fewer than 2^31 cells.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -50,6 +50,16 @@ __device__ __forceinline__ bf16x8 as_bf8(uint4 v) { return __builtin_bit_cast(bf
 __device__ __forceinline__ uint4 ld16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
 
 __device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// (i, j, k) of cell c = i + nx (j + ny k), 32-bit arithmetic (fewer than 2^31 cells)
+__device__ __forceinline__ void cell_ijk(unsigned c, int nx, int ny, int& i, int& j, int& k)
+{
+    const unsigned q = c / (unsigned)nx;
+    i = (int)(c - q * (unsigned)nx);
+    const unsigned k_ = q / (unsigned)ny;
+    j = (int)(q - k_ * (unsigned)ny);
+    k = (int)k_;
+}
 
 // ---------------------------------------------------------------------------
 // weight packing
@@ -116,14 +126,30 @@ __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
     const uint4* __restrict__ wp = reinterpret_cast<const uint4*>(A.wp);
 
     // stage the halo: piece q of halo cell h, consecutive threads on
-    // consecutive pieces (contiguous along x in global memory)
-    for (int t = threadIdx.x; t < CH_CELLS * PARTS; t += 256) {
-        const int h = t / PARTS, q = t % PARTS;
-        const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
-        const unsigned src = (unsigned)wrap1(x0 - 1 + hx, nx) +
-                             (unsigned)nx * ((unsigned)wrap1(y0 - 1 + hy, ny) +
-                                             (unsigned)ny * (unsigned)wrap1(z0 - 1 + hz, nz));
-        *reinterpret_cast<uint4*>(tile + h * CS + 8 * q) = ld16(x + (size_t)src * CIN + 8 * q);
+    // consecutive pieces (contiguous along x in global memory); all loads
+    // of a thread are issued before its LDS writes
+    constexpr int FILL = (CH_CELLS * PARTS + 255) / 256;
+    uint4 fv[FILL];
+#pragma unroll
+    for (int f = 0; f < FILL; ++f) {
+        const int t = threadIdx.x + 256 * f;
+        fv[f] = make_uint4(0, 0, 0, 0);
+        if (t < CH_CELLS * PARTS) {
+            const int h = t / PARTS, q = t % PARTS;
+            const int hx = h % CH_X, hy = (h / CH_X) % CH_Y, hz = h / (CH_X * CH_Y);
+            const unsigned src = (unsigned)wrap1(x0 - 1 + hx, nx) +
+                                 (unsigned)nx * ((unsigned)wrap1(y0 - 1 + hy, ny) +
+                                                 (unsigned)ny * (unsigned)wrap1(z0 - 1 + hz, nz));
+            fv[f] = ld16(x + (size_t)src * CIN + 8 * q);
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < FILL; ++f) {
+        const int t = threadIdx.x + 256 * f;
+        if (t < CH_CELLS * PARTS) {
+            const int h = t / PARTS, q = t % PARTS;
+            *reinterpret_cast<uint4*>(tile + h * CS + 8 * q) = fv[f];
+        }
     }
     __syncthreads();
 
@@ -133,27 +159,46 @@ __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f4{ 0.f, 0.f, 0.f, 0.f };
 
-#pragma unroll 3
-    for (int s = 0; s < KS; ++s) {
+    // K step s: weight fragments from global memory (L2), activation
+    // fragments from the LDS halo; the loop is unrolled and the fragments of
+    // step s + 1 are loaded while the MFMAs of step s run
+    const int hbase = (wave + 1) * (CH_X * CH_Y) + CH_X + (r + 1);
+    auto load_a = [&](int s, bf16x8* a) {
+#pragma unroll
+        for (int m = 0; m < MB; ++m) a[m] = as_bf8(wp[((size_t)s * MB + m) * 64 + lane]);
+    };
+    auto load_b = [&](int s, bf16x8* bv) {
         const int K = 32 * s + 8 * g;
         const int o = K / CIN, c0 = K % CIN;
         const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-        bf16x8 bf[NB];
+        const int h0 = hbase + dz * (CH_X * CH_Y) + dy * CH_X + dx;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (o < 27) {
-                const int h = (wave + 1 + dz) * (CH_X * CH_Y) + (nb + 1 + dy) * CH_X + (r + 1 + dx);
-                v = *reinterpret_cast<const uint4*>(tile + h * CS + c0);
-            }
-            bf[nb] = as_bf8(v);
+            if (o < 27) v = *reinterpret_cast<const uint4*>(tile + (h0 + nb * CH_X) * CS + c0);
+            bv[nb] = as_bf8(v);
+        }
+    };
+    bf16x8 a_cur[MB], b_cur[NB];
+    load_a(0, a_cur);
+    load_b(0, b_cur);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        bf16x8 a_nxt[MB], b_nxt[NB];
+        if (s + 1 < KS) {
+            load_a(s + 1, a_nxt);
+            load_b(s + 1, b_nxt);
         }
 #pragma unroll
-        for (int m = 0; m < MB; ++m) {
-            const bf16x8 af = as_bf8(wp[((size_t)s * MB + m) * 64 + lane]);
+        for (int m = 0; m < MB; ++m)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
-                acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[nb], acc[m][nb], 0, 0, 0);
+                acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[m], b_cur[nb], acc[m][nb], 0, 0, 0);
+        if (s + 1 < KS) {
+#pragma unroll
+            for (int m = 0; m < MB; ++m) a_cur[m] = a_nxt[m];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) b_cur[nb] = b_nxt[nb];
         }
     }
 
@@ -223,68 +268,129 @@ hipError_t launch_conv3d(const ConvArgs& A, int cin, int cout, int epi, hipStrea
 // wgrad
 // ---------------------------------------------------------------------------
 
-// 8 consecutive values of a row starting at xs + dx (periodic), xs a
-// multiple of 8, from aligned 16-byte loads
-__device__ __forceinline__ uint4 shifted8(const uint16_t* row, int xs, int dx, int nx)
+// 8 consecutive bf16 starting one element after (dx = +1) or before
+// (dx = -1) the aligned group c, from the aligned groups around it
+__device__ __forceinline__ uint4 shift_right1(uint4 c, uint4 n)    // elements c[1..7], n[0]
 {
-    if (dx == 0) return ld16(row + xs);
-    if (dx > 0) {
-        const uint4 a = ld16(row + xs);
-        const uint4 b = ld16(row + (xs + 8 == nx ? 0 : xs + 8));
-        return make_uint4((a.x >> 16) | (a.y << 16), (a.y >> 16) | (a.z << 16),
-                          (a.z >> 16) | (a.w << 16), (a.w >> 16) | (b.x << 16));
-    }
-    const uint4 a = ld16(row + (xs == 0 ? nx - 8 : xs - 8));
-    const uint4 b = ld16(row + xs);
-    return make_uint4((a.w >> 16) | (b.x << 16), (b.x >> 16) | (b.y << 16),
-                      (b.y >> 16) | (b.z << 16), (b.z >> 16) | (b.w << 16));
+    return make_uint4((c.x >> 16) | (c.y << 16), (c.y >> 16) | (c.z << 16), (c.z >> 16) | (c.w << 16),
+                      (c.w >> 16) | (n.x << 16));
+}
+__device__ __forceinline__ uint4 shift_left1(uint4 p, uint4 c)     // elements p[7], c[0..6]
+{
+    return make_uint4((p.w >> 16) | (c.x << 16), (c.x >> 16) | (c.y << 16), (c.y >> 16) | (c.z << 16),
+                      (c.z >> 16) | (c.w << 16));
 }
 
+// Tile of wgrad: 32 (x) x 4 (y) x 2 (z) cells = 8 K steps of 32 cells (one
+// row segment each).  Its input halo is staged channel-major in LDS,
+// x from x0 - 8 to x0 + 40 (aligned groups of 8, so the dx = -1, 0, +1
+// fragments of a group come from three aligned 16-byte reads), y and z one
+// cell each side; the tile's dy rows are staged beside it (channel stride
+// padded by 8 bf16 so the 16 channels of a fragment read spread over the
+// banks).
+constexpr int WT_X = 32, WT_Y = 4, WT_Z = 2;
+constexpr int WL_X = WT_X + 16, WL_Y = WT_Y + 2, WL_Z = WT_Z + 2;
+
+// dW[o][ci][co] = sum_cell x[cell + d(o)][ci] dy[cell][co] as MFMA with
+// M = co (A = dy, channel-major), N = ci (B = shifted x), K = cells.  Nine
+// waves: wave w owns the offsets with (dy, dz) = (w % 3 - 1, w / 3 - 1) and
+// all three dx.  Persistent over tiles; each workgroup writes its partial
+// sums, wgrad_reduce adds them in a fixed order.
 template <int CI, int CO>
-__global__ void __launch_bounds__(256) conv3d_wgrad_kernel(WgradArgs A)
+__global__ void __launch_bounds__(576) conv3d_wgrad_kernel(WgradArgs A)
 {
-    constexpr int MB = (CO + 15) / 16, NBI = (CI + 15) / 16, NT = 7;   // offsets w + 4t
+    constexpr int MB = (CO + 15) / 16, NBI = (CI + 15) / 16;
+    constexpr int KSTEPS = WT_Y * WT_Z, DYS = KSTEPS * WT_X + 8;   // dy row of a channel, padded
+    // x channel stride padded by 8 bf16: the 16 channels of a fragment read
+    // then start 4 banks apart instead of on the same bank
+    constexpr int XCS = WL_Z * WL_Y * WL_X + 8;
+    __shared__ __align__(16) uint16_t xs[CI * XCS];
+    __shared__ __align__(16) uint16_t dys[CO * DYS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
+    const int ddy = wave % 3 - 1, ddz = wave / 3 - 1;
     const int nx = A.n[0], ny = A.n[1], nz = A.n[2];
     const size_t N = (size_t)nx * ny * nz;
-    const int nrows = ny * nz;
-    const int row0 = blockIdx.x * A.rows_per_wg;
-    const int row1 = min(nrows, row0 + A.rows_per_wg);
+    const int tx = nx / WT_X, ty = ny / WT_Y, ntiles = tx * ty * (nz / WT_Z);
 
-    f4 acc[NT][MB][NBI];
+    f4 acc[3][MB][NBI];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int m = 0; m < MB; ++m)
 #pragma unroll
-            for (int q = 0; q < NBI; ++q) acc[t][m][q] = f4{ 0.f, 0.f, 0.f, 0.f };
+            for (int q = 0; q < NBI; ++q) acc[d][m][q] = f4{ 0.f, 0.f, 0.f, 0.f };
 
-    for (int row = row0; row < row1; ++row) {
-        const int j = row % ny, k = row / ny;
-        for (int x0 = 0; x0 < nx; x0 += 32) {
-            const int xs = x0 + 8 * g;
-            bf16x8 af[MB];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int x0 = (t % tx) * WT_X, y0 = ((t / tx) % ty) * WT_Y, z0 = (t / (tx * ty)) * WT_Z;
+        // fill x (with halo) and dy of the tile in batches of FB loads per
+        // thread, each batch in flight at once; x item it < XI, dy items after
+        constexpr int XI = CI * WL_Z * WL_Y * (WL_X / 8), DI = CO * KSTEPS * (WT_X / 8), ITEMS = XI + DI;
+        constexpr int FILL = (ITEMS + 575) / 576, FB = FILL < 4 ? FILL : 4;
+        __syncthreads();                                   // previous tile's reads are done
+#pragma unroll
+        for (int f0 = 0; f0 < FILL; f0 += FB) {
+            uint4 fv[FB];
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                const int it = threadIdx.x + 576 * (f0 + f);
+                fv[f] = make_uint4(0, 0, 0, 0);
+                if (f0 + f < FILL && it < XI) {
+                    const int gx = it % (WL_X / 8), hy = (it / (WL_X / 8)) % WL_Y;
+                    const int hz = (it / (WL_X / 8 * WL_Y)) % WL_Z, ci = it / (WL_X / 8 * WL_Y * WL_Z);
+                    const int sx = x0 - 8 + 8 * gx, gxs = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+                    const size_t src = (size_t)ci * N + (size_t)gxs +
+                                       (size_t)nx * ((size_t)wrap1(y0 - 1 + hy, ny) + (size_t)ny * wrap1(z0 - 1 + hz, nz));
+                    fv[f] = ld16(A.xT + src);
+                } else if (f0 + f < FILL && it < ITEMS) {
+                    const int d = it - XI, gg = d % (WT_X / 8), ks = (d / (WT_X / 8)) % KSTEPS;
+                    const int co = d / (WT_X / 8 * KSTEPS);
+                    const size_t src = (size_t)co * N + (size_t)(x0 + 8 * gg) +
+                                       (size_t)nx * ((size_t)(y0 + ks % WT_Y) + (size_t)ny * (z0 + ks / WT_Y));
+                    fv[f] = ld16(A.dyT + src);
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < FB; ++f) {
+                const int it = threadIdx.x + 576 * (f0 + f);
+                if (f0 + f < FILL && it < XI) {
+                    const int gx = it % (WL_X / 8), hy = (it / (WL_X / 8)) % WL_Y;
+                    const int hz = (it / (WL_X / 8 * WL_Y)) % WL_Z, ci = it / (WL_X / 8 * WL_Y * WL_Z);
+                    *reinterpret_cast<uint4*>(xs + ci * XCS + (hz * WL_Y + hy) * WL_X + 8 * gx) = fv[f];
+                } else if (f0 + f < FILL && it < ITEMS) {
+                    const int d = it - XI, gg = d % (WT_X / 8), ks = (d / (WT_X / 8)) % KSTEPS;
+                    const int co = d / (WT_X / 8 * KSTEPS);
+                    *reinterpret_cast<uint4*>(dys + co * DYS + ks * WT_X + 8 * gg) = fv[f];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int ks = 0; ks < KSTEPS; ++ks) {
+            const int ky = ks % WT_Y, kz = ks / WT_Y;
+            bf16x8 af[MB];                                 // dy: 8 cells of one row segment per lane
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
                 const int co = 16 * m + r;
-                af[m] = as_bf8(co < CO ? ld16(A.dyT + (size_t)co * N + (size_t)row * nx + xs)
+                af[m] = as_bf8(co < CO ? *reinterpret_cast<const uint4*>(dys + co * DYS + ks * WT_X + 8 * g)
                                        : make_uint4(0, 0, 0, 0));
             }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int o = wave + 4 * t;
-                if (o >= 27) continue;
-                const int dx = o % 3 - 1, dy = (o / 3) % 3 - 1, dz = o / 9 - 1;
-                const size_t srow = (size_t)nx * ((size_t)wrap1(j + dy, ny) + (size_t)ny * wrap1(k + dz, nz));
+            for (int q = 0; q < NBI; ++q) {
+                const int ci = 16 * q + r;
+                uint4 lo = make_uint4(0, 0, 0, 0), mid = lo, hi = lo;
+                if (ci < CI) {
+                    const uint16_t* row = xs + ci * XCS + ((kz + 1 + ddz) * WL_Y + ky + 1 + ddy) * WL_X + 8 * g;
+                    lo = *reinterpret_cast<const uint4*>(row);
+                    mid = *reinterpret_cast<const uint4*>(row + 8);
+                    hi = *reinterpret_cast<const uint4*>(row + 16);
+                }
+                const bf16x8 bm = as_bf8(shift_left1(lo, mid)), b0 = as_bf8(mid), bp = as_bf8(shift_right1(mid, hi));
 #pragma unroll
-                for (int q = 0; q < NBI; ++q) {
-                    const int ci = 16 * q + r;
-                    const bf16x8 bf = as_bf8(ci < CI ? shifted8(A.xT + (size_t)ci * N + srow, xs, dx, nx)
-                                                     : make_uint4(0, 0, 0, 0));
-#pragma unroll
-                    for (int m = 0; m < MB; ++m)
-                        acc[t][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bf, acc[t][m][q], 0, 0, 0);
+                for (int m = 0; m < MB; ++m) {
+                    acc[0][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bm, acc[0][m][q], 0, 0, 0);
+                    acc[1][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], b0, acc[1][m][q], 0, 0, 0);
+                    acc[2][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bp, acc[2][m][q], 0, 0, 0);
                 }
             }
         }
@@ -292,9 +398,8 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(WgradArgs A)
     // D[co][ci] of offset o: lane holds co = 16 m + 4 g + e, ci = 16 q + r
     float* out = A.partial + (size_t)blockIdx.x * 27 * CI * CO;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int o = wave + 4 * t;
-        if (o >= 27) continue;
+    for (int d = 0; d < 3; ++d) {
+        const int o = (ddz + 1) * 9 + (ddy + 1) * 3 + d;
 #pragma unroll
         for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -304,19 +409,33 @@ __global__ void __launch_bounds__(256) conv3d_wgrad_kernel(WgradArgs A)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int co = 16 * m + 4 * g + e;
-                    if (co < CO) out[((size_t)o * CI + ci) * CO + co] = acc[t][m][q][e];
+                    if (co < CO) out[((size_t)o * CI + ci) * CO + co] = acc[d][m][q][e];
                 }
             }
     }
 }
 
-// dw[i] = sum over workgroups of partial[wg][i], in workgroup order
-__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int nwg, int count, float* __restrict__ dw)
+// dw[i] = sum over workgroups of partial[wg][i] in workgroup order: pass 1
+// sums WR_GROUPS contiguous ranges of workgroups, pass 2 the ranges
+constexpr int WR_GROUPS = 16;
+__global__ void wgrad_reduce1_kernel(const float* __restrict__ partial, int nwg, int count, float* __restrict__ mid)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int grp = blockIdx.y;
+    if (i >= count) return;
+    const int per = (nwg + WR_GROUPS - 1) / WR_GROUPS;
+    const int w0 = grp * per, w1 = min(nwg, w0 + per);
+    float acc = 0.0f;
+    for (int w = w0; w < w1; ++w) acc += partial[(size_t)w * count + i];
+    mid[(size_t)grp * count + i] = acc;
+}
+
+__global__ void wgrad_reduce2_kernel(const float* __restrict__ mid, int count, float* __restrict__ dw)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     float acc = 0.0f;
-    for (int w = 0; w < nwg; ++w) acc += partial[(size_t)w * count + i];
+    for (int k = 0; k < WR_GROUPS; ++k) acc += mid[(size_t)k * count + i];
     dw[i] = acc;
 }
 
@@ -357,28 +476,33 @@ __global__ void bias_grad_final_kernel(const double* __restrict__ partial, int n
     dbias[co] = (float)acc;
 }
 
-int wgrad_blocks(const int n[3], int& rows_per_wg)
+int wgrad_blocks(const int n[3], int& tiles_per_wg)
 {
-    const int nrows = n[1] * n[2];
-    rows_per_wg = (nrows + 511) / 512;
-    return (nrows + rows_per_wg - 1) / rows_per_wg;
+    const int ntiles = (n[0] / WT_X) * (n[1] / WT_Y) * (n[2] / WT_Z);
+    const int nwg = ntiles < WGRAD_MAX_WG ? ntiles : WGRAD_MAX_WG;
+    tiles_per_wg = (ntiles + nwg - 1) / nwg;
+    return nwg;
 }
 
 hipError_t launch_conv3d_wgrad(const WgradArgs& A, int cin, int cout, float* dw, hipStream_t s)
 {
-    const int nwg = (A.n[1] * A.n[2] + A.rows_per_wg - 1) / A.rows_per_wg;
+    int tpw = 0;
+    const int nwg = wgrad_blocks(A.n, tpw);
     if (cin == 8 && cout == 32)
-        hipLaunchKernelGGL((conv3d_wgrad_kernel<8, 32>), dim3(nwg), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((conv3d_wgrad_kernel<8, 32>), dim3(nwg), dim3(576), 0, s, A);
     else if (cin == 32 && cout == 32)
-        hipLaunchKernelGGL((conv3d_wgrad_kernel<32, 32>), dim3(nwg), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((conv3d_wgrad_kernel<32, 32>), dim3(nwg), dim3(576), 0, s, A);
     else if (cin == 32 && cout == 8)
-        hipLaunchKernelGGL((conv3d_wgrad_kernel<32, 8>), dim3(nwg), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((conv3d_wgrad_kernel<32, 8>), dim3(nwg), dim3(576), 0, s, A);
     else if (cin == 8 && cout == 8)
-        hipLaunchKernelGGL((conv3d_wgrad_kernel<8, 8>), dim3(nwg), dim3(256), 0, s, A);
+        hipLaunchKernelGGL((conv3d_wgrad_kernel<8, 8>), dim3(nwg), dim3(576), 0, s, A);
     else
         return hipErrorInvalidValue;
     const int count = 27 * cin * cout;
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((count + 255) / 256), dim3(256), 0, s, A.partial, nwg, count, dw);
+    float* mid = A.partial + (size_t)nwg * count;
+    hipLaunchKernelGGL(wgrad_reduce1_kernel, dim3((count + 255) / 256, WR_GROUPS), dim3(256), 0, s, A.partial, nwg,
+                       count, mid);
+    hipLaunchKernelGGL(wgrad_reduce2_kernel, dim3((count + 255) / 256), dim3(256), 0, s, mid, count, dw);
     return hipGetLastError();
 }
 
@@ -423,7 +547,7 @@ __global__ void normalize_kernel(const float* __restrict__ u, size_t N, ClosureS
 #pragma unroll
         for (int f = 0; f < 8; ++f) {
             b[f] = f2bf((u[(size_t)f * N + c] - sc.in_mean[f]) / sc.in_std[f]);
-            xT[(size_t)f * N + c] = b[f];
+            if (xT) xT[(size_t)f * N + c] = b[f];
         }
         uint4 v;
         v.x = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
@@ -459,13 +583,24 @@ __global__ void __launch_bounds__(256) chsum_partial_kernel(const float* __restr
     if (threadIdx.x < nch) partial[(size_t)blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void chsum_final_kernel(const double* partial, int nblk, int nch, double scale, double* out)
+// out[f] = scale * sum over blocks of partial[b * 8 + f]: 256 threads, each a
+// fixed stride of blocks, then a fixed tree (deterministic)
+__global__ void __launch_bounds__(256) chsum_final_kernel(const double* partial, int nblk, int nch, double scale,
+                                                          double* out)
 {
-    const int f = threadIdx.x;
-    if (f >= nch) return;
-    double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += partial[(size_t)b * 8 + f];
-    out[f] = acc * scale;
+    __shared__ double sh[8][256];
+    for (int f = 0; f < nch; ++f) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[(size_t)b * 8 + f];
+        sh[f][threadIdx.x] = acc;
+    }
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st)
+            for (int f = 0; f < nch; ++f) sh[f][threadIdx.x] += sh[f][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < nch) out[threadIdx.x] = sh[threadIdx.x][0] * scale;
 }
 
 hipError_t launch_chsum(const float* a, size_t N, size_t cstride, size_t fstride, int nch, double scale,
@@ -473,7 +608,7 @@ hipError_t launch_chsum(const float* a, size_t N, size_t cstride, size_t fstride
 {
     const int nblk = CHSUM_BLOCKS;
     hipLaunchKernelGGL(chsum_partial_kernel, dim3(nblk), dim3(256), 0, s, a, N, cstride, fstride, nch, partial);
-    hipLaunchKernelGGL(chsum_final_kernel, dim3(1), dim3(64), 0, s, partial, nblk, nch, scale, out);
+    hipLaunchKernelGGL(chsum_final_kernel, dim3(1), dim3(256), 0, s, partial, nblk, nch, scale, out);
     return hipGetLastError();
 }
 
@@ -483,7 +618,8 @@ __global__ void project_kernel(const float* __restrict__ o, const double* __rest
 {
     const size_t N = (size_t)nx * ny * nz;
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        int i, j, k;
+        cell_ijk((unsigned)c, nx, ny, i, j, k);
         for (int f = 0; f < 5; ++f) delta[(size_t)f * N + c] = sc.out_scale[f] * (float)((double)o[c * 8 + f] - mean[f]);
         const size_t cxp = (size_t)wrap1(i + 1, nx) + (size_t)nx * (j + (size_t)ny * k);
         const size_t cyp = (size_t)i + (size_t)nx * (wrap1(j + 1, ny) + (size_t)ny * k);
@@ -509,7 +645,8 @@ __global__ void project_T_kernel(const float* __restrict__ g, const double* __re
 {
     const size_t N = (size_t)nx * ny * nz;
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        int i, j, k;
+        cell_ijk((unsigned)c, nx, ny, i, j, k);
         for (int f = 0; f < 5; ++f) go[c * 8 + f] = sc.out_scale[f] * (float)((double)g[(size_t)f * N + c] - gmean[f]);
         const size_t cxm = (size_t)wrap1(i - 1, nx) + (size_t)nx * (j + (size_t)ny * k);
         const size_t cym = (size_t)i + (size_t)nx * (wrap1(j - 1, ny) + (size_t)ny * k);
@@ -534,13 +671,15 @@ hipError_t launch_project_T(const float* g, const double* gmean, const int n[3],
 __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ delta, const float* __restrict__ target,
                                                    size_t N, ClosureScales sc, float* __restrict__ g, double* partial)
 {
+    const int f = blockIdx.y;
+    const float ts = sc.target_scale[f];
+    const double gsc = 2.0 / (double)ts / (8.0 * (double)N);
+    const size_t off = (size_t)f * N;
     double acc = 0.0;
-    const double inv = 1.0 / (8.0 * (double)N);
-    for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < 8 * N; t += (size_t)gridDim.x * 256) {
-        const int f = (int)(t / N);
-        const float r = (delta[t] - target[t]) / sc.target_scale[f];
+    for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < N; c += (size_t)gridDim.x * 256) {
+        const float r = (delta[off + c] - target[off + c]) / ts;
         acc += (double)r * (double)r;
-        g[t] = (float)(2.0 * (double)r / (double)sc.target_scale[f] * inv);
+        g[off + c] = (float)((double)r * gsc);
     }
     __shared__ double sh[256];
     sh[threadIdx.x] = acc;
@@ -549,67 +688,112 @@ __global__ void __launch_bounds__(256) loss_kernel(const float* __restrict__ del
         if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x * 8] = sh[0];
+    if (threadIdx.x == 0) partial[(size_t)f * gridDim.x + blockIdx.x] = sh[0];
+}
+
+// out = scale * sum of partial[0 .. n), 256 threads at fixed strides, then a
+// fixed tree (deterministic)
+__global__ void __launch_bounds__(256) sum_final_kernel(const double* __restrict__ partial, int n, double scale,
+                                                        double* out)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < n; b += 256) acc += partial[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0] * scale;
 }
 
 hipError_t launch_loss(const float* delta, const float* target, size_t N, const ClosureScales& sc, float* g,
                        double* partial, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(loss_kernel, dim3(CHSUM_BLOCKS), dim3(256), 0, s, delta, target, N, sc, g, partial);
-    hipLaunchKernelGGL(chsum_final_kernel, dim3(1), dim3(64), 0, s, partial, CHSUM_BLOCKS, 1,
-                       1.0 / (8.0 * (double)N), out);
+    // LOSS_BLOCKS per field, 8 * LOSS_BLOCKS dense partials (fits the CHSUM_BLOCKS * 8 scratch)
+    constexpr int LOSS_BLOCKS = CHSUM_BLOCKS / 2;
+    hipLaunchKernelGGL(loss_kernel, dim3(LOSS_BLOCKS, 8), dim3(256), 0, s, delta, target, N, sc, g, partial);
+    hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(256), 0, s, partial, 8 * LOSS_BLOCKS, 1.0 / (8.0 * (double)N),
+                       out);
     return hipGetLastError();
 }
 
 // Guard of the corrected state u + theta delta for theta = 2^-k, k = 0..3:
 // bit k of *bad is raised if some cell has rho <= 0, p < 0 or a non-finite
 // value at that theta (pressure from the cell-centred field, the mean of
-// the two faces).
-__global__ void guard_levels_kernel(const float* __restrict__ u, const float* __restrict__ delta, int nx, int ny,
-                                    int nz, float gamma, int* bad)
+// the two faces; tested without a division as 2 rho (e - |B|^2/2) >= |m|^2).
+__global__ void __launch_bounds__(256) guard_levels_kernel(const float* __restrict__ u,
+                                                          const float* __restrict__ delta, int nx, int ny, int nz,
+                                                          int* bad)
 {
-    const size_t N = (size_t)nx * ny * nz;
+    // 4 consecutive x cells per thread (nx is a multiple of 4)
+    const unsigned N = (unsigned)nx * ny * nz, N4 = N / 4;
     int b = 0;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
-        const size_t cn[3] = { (size_t)wrap1(i + 1, nx) + (size_t)nx * (j + (size_t)ny * k),
-                               (size_t)i + (size_t)nx * (wrap1(j + 1, ny) + (size_t)ny * k),
-                               (size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k + 1, nz)) };
-        float u0[8], d0[8], u1[3], d1[3];
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < N4; t += gridDim.x * blockDim.x) {
+        const unsigned c = 4 * t;
+        int i, j, k;
+        cell_ijk(c, nx, ny, i, j, k);
+        const unsigned xp = c - i + wrap1(i + 4, nx);
+        const unsigned cyp = (unsigned)i + (unsigned)nx * ((unsigned)wrap1(j + 1, ny) + (unsigned)ny * k);
+        const unsigned czp = (unsigned)i + (unsigned)nx * ((unsigned)j + (unsigned)ny * wrap1(k + 1, nz));
+        float u0[8][4], d0[8][4], u1[3][4], d1[3][4];
         for (int f = 0; f < 8; ++f) {
-            u0[f] = u[(size_t)f * N + c];
-            d0[f] = delta[(size_t)f * N + c];
+            const float4 a4 = *reinterpret_cast<const float4*>(u + (size_t)f * N + c);
+            const float4 b4 = *reinterpret_cast<const float4*>(delta + (size_t)f * N + c);
+            u0[f][0] = a4.x; u0[f][1] = a4.y; u0[f][2] = a4.z; u0[f][3] = a4.w;
+            d0[f][0] = b4.x; d0[f][1] = b4.y; d0[f][2] = b4.z; d0[f][3] = b4.w;
         }
-        for (int a = 0; a < 3; ++a) {
-            u1[a] = u[(size_t)(5 + a) * N + cn[a]];
-            d1[a] = delta[(size_t)(5 + a) * N + cn[a]];
+        // upper faces: b_x of the next cell along x, b_y / b_z of the next row / plane
+        for (int q = 0; q < 3; ++q) { u1[0][q] = u0[5][q + 1]; d1[0][q] = d0[5][q + 1]; }
+        u1[0][3] = u[(size_t)5 * N + xp];
+        d1[0][3] = delta[(size_t)5 * N + xp];
+        {
+            const float4 a4 = *reinterpret_cast<const float4*>(u + (size_t)6 * N + cyp);
+            const float4 b4 = *reinterpret_cast<const float4*>(delta + (size_t)6 * N + cyp);
+            const float4 c4 = *reinterpret_cast<const float4*>(u + (size_t)7 * N + czp);
+            const float4 e4 = *reinterpret_cast<const float4*>(delta + (size_t)7 * N + czp);
+            u1[1][0] = a4.x; u1[1][1] = a4.y; u1[1][2] = a4.z; u1[1][3] = a4.w;
+            d1[1][0] = b4.x; d1[1][1] = b4.y; d1[1][2] = b4.z; d1[1][3] = b4.w;
+            u1[2][0] = c4.x; u1[2][1] = c4.y; u1[2][2] = c4.z; u1[2][3] = c4.w;
+            d1[2][0] = e4.x; d1[2][1] = e4.y; d1[2][2] = e4.z; d1[2][3] = e4.w;
         }
-        for (int lev = 0; lev < GUARD_LEVELS; ++lev) {
-            const float th = ldexpf(1.0f, -lev);
-            float v[8];
-            bool ok = true;
-            for (int f = 0; f < 8; ++f) {
-                v[f] = u0[f] + th * d0[f];
-                ok = ok && isfinite(v[f]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int lev = 0; lev < GUARD_LEVELS; ++lev) {
+                const float th = ldexpf(1.0f, -lev);
+                float v[8];
+                bool ok = true;
+                for (int f = 0; f < 8; ++f) {
+                    v[f] = u0[f][q] + th * d0[f][q];
+                    ok = ok && isfinite(v[f]);
+                }
+                float b2 = 0.0f;
+                for (int a = 0; a < 3; ++a) {
+                    const float bc = 0.5f * (v[5 + a] + (u1[a][q] + th * d1[a][q]));
+                    b2 += bc * bc;
+                }
+                // p >= 0 with rho > 0  <=>  2 rho (e - |B|^2 / 2) >= |m|^2 (gamma > 1)
+                const float lhs = 2.0f * v[0] * (v[4] - 0.5f * b2);
+                const float m2 = v[1] * v[1] + v[2] * v[2] + v[3] * v[3];
+                ok = ok && v[0] > 0.0f && lhs >= m2;
+                if (!ok) b |= 1 << lev;
             }
-            float b2 = 0.0f;
-            for (int a = 0; a < 3; ++a) {
-                const float bc = 0.5f * (v[5 + a] + (u1[a] + th * d1[a]));
-                b2 += bc * bc;
-            }
-            const float p = (gamma - 1.0f) * (v[4] - 0.5f * (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / v[0] -
-                                               0.5f * b2);
-            ok = ok && v[0] > 0.0f && p >= 0.0f;
-            if (!ok) b |= 1 << lev;
-        }
     }
-    if (b) atomicOr(bad, b);
+    // one atomic per wave: OR of the level bits over its lanes
+    int wb = 0;
+#pragma unroll
+    for (int lev = 0; lev < GUARD_LEVELS; ++lev)
+        if (__ballot((b >> lev) & 1)) wb |= 1 << lev;
+    if ((threadIdx.x & 63) == 0 && wb) atomicOr(bad, wb);
 }
 
 hipError_t launch_guard_levels(const float* u, const float* delta, const int n[3], float gamma, int* bad,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(guard_levels_kernel, dim3(2048), dim3(256), 0, s, u, delta, n[0], n[1], n[2], gamma, bad);
+    (void)gamma;                      // the sign of p does not depend on gamma > 1
+    hipLaunchKernelGGL(guard_levels_kernel, dim3(2048), dim3(256), 0, s, u, delta, n[0], n[1], n[2], bad);
     return hipGetLastError();
 }
 
@@ -694,7 +878,8 @@ __global__ void __launch_bounds__(256) stats_partial_kernel(const float* __restr
     const float* tf = t + (size_t)f * N;
     double a[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 };
     for (size_t c = (size_t)blockIdx.x * 256 + threadIdx.x; c < N; c += (size_t)gridDim.x * 256) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        int i, j, k;
+        cell_ijk((unsigned)c, nx, ny, i, j, k);
         const double x = uf[c];
         a[0] += x;
         a[1] += x * x;
@@ -719,47 +904,72 @@ __global__ void __launch_bounds__(256) stats_partial_kernel(const float* __restr
     if (threadIdx.x < 5) partial[((size_t)blockIdx.x * 8 + f) * 5 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// out[q * 8 + f] = sum over blocks of partial[(b * 8 + f) * 5 + q]
-__global__ void stats_final_kernel(const double* __restrict__ partial, int nblk, double* __restrict__ out)
+// out[q * 8 + f] = sum over blocks of partial[(b * 8 + f) * 5 + q]: 256
+// threads over the blocks, then a fixed tree per output
+__global__ void __launch_bounds__(256) stats_final_kernel(const double* __restrict__ partial, int nblk,
+                                                          double* __restrict__ out)
 {
-    const int k = threadIdx.x;
-    if (k >= 40) return;
-    const int q = k / 8, f = k % 8;
-    double acc = 0.0;
-    for (int b = 0; b < nblk; ++b) acc += partial[((size_t)b * 8 + f) * 5 + q];
-    out[k] = acc;
+    __shared__ double sh[256];
+    for (int k = 0; k < 40; ++k) {
+        const int q = k / 8, f = k % 8;
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 256) acc += partial[((size_t)b * 8 + f) * 5 + q];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = sh[0];
+        __syncthreads();
+    }
 }
 
 hipError_t launch_stats(const float* u, const float* t, const int n[3], double* partial, double* out, hipStream_t s)
 {
     hipLaunchKernelGGL(stats_partial_kernel, dim3(STATS_BLOCKS, 8), dim3(256), 0, s, u, t, n[0], n[1], n[2], partial);
-    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(64), 0, s, partial, STATS_BLOCKS, out);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(256), 0, s, partial, STATS_BLOCKS, out);
     return hipGetLastError();
 }
 
 // Roughness gate: g0(c) = (1/8) sum_f inv_R[f] * sum over axes
-// |u_f(c+a) - 2 u_f(c) + u_f(c-a)| (u field-major FP32)
+// |u_f(c+a) - 2 u_f(c) + u_f(c-a)| (u field-major FP32).  A thread takes 4
+// consecutive x cells (nx is a multiple of 4): one 16-byte load per field
+// for the cells and for each y / z neighbour row, two scalars for x.
 __global__ void __launch_bounds__(256) gate_rough_kernel(const float* __restrict__ u, int nx, int ny, int nz,
                                                          GateScales gs, float* __restrict__ g0)
 {
-    const size_t N = (size_t)nx * ny * nz;
-    for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
-        const size_t row = (size_t)nx * (j + (size_t)ny * k);
-        const size_t nb[6] = { row + wrap1(i + 1, nx), row + wrap1(i - 1, nx),
-                               (size_t)i + (size_t)nx * (wrap1(j + 1, ny) + (size_t)ny * k),
-                               (size_t)i + (size_t)nx * (wrap1(j - 1, ny) + (size_t)ny * k),
-                               (size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k + 1, nz)),
-                               (size_t)i + (size_t)nx * (j + (size_t)ny * wrap1(k - 1, nz)) };
-        float acc = 0.0f;
+    const unsigned N = (unsigned)nx * ny * nz, N4 = N / 4;
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < N4; t += gridDim.x * blockDim.x) {
+        const unsigned c = 4 * t;
+        int i, j, k;
+        cell_ijk(c, nx, ny, i, j, k);
+        const unsigned row = c - i;
+        const unsigned cyp = (unsigned)i + (unsigned)nx * ((unsigned)wrap1(j + 1, ny) + (unsigned)ny * k);
+        const unsigned cym = (unsigned)i + (unsigned)nx * ((unsigned)wrap1(j - 1, ny) + (unsigned)ny * k);
+        const unsigned czp = (unsigned)i + (unsigned)nx * ((unsigned)j + (unsigned)ny * wrap1(k + 1, nz));
+        const unsigned czm = (unsigned)i + (unsigned)nx * ((unsigned)j + (unsigned)ny * wrap1(k - 1, nz));
+        const unsigned xm = row + wrap1(i - 1, nx), xp = row + wrap1(i + 4, nx);
+        float acc[4] = { 0.f, 0.f, 0.f, 0.f };
         for (int f = 0; f < 8; ++f) {
             const float* uf = u + (size_t)f * N;
-            const float x2 = 2.0f * uf[c];
-            float r = 0.0f;
-            for (int a = 0; a < 3; ++a) r += fabsf((uf[nb[2 * a]] - x2) + uf[nb[2 * a + 1]]);
-            acc += r * gs.inv_r[f];
+            const float4 v = *reinterpret_cast<const float4*>(uf + c);
+            const float4 vyp = *reinterpret_cast<const float4*>(uf + cyp);
+            const float4 vym = *reinterpret_cast<const float4*>(uf + cym);
+            const float4 vzp = *reinterpret_cast<const float4*>(uf + czp);
+            const float4 vzm = *reinterpret_cast<const float4*>(uf + czm);
+            const float a[6] = { uf[xm], v.x, v.y, v.z, v.w, uf[xp] };
+            const float yp[4] = { vyp.x, vyp.y, vyp.z, vyp.w }, ym[4] = { vym.x, vym.y, vym.z, vym.w };
+            const float zp[4] = { vzp.x, vzp.y, vzp.z, vzp.w }, zm[4] = { vzm.x, vzm.y, vzm.z, vzm.w };
+            const float w = gs.inv_r[f];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float x2 = 2.0f * a[q + 1];
+                const float r = fabsf((a[q + 2] - x2) + a[q]) + fabsf((yp[q] - x2) + ym[q]) + fabsf((zp[q] - x2) + zm[q]);
+                acc[q] += r * w;
+            }
         }
-        g0[c] = 0.125f * acc;
+        *reinterpret_cast<float4*>(g0 + c) = make_float4(0.125f * acc[0], 0.125f * acc[1], 0.125f * acc[2], 0.125f * acc[3]);
     }
 }
 
@@ -769,7 +979,8 @@ __global__ void __launch_bounds__(256) gate_max_kernel(const float* __restrict__
 {
     const size_t N = (size_t)nx * ny * nz;
     for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+        int i, j, k;
+        cell_ijk((unsigned)c, nx, ny, i, j, k);
         const size_t row = (size_t)nx * (j + (size_t)ny * k);
         float m = g0[c];
         m = fmaxf(m, g0[row + wrap1(i + 1, nx)]);

@@ -52,7 +52,7 @@ struct mhd_closure {
     GateScales gs;
     float *gate0, *gate;
     int *bad, *fallbacks;
-    int rows_per_wg, nwg;
+    int tiles_per_wg, nwg;
 };
 
 static int check_cl(const mhd_closure* c)
@@ -93,7 +93,7 @@ extern "C" mhd_closure* mhd_closure_create(int nx, int ny, int nz, void* hip_str
         c->sc.out_scale[f] = 1.0f; c->sc.target_scale[f] = 1.0f;
     }
     const size_t N = c->N;
-    c->nwg = wgrad_blocks(c->n, c->rows_per_wg);
+    c->nwg = wgrad_blocks(c->n, c->tiles_per_wg);
     bool ok = true;
     auto A = [&](void** p, size_t bytes) { if (ok && hipMalloc(p, bytes) != hipSuccess) ok = false; };
     A((void**)&c->params, NPARAM * 4); A((void**)&c->grads, NPARAM * 4);
@@ -110,7 +110,7 @@ extern "C" mhd_closure* mhd_closure_create(int nx, int ny, int nz, void* hip_str
     A((void**)&c->g1, N * 32 * 2); A((void**)&c->g1T, N * 32 * 2);
     A((void**)&c->o, N * 8 * 4); A((void**)&c->delta, N * 8 * 4); A((void**)&c->g, N * 8 * 4);
     A((void**)&c->go, N * 8 * 4);
-    A((void**)&c->wpart, (size_t)c->nwg * 27 * 32 * 32 * 4);
+    A((void**)&c->wpart, (size_t)(c->nwg + 16) * 27 * 32 * 32 * 4);
     A((void**)&c->chpart, (size_t)CHSUM_BLOCKS * 8 * 8); A((void**)&c->chout, 16 * 8);
     A((void**)&c->loss, 8); A((void**)&c->bad, 4); A((void**)&c->fallbacks, 8);
     A((void**)&c->stpart, (size_t)STATS_BLOCKS * 8 * 5 * 8); A((void**)&c->stout, 40 * 8);
@@ -209,18 +209,19 @@ static int pack_all(mhd_closure* c)
     return MHD_OK;
 }
 
-// u: FP32 field-major [8][cell] -> delta [8][cell]
-static int forward(mhd_closure* c, const float* u)
+// u: FP32 field-major [8][cell] -> delta [8][cell]; with `train` the
+// channel-major activation copies that wgrad reads are written too
+static int forward(mhd_closure* c, const float* u, bool train)
 {
     int r = pack_all(c);
     if (r) return r;
-    HIP_TRY(c, launch_normalize(u, c->N, c->sc, c->x0, c->x0T, c->stream));
+    HIP_TRY(c, launch_normalize(u, c->N, c->sc, c->x0, train ? c->x0T : nullptr, c->stream));
     ConvArgs A;
     memset(&A, 0, sizeof A);
     A.n[0] = c->n[0]; A.n[1] = c->n[1]; A.n[2] = c->n[2];
-    A.x = c->x0; A.wp = c->wp[0]; A.bias = c->params + boff(0); A.yb = c->a1; A.ybT = c->a1T;
+    A.x = c->x0; A.wp = c->wp[0]; A.bias = c->params + boff(0); A.yb = c->a1; A.ybT = train ? c->a1T : nullptr;
     HIP_TRY(c, launch_conv3d(A, 8, 32, EPI_BIAS_RELU, c->stream));
-    A.x = c->a1; A.wp = c->wp[1]; A.bias = c->params + boff(1); A.yb = c->a2; A.ybT = c->a2T;
+    A.x = c->a1; A.wp = c->wp[1]; A.bias = c->params + boff(1); A.yb = c->a2; A.ybT = train ? c->a2T : nullptr;
     HIP_TRY(c, launch_conv3d(A, 32, 32, EPI_BIAS_RELU, c->stream));
     A.x = c->a2; A.wp = c->wp[2]; A.bias = c->params + boff(2); A.yb = nullptr; A.ybT = nullptr; A.yf = c->o;
     HIP_TRY(c, launch_conv3d(A, 32, 8, EPI_BIAS_F32, c->stream));
@@ -246,7 +247,7 @@ static int backward(mhd_closure* c, const float* target)
     WgradArgs W;
     W.n[0] = c->n[0]; W.n[1] = c->n[1]; W.n[2] = c->n[2];
     W.partial = c->wpart;
-    W.rows_per_wg = c->rows_per_wg;
+    W.tiles_per_wg = c->tiles_per_wg;
     // layer 3
     W.xT = c->a2T; W.dyT = c->gobT;
     HIP_TRY(c, launch_conv3d_wgrad(W, 32, 8, c->grads + woff(2), c->stream));
@@ -274,7 +275,7 @@ extern "C" int mhd_closure_forward(mhd_closure* c, const float* u_dev, float* de
     int r = check_cl(c);
     if (r) return r;
     if (!u_dev || !delta_dev) return mhd_fail(MHD_EINVAL, "null device pointer");
-    if ((r = forward(c, u_dev))) return r;
+    if ((r = forward(c, u_dev, false))) return r;
     HIP_TRY(c, hipMemcpyAsync(delta_dev, c->delta, c->N * 8 * 4, hipMemcpyDeviceToDevice, c->stream));
     return MHD_OK;
 }
@@ -286,7 +287,7 @@ extern "C" int mhd_closure_grad(mhd_closure* c, const float* u_dev, const float*
     if (r) return r;
     if (!u_dev || !target_dev) return mhd_fail(MHD_EINVAL, "null device pointer");
     if (grad_host && n != NPARAM) return mhd_fail(MHD_EINVAL, "expected %zu gradient entries", NPARAM);
-    if ((r = forward(c, u_dev))) return r;
+    if ((r = forward(c, u_dev, true))) return r;
     if ((r = backward(c, target_dev))) return r;
     if (loss) HIP_TRY(c, hipMemcpyAsync(loss, c->loss, 8, hipMemcpyDeviceToHost, c->stream));
     if (grad_host) HIP_TRY(c, hipMemcpyAsync(grad_host, c->grads, NPARAM * 4, hipMemcpyDeviceToHost, c->stream));
@@ -301,7 +302,7 @@ extern "C" int mhd_closure_train_step(mhd_closure* c, const float* u_dev, const 
     if (r) return r;
     if (!u_dev || !target_dev) return mhd_fail(MHD_EINVAL, "null device pointer");
     if (!(lr > 0.0f)) return mhd_fail(MHD_EINVAL, "learning rate must be > 0");
-    if ((r = forward(c, u_dev))) return r;
+    if ((r = forward(c, u_dev, true))) return r;
     if ((r = backward(c, target_dev))) return r;
     c->adam_step += 1;
     HIP_TRY(c, launch_adam(c->params, c->grads, c->adam_m, c->adam_v, (int)NPARAM, lr, 0.9f, 0.999f, 1e-8f,
@@ -330,7 +331,7 @@ extern "C" int mhd_closure_step(mhd_closure* c, mhd_ctx* coarse, double cfl)
     int all0 = 0;
     float* u = (float*)mhd_internal_state(coarse, &all0);
     if (!all0) return mhd_fail(MHD_ESTATE, "coarse state not in its first buffer");
-    if ((r = forward(c, u))) return r;
+    if ((r = forward(c, u, false))) return r;
     HIP_TRY(c, launch_zero_int(c->bad, c->stream));
     HIP_TRY(c, launch_guard_levels(u, c->delta, c->n, (float)mhd_internal_gamma(coarse), c->bad, c->stream));
     HIP_TRY(c, launch_apply_level(u, c->delta, c->N * 8, c->bad, c->fallbacks, c->stream));
@@ -457,10 +458,10 @@ extern "C" int mhd_conv3d_wgrad(const int* n, int cin, int cout, const void* xT,
     WgradArgs W;
     W.n[0] = n[0]; W.n[1] = n[1]; W.n[2] = n[2];
     W.xT = (const uint16_t*)xT; W.dyT = (const uint16_t*)dyT;
-    const int nwg = wgrad_blocks(W.n, W.rows_per_wg);
+    const int nwg = wgrad_blocks(W.n, W.tiles_per_wg);
     float *part = nullptr, *dw = nullptr, *db = nullptr;
     const size_t nw = (size_t)27 * cin * cout;
-    HIP_TRY(&h, hipMalloc(&part, (size_t)nwg * nw * 4));
+    HIP_TRY(&h, hipMalloc(&part, (size_t)(nwg + 16) * nw * 4));
     HIP_TRY(&h, hipMalloc(&dw, nw * 4));
     HIP_TRY(&h, hipMalloc(&db, cout * 4));
     W.partial = part;
