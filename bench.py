@@ -193,8 +193,9 @@ def run_closure(args, wl, torch, mhd):
         mean = st[0] / ncell
         std = np.sqrt(np.maximum(st[1] / ncell - mean ** 2, 0.0)) + 1e-6
         cl.set_scales(mean, std, np.full(8, 1e-4), np.full(8, 1e-4))
-        R = st[4] / ncell
-        cl.set_gate(np.maximum(R, 1e-6 * max(R.max(), 1e-30)))
+        # one pooled mean roughness for all fields (fields that start flat,
+        # like the density here, would otherwise get a huge gate)
+        cl.set_gate(np.full(8, max(float(np.mean(st[4])) / ncell, 1e-30)))
         wdesc = "untrained weights (timing only)"
     log(f"[bench] closure {n}^3, {wdesc}; warm-up")
     for _ in range(args.warmup):

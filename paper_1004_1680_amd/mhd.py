@@ -43,6 +43,12 @@ def load():
         raise RuntimeError(
             f"HIP library {LIB_PATH} not built: run paper_1004_1680_amd/build.py "
             "(or __graft_entry__.build())")
+    # One HIP runtime per process: torch ships its own libamdhip64.so.7.
+    # Loading torch first makes the dynamic loader bind libmhd.so to that
+    # same runtime (same soname), so torch's streams and device pointers are
+    # native to the library; the other order would bring up a second runtime
+    # that keeps torch from seeing the GPU.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     dp = ctypes.POINTER(ctypes.c_double)

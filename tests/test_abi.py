@@ -24,7 +24,7 @@ def test_header_declares_the_boundary():
 
 def test_library_exports_every_declared_symbol():
     from paper_1004_1680_amd import mhd
-    lib = ctypes.CDLL(mhd.LIB_PATH)
+    lib = mhd.load()
     missing = [n for n in declared_symbols() if not hasattr(lib, n)]
     assert not missing, missing
     # the binding wraps each of them under the same name
@@ -60,3 +60,14 @@ def test_null_handle_calls_fail_cleanly():
     assert lib.mhd_fluid(None, 3, 0.1) == mhd.MHD_EINVAL
     assert lib.mhd_diag(None, None) == mhd.MHD_EINVAL
     lib.mhd_destroy(None)
+
+
+def test_library_shares_torchs_hip_runtime():
+    """after load(), exactly one libamdhip64 is mapped in the process: the
+    one torch loaded (two HIP runtimes in one process keep torch from seeing
+    the GPU once the library's runtime initialised first)"""
+    from paper_1004_1680_amd import mhd
+    mhd.load()
+    with open("/proc/self/maps") as f:
+        libs = {line.split()[-1] for line in f if "libamdhip64" in line}
+    assert len(libs) == 1, libs
