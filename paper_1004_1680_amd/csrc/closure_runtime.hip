@@ -335,6 +335,7 @@ extern "C" int mhd_closure_step(mhd_closure* c, mhd_ctx* coarse, double cfl)
     HIP_TRY(c, launch_zero_int(c->bad, c->stream));
     HIP_TRY(c, launch_guard_levels(u, c->delta, c->n, (float)mhd_internal_gamma(coarse), c->bad, c->stream));
     HIP_TRY(c, launch_apply_level(u, c->delta, c->N * 8, c->bad, c->fallbacks, c->stream));
+    mhd_internal_state_changed(coarse);   // the fused CFL of the plain step no longer applies
     return MHD_OK;
 }
 

@@ -204,4 +204,30 @@ __device__ __forceinline__ T upwind_flux2(T a, T qm, T q0, T q1, T q2)
 // Index helpers for a periodic [nz][ny][nx] grid.
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Signal speed max_d |v_d| + sqrt((gamma p + |Bbar|^2) / rho) of one cell in
+// FP64 (the CFL condition, section II.B), the cell-centred field the mean of
+// the two faces of each axis (b*0: own low face, b*1: the next cell's).
+// Folds it into vmax, or raises bad for rho <= 0, p < 0 or a non-finite
+// value.  The CFL reduction and the fused epilogue of the last fluid
+// operator both call it, so they find the same maximum bit for bit.
+__device__ __forceinline__ void signal_speed64(double rho, double mx, double my, double mz, double e,
+                                               double bx0, double bx1, double by0, double by1, double bz0,
+                                               double bz1, double gamma, double& vmax, int& bad)
+{
+    const double bx = 0.5 * (bx0 + bx1);
+    const double by = 0.5 * (by0 + by1);
+    const double bz = 0.5 * (bz0 + bz1);
+    const double b2 = bx * bx + by * by + bz * bz;
+    const double mm = mx * mx + my * my + mz * mz;
+    const double p = (gamma - 1.0) * (e - 0.5 * mm / rho - 0.5 * b2);
+    const double vx = fabs(mx / rho), vy = fabs(my / rho), vz = fabs(mz / rho);
+    double vm = vx > vy ? vx : vy;
+    vm = vm > vz ? vm : vz;
+    const double sp = vm + sqrt((gamma * p + b2) / rho);
+    if (!(rho > 0.0) || !(p >= 0.0) || !isfinite(sp) || !isfinite(e) || !isfinite(mm) || !isfinite(b2))
+        bad = 1;
+    else if (sp > vmax)
+        vmax = sp;
+}
+
 }  // namespace mhd

@@ -12,6 +12,7 @@ enum { SCAL_DT = 0, SCAL_C = 1, SCAL_TIME = 2, SCAL_VMAX = 3, SCAL_COUNT = 4 };
 // CFL of mhd_step_auto, [1] number of such steps that ran, [2] result of the
 // synchronous CFL.
 enum { FLAG_NONPHYS = 0, FLAG_STEPS = 1, FLAG_SYNC = 2, FLAG_COUNT = 4 };
+constexpr int CFL_ACC_SLOTS = 256;     // fused-CFL maximum slots (+1 word for the flag)
 
 template <typename T>
 struct SweepParams {
@@ -21,6 +22,13 @@ struct SweepParams {
     T gamma;
     const double* scal;      // device scalar block (dt, relaxation speed)
     const int* flag;         // if *flag != 0 the operator copies in -> out
+    // fused CFL (x fluid operator only; null: off): the FP64 signal-speed
+    // maximum of the operator's output is accumulated in cfl_acc[0 ..
+    // CFL_ACC_SLOTS) (bits of the double, atomic max into the slot of the
+    // workgroup, spreading the atomics) and non-physical cells in
+    // cfl_acc[CFL_ACC_SLOTS]
+    unsigned long long* cfl_acc;
+    double gamma64;          // gamma in FP64 for that speed
 };
 
 // Launch shape choices of the march kernels: chunk length along y and z
@@ -80,6 +88,8 @@ hipError_t launch_batch_advance(double* scal, int* flag, int nbox, hipStream_t s
 template <typename T>
 hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s);
 template <typename T>
+bool fused_cfl_possible(int nx);
+template <typename T>
 hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s);
 
 // CFL: per-block maxima of the signal speed into partial[], then a final
@@ -91,6 +101,11 @@ hipError_t launch_cfl(const T* const f[8], int nx, int ny, int nz, double gamma,
                       double* partial, int* partial_bad, int nblocks, double* scal, int* flag,
                       hipStream_t s);
 int cfl_blocks(size_t ncell);
+// CFL from the maximum accumulated by the fused epilogue (then cleared), and
+// clearing the accumulator
+hipError_t launch_cfl_from_acc(unsigned long long* acc, int nx, double cfl, double* scal, int* flag,
+                               hipStream_t s);
+hipError_t launch_clear_acc(unsigned long long* acc, hipStream_t s);
 
 // Diagnostics: 8 field sums (FP64, fixed order), max |div b|, max |b|.
 template <typename T>

@@ -60,6 +60,12 @@ struct mhd_ctx {
     bool have_c;
     double c_host;
     bool scal_known;        // host knows what dt / c the device block holds
+    // fused CFL: the last fluid operator of a step leaves the FP64 maximum
+    // signal speed of the new state in cfl_acc; acc_valid while the state
+    // is still the one it describes
+    unsigned long long* cfl_acc;
+    bool acc_valid;
+    bool fuse_ok;           // grid shape allows the fused epilogue
     double scal_dt, scal_c;
     bool failed;
     LaunchTuning tune;
@@ -165,6 +171,7 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
               hipMalloc(&h->partial, npart * sizeof(double)) == hipSuccess &&
               hipMalloc(&h->partial_bad, h->nblk_cfl * sizeof(int)) == hipSuccess &&
               hipMalloc(&h->diag_out, 9 * sizeof(double)) == hipSuccess &&
+              hipMalloc(&h->cfl_acc, (CFL_ACC_SLOTS + 1) * sizeof(unsigned long long)) == hipSuccess &&
               hipHostMalloc(&h->pinned, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
@@ -176,6 +183,7 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
          hipMemsetAsync(h->buf[1], 0, bytes, h->stream) == hipSuccess &&
          hipMemsetAsync(h->scal, 0, SCAL_COUNT * sizeof(double), h->stream) == hipSuccess &&
          hipMemsetAsync(h->flag, 0, FLAG_COUNT * sizeof(int), h->stream) == hipSuccess &&
+         hipMemsetAsync(h->cfl_acc, 0, (CFL_ACC_SLOTS + 1) * sizeof(unsigned long long), h->stream) == hipSuccess &&
          hipStreamSynchronize(h->stream) == hipSuccess;
     if (!ok) {
         fail(MHD_EDEVICE, "device initialisation failed");
@@ -183,6 +191,8 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
         return nullptr;
     }
     default_tuning(h);
+    h->fuse_ok = prec == MHD_F64 ? fused_cfl_possible<double>(nx) : fused_cfl_possible<float>(nx);
+    h->acc_valid = false;
     return h;
 }
 
@@ -202,6 +212,7 @@ extern "C" void mhd_destroy(mhd_ctx* h)
     if (h->partial) (void)hipFree(h->partial);
     if (h->partial_bad) (void)hipFree(h->partial_bad);
     if (h->diag_out) (void)hipFree(h->diag_out);
+    if (h->cfl_acc) (void)hipFree(h->cfl_acc);
     if (h->pinned) (void)hipHostFree(h->pinned);
     delete h;
 }
@@ -220,6 +231,7 @@ extern "C" int mhd_info(const mhd_ctx* h, int dims[3], int* prec)
 
 static int reset_after_set(mhd_ctx* h)
 {
+    h->acc_valid = false;
     for (int q = 0; q < 8; ++q) h->cur[q] = 0;
     h->have_c = false;
     h->c_host = 0.0;
@@ -423,7 +435,7 @@ extern "C" int mhd_get_relaxation_speed(const mhd_ctx* hc, double* c)
 
 // op 0 = fluid, 1 = magnetic; flag (nullable): skip-and-copy switch
 template <typename T>
-static hipError_t enqueue_op(mhd_ctx* h, int op, int d, const int* flag)
+static hipError_t enqueue_op(mhd_ctx* h, int op, int d, const int* flag, unsigned long long* acc)
 {
     SweepParams<T> P;
     for (int q = 0; q < 8; ++q) {
@@ -434,6 +446,8 @@ static hipError_t enqueue_op(mhd_ctx* h, int op, int d, const int* flag)
     P.gamma = (T)h->gamma;
     P.scal = h->scal;
     P.flag = flag;
+    P.cfl_acc = acc;
+    P.gamma64 = h->gamma;
     hipError_t e = op == 0 ? launch_fluid<T>(P, d, h->tune, h->stream)
                            : launch_magnetic<T>(P, d, h->tune, h->stream);
     if (e == hipSuccess) {
@@ -445,9 +459,10 @@ static hipError_t enqueue_op(mhd_ctx* h, int op, int d, const int* flag)
     return e;
 }
 
-static hipError_t op(mhd_ctx* h, int o, int d, const int* flag)
+// acc (nullable, fluid along x only): fused CFL accumulator
+static hipError_t op(mhd_ctx* h, int o, int d, const int* flag, unsigned long long* acc = nullptr)
 {
-    return h->prec == MHD_F64 ? enqueue_op<double>(h, o, d, flag) : enqueue_op<float>(h, o, d, flag);
+    return h->prec == MHD_F64 ? enqueue_op<double>(h, o, d, flag, acc) : enqueue_op<float>(h, o, d, flag, acc);
 }
 
 static int check_dt(double dt)
@@ -479,6 +494,7 @@ extern "C" int mhd_fluid(mhd_ctx* h, int dim, double dt)
     if (dim < 0 || dim > 2) return fail(MHD_EINVAL, "dim must be 0, 1 or 2 (got %d)", dim);
     int r = prepare_host_dt(h, dt, true);
     if (r) return r;
+    h->acc_valid = false;
     HIP_TRY(h, op(h, 0, dim, nullptr));
     return MHD_OK;
 }
@@ -488,6 +504,7 @@ extern "C" int mhd_magnetic(mhd_ctx* h, int dim, double dt)
     if (dim < 0 || dim > 2) return fail(MHD_EINVAL, "dim must be 0, 1 or 2 (got %d)", dim);
     int r = prepare_host_dt(h, dt, false);
     if (r) return r;
+    h->acc_valid = false;
     HIP_TRY(h, op(h, 1, dim, nullptr));
     return MHD_OK;
 }
@@ -497,6 +514,7 @@ extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
     if (dim < 0 || dim > 5) return fail(MHD_EINVAL, "sweep code must be 0..5 (got %d)", dim);
     int r = prepare_host_dt(h, dt, true);
     if (r) return r;
+    h->acc_valid = false;
     const int d = dim % 3;
     if (dim < 3) {
         HIP_TRY(h, op(h, 0, d, nullptr));
@@ -509,8 +527,9 @@ extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
 }
 
 // the 12 operators of a full step: x, y, z forward (fluid, magnetic), then
-// z, y, x reverse (magnetic, fluid)
-static int enqueue_step_ops(mhd_ctx* h, const int* flag)
+// z, y, x reverse (magnetic, fluid).  acc (nullable): the last operator
+// (F_x) also accumulates the CFL maximum of the state it leaves.
+static int enqueue_step_ops(mhd_ctx* h, const int* flag, unsigned long long* acc)
 {
     for (int d = 0; d < 3; ++d) {
         HIP_TRY(h, op(h, 0, d, flag));
@@ -518,7 +537,7 @@ static int enqueue_step_ops(mhd_ctx* h, const int* flag)
     }
     for (int d = 2; d >= 0; --d) {
         HIP_TRY(h, op(h, 1, d, flag));
-        HIP_TRY(h, op(h, 0, d, flag));
+        HIP_TRY(h, op(h, 0, d, flag, d == 0 ? acc : nullptr));
     }
     return MHD_OK;
 }
@@ -527,8 +546,11 @@ extern "C" int mhd_step(mhd_ctx* h, double dt)
 {
     int r = prepare_host_dt(h, dt, true);
     if (r) return r;
-    if ((r = enqueue_step_ops(h, nullptr))) return r;
+    h->acc_valid = false;
+    if (h->fuse_ok) HIP_TRY(h, launch_clear_acc(h->cfl_acc, h->stream));
+    if ((r = enqueue_step_ops(h, nullptr, h->fuse_ok ? h->cfl_acc : nullptr))) return r;
     HIP_TRY(h, launch_advance_time(h->scal, nullptr, nullptr, h->stream));
+    h->acc_valid = h->fuse_ok;
     return MHD_OK;
 }
 
@@ -539,9 +561,18 @@ extern "C" int mhd_step_auto(mhd_ctx* h, double cfl)
     if (!(cfl > 0.0) || !isfinite(cfl)) return fail(MHD_EINVAL, "cfl must be > 0 (got %g)", cfl);
     HIP_TRY(h, hipSetDevice(h->device));
     h->scal_known = false;
-    HIP_TRY(h, h->prec == MHD_F64 ? enqueue_cfl<double>(h, cfl, h->flag + FLAG_NONPHYS)
-                                  : enqueue_cfl<float>(h, cfl, h->flag + FLAG_NONPHYS));
-    if ((r = enqueue_step_ops(h, h->flag + FLAG_NONPHYS))) return r;
+    if (h->acc_valid) {
+        // the previous step's last operator already found this state's
+        // largest signal speed (same FP64 expression, same maximum)
+        HIP_TRY(h, launch_cfl_from_acc(h->cfl_acc, h->n[0], cfl, h->scal, h->flag + FLAG_NONPHYS, h->stream));
+    } else {
+        HIP_TRY(h, h->prec == MHD_F64 ? enqueue_cfl<double>(h, cfl, h->flag + FLAG_NONPHYS)
+                                      : enqueue_cfl<float>(h, cfl, h->flag + FLAG_NONPHYS));
+        if (h->fuse_ok) HIP_TRY(h, launch_clear_acc(h->cfl_acc, h->stream));
+    }
+    h->acc_valid = false;
+    if ((r = enqueue_step_ops(h, h->flag + FLAG_NONPHYS, h->fuse_ok ? h->cfl_acc : nullptr))) return r;
+    h->acc_valid = h->fuse_ok;
     HIP_TRY(h, launch_advance_time(h->scal, h->flag + FLAG_NONPHYS, h->flag + FLAG_STEPS, h->stream));
     // the device CFL also set the relaxation speed; it stays on the device
     // (c_host < 0 marks that) until read back
@@ -682,6 +713,11 @@ void* mhd_internal_state(mhd_ctx* h, int* all_in_first_buffer)
 int mhd_internal_prec(const mhd_ctx* h) { return h->prec; }
 void mhd_internal_dims(const mhd_ctx* h, int n[3]) { n[0] = h->n[0]; n[1] = h->n[1]; n[2] = h->n[2]; }
 hipStream_t mhd_internal_stream(const mhd_ctx* h) { return h->stream; }
+void mhd_internal_state_changed(mhd_ctx* h)
+{
+    h->acc_valid = false;
+}
+
 double mhd_internal_gamma(const mhd_ctx* h) { return h->gamma; }
 
 extern "C" const char* mhd_last_error(void)

@@ -9,6 +9,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "mhd_device.h"
 #include "mhd_kernels.h"
 
 namespace mhd {
@@ -60,24 +61,9 @@ __device__ __forceinline__ void cell_signal_speed(const T* const* f, size_t c, i
     const size_t cx = i + 1 == nx ? c - (nx - 1) : c + 1;
     const size_t cy = j + 1 == ny ? c - (ny - 1) * sy : c + sy;
     const size_t cz = k + 1 == nz ? c - (size_t)(nz - 1) * sz : c + sz;
-    const double rho = (double)f[0][c];
-    const double mx = (double)f[1][c], my = (double)f[2][c], mz = (double)f[3][c];
-    const double e = (double)f[4][c];
-    const double bx = 0.5 * ((double)f[5][c] + (double)f[5][cx]);
-    const double by = 0.5 * ((double)f[6][c] + (double)f[6][cy]);
-    const double bz = 0.5 * ((double)f[7][c] + (double)f[7][cz]);
-    const double b2 = bx * bx + by * by + bz * bz;
-    const double mm = mx * mx + my * my + mz * mz;
-    const double p = (gamma - 1.0) * (e - 0.5 * mm / rho - 0.5 * b2);
-    const double vx = fabs(mx / rho), vy = fabs(my / rho), vz = fabs(mz / rho);
-    double vm = vx > vy ? vx : vy;
-    vm = vm > vz ? vm : vz;
-    const double sp = vm + sqrt((gamma * p + b2) / rho);
-    if (!(rho > 0.0) || !(p >= 0.0) || !isfinite(sp) || !isfinite(e) || !isfinite(mm) ||
-        !isfinite(b2))
-        bad = 1;
-    else if (sp > vmax)
-        vmax = sp;
+    signal_speed64((double)f[0][c], (double)f[1][c], (double)f[2][c], (double)f[3][c], (double)f[4][c],
+                   (double)f[5][c], (double)f[5][cx], (double)f[6][c], (double)f[6][cy], (double)f[7][c],
+                   (double)f[7][cz], gamma, vmax, bad);
 }
 
 // per-block maximum and non-physical flag of the signal speed
@@ -163,6 +149,56 @@ template hipError_t launch_cfl<float>(const float* const[8], int, int, int, doub
                                       double*, int*, int, double*, int*, hipStream_t);
 template hipError_t launch_cfl<double>(const double* const[8], int, int, int, double, double,
                                        double*, int*, int, double*, int*, hipStream_t);
+
+// The CFL from the maximum that the fused epilogue of the previous step's
+// last fluid operator accumulated (acc[0 .. CFL_ACC_SLOTS): bits of FP64
+// maxima, acc[CFL_ACC_SLOTS]: non-physical flag); the same dt / relaxation
+// speed / flag rules as cfl_final_kernel.  Clears acc for the next
+// accumulation.  One block of CFL_ACC_SLOTS threads.
+__global__ void __launch_bounds__(CFL_ACC_SLOTS) cfl_from_acc_kernel(unsigned long long* acc, int nx, double cfl,
+                                                                     double* scal, int* flag)
+{
+    double m = __longlong_as_double((long long)acc[threadIdx.x]);
+    m = wave_max(m);
+    __shared__ double smax[CFL_ACC_SLOTS / 64];
+    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double vmax = smax[0];
+        for (int q = 1; q < CFL_ACC_SLOTS / 64; ++q) vmax = fmax(vmax, smax[q]);
+        const int b = (int)acc[CFL_ACC_SLOTS];
+        if (b || !(vmax > 0.0)) {
+            scal[SCAL_DT] = 0.0;
+            scal[SCAL_VMAX] = 0.0;
+            flag[0] = b ? 1 : 2;
+        } else {
+            scal[SCAL_DT] = cfl * (1.0 / (double)nx) / vmax;
+            scal[SCAL_VMAX] = vmax;
+            scal[SCAL_C] = vmax;
+        }
+        acc[CFL_ACC_SLOTS] = 0;
+    }
+    acc[threadIdx.x] = 0;
+}
+
+hipError_t launch_cfl_from_acc(unsigned long long* acc, int nx, double cfl, double* scal, int* flag,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(cfl_from_acc_kernel, dim3(1), dim3(CFL_ACC_SLOTS), 0, s, acc, nx, cfl, scal, flag);
+    return hipGetLastError();
+}
+
+__global__ void clear_acc_kernel(unsigned long long* acc)
+{
+    acc[threadIdx.x] = 0;
+    if (threadIdx.x == 0) acc[CFL_ACC_SLOTS] = 0;
+}
+
+hipError_t launch_clear_acc(unsigned long long* acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(clear_acc_kernel, dim3(1), dim3(CFL_ACC_SLOTS), 0, s, acc);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Per-box CFL of a batched ensemble

@@ -22,3 +22,4 @@ int mhd_internal_prec(const mhd_ctx* h);
 void mhd_internal_dims(const mhd_ctx* h, int n[3]);
 hipStream_t mhd_internal_stream(const mhd_ctx* h);
 double mhd_internal_gamma(const mhd_ctx* h);
+void mhd_internal_state_changed(mhd_ctx* h);   // the state was modified outside the operators

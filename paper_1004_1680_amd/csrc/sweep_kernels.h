@@ -87,7 +87,10 @@ __device__ __forceinline__ void step_scalars(const SweepParams<T>& P, T& tau, T&
 
 // One tile of rows_per_wg rows of one grid; every thread of the workgroup
 // calls it (it holds barriers).  Threads beyond rows_per_wg * tpr idle.
-template <typename T>
+// CFL = true: also the fused CFL epilogue (FP64 signal speed of every output
+// cell, maximum per wave, atomic maximum into P.cfl_acc); needs full waves
+// (blockDim.x a multiple of 64).
+template <typename T, bool CFL = false>
 __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
                                              int rows_per_wg, T* const A)
 {
@@ -116,6 +119,8 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
                 vec4<T>::load(P.in[f] + base + i0, v);
                 vec4<T>::store(P.out[f] + base + i0, v);
             }
+        if constexpr (CFL)
+            if (threadIdx.x == 0) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, 1ull);
         return;
     }
 
@@ -124,6 +129,7 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
     const T gamma = P.gamma;
 
     T u[4][5], bb[4][3];
+    double fb[CFL ? 4 : 1][6];    // fused CFL: raw face values (own, next) of b_x, b_y, b_z
     {
         T tmp[4], tmp2[4];
         for (int q = 0; q < 5; ++q) {
@@ -140,15 +146,24 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
         } else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) bb[k][0] = T(0.5) * (tmp[k] + (k < 3 ? tmp[k + 1] : bxn));
+        if constexpr (CFL)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { fb[k][0] = (double)tmp[k]; fb[k][1] = (double)(k < 3 ? tmp[k + 1] : bxn); }
         // Bbar_y: faces at y and y+1; Bbar_z: faces at z and z+1
         if (active) { vec4<T>::load(P.in[BY] + base + i0, tmp); vec4<T>::load(P.in[BY] + base_yp + i0, tmp2); }
         else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) bb[k][1] = T(0.5) * (tmp[k] + tmp2[k]);
+        if constexpr (CFL)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { fb[k][2] = (double)tmp[k]; fb[k][3] = (double)tmp2[k]; }
         if (active) { vec4<T>::load(P.in[BZ] + base + i0, tmp); vec4<T>::load(P.in[BZ] + base_zp + i0, tmp2); }
         else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) bb[k][2] = T(0.5) * (tmp[k] + tmp2[k]);
+        if constexpr (CFL)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { fb[k][4] = (double)tmp[k]; fb[k][5] = (double)tmp2[k]; }
     }
 
     // stage 1: relaxed split and first-order upwind interface fluxes
@@ -213,22 +228,54 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
 #pragma unroll
     for (int q = 0; q < 5; ++q) B[q * nt + t] = phi[3][q];
     __syncthreads();
-    if (!active) return;
+    if constexpr (!CFL) {
+        if (!active) return;
+    }
+    T onew[CFL ? 4 : 1][5];
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const T phiprev = B[q * nt + tprev];
-        T o[4];
+        for (int q = 0; q < 5; ++q) {
+            const T phiprev = B[q * nt + tprev];
+            T o[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = sub_scaled(u[k][q], tau, phi[k][q] - (k > 0 ? phi[k - 1][q] : phiprev));
-        vec4<T>::store(P.out[q] + base + i0, o);
+            for (int k = 0; k < 4; ++k) o[k] = sub_scaled(u[k][q], tau, phi[k][q] - (k > 0 ? phi[k - 1][q] : phiprev));
+            vec4<T>::store(P.out[q] + base + i0, o);
+            if constexpr (CFL)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) onew[k][q] = o[k];
+        }
+    }
+    if constexpr (CFL) {
+        // the CFL of the state this operator leaves (the last of a step),
+        // from the values as stored; every lane of the wave takes part
+        double vmax = 0.0;
+        int bad = 0;
+        if (active)
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                signal_speed64((double)onew[k][0], (double)onew[k][1], (double)onew[k][2], (double)onew[k][3],
+                               (double)onew[k][4], fb[k][0], fb[k][1], fb[k][2], fb[k][3], fb[k][4], fb[k][5],
+                               P.gamma64, vmax, bad);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
+            bad |= __shfl_xor(bad, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            // a non-negative double orders like its bit pattern
+            if (vmax > 0.0)
+                atomicMax(P.cfl_acc + (blockIdx.x & (CFL_ACC_SLOTS - 1)),
+                          (unsigned long long)__double_as_longlong(vmax));
+            if (bad) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, 1ull);
+        }
     }
 }
 
-template <typename T>
+template <typename T, bool CFL>
 __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fluid_x_tile(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    fluid_x_tile<T, CFL>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // Magnetic sweep along x: e = y then z.  For each e two edge-flux chains
@@ -710,6 +757,15 @@ inline void row_shape(int nx, int& tpr, int& rows_per_wg, int& threads)
     threads = rows_per_wg * tpr;
 }
 
+// the fused CFL epilogue needs the x fluid kernel's workgroups to be whole waves
+template <typename T>
+bool fused_cfl_possible(int nx)
+{
+    int tpr, rpw, threads;
+    row_shape<T>(nx, tpr, rpw, threads);
+    return threads % 64 == 0;
+}
+
 template <typename T>
 hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
@@ -719,7 +775,12 @@ hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune
         const int nrows = P.ny * P.nz;
         const int grid = (nrows + rpw - 1) / rpw;
         const size_t lds = sizeof(T) * 25 * threads;
-        hipLaunchKernelGGL(fluid_x_kernel<T>, dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+        if (P.cfl_acc) {
+            if (threads % 64) return hipErrorInvalidValue;      // fused CFL needs full waves
+            hipLaunchKernelGGL((fluid_x_kernel<T, true>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+        } else {
+            hipLaunchKernelGGL((fluid_x_kernel<T, false>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+        }
     } else {
         const int nd = d == 1 ? P.ny : P.nz;
         const int npencil = P.nx * (d == 1 ? P.nz : P.ny);
@@ -783,6 +844,8 @@ __device__ __forceinline__ SweepParams<T> box_params(const BatchParams<T>& B, in
     P.gamma = B.gamma;
     P.scal = B.scal + (size_t)box * SCAL_COUNT;
     P.flag = B.flag ? B.flag + (size_t)box * FLAG_COUNT : nullptr;
+    P.cfl_acc = nullptr;
+    P.gamma64 = 0.0;
     return P;
 }
 

@@ -287,6 +287,68 @@ def test_step_auto_matches_host_path(M, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_cfl_follows_state_changes(M, prec):
+    """step_auto takes the CFL of a step from the previous step's last
+    operator while the state is unchanged, and recomputes it after a single
+    operator or a new state: every step equals the host path (cfl_dt + step)
+    bit for bit"""
+    n = (32, 32, 32)
+    say(f"case: fused CFL and state changes {prec}")
+    s1 = I.random_smooth(n, seed=4)
+    s2 = I.random_smooth(n, seed=5)
+    A = M.Solver(n, prec=prec)
+    B = M.Solver(n, prec=prec)
+    A.set_state(s1)
+    B.set_state(s1)
+    for _ in range(3):
+        A.step_auto(0.7)
+        dtb = B.cfl_dt(0.7)
+        B.step(dtb)
+    # a single operator (both with the relaxation speed of the last CFL):
+    # the fused CFL of A is stale afterwards
+    dt = 0.3 * dtb
+    A.fluid(1, dt)
+    B.fluid(1, dt)
+    for _ in range(2):
+        A.step_auto(0.7)
+        B.step(B.cfl_dt(0.7))
+    assert np.array_equal(A.get_state(), B.get_state())
+    A.set_state(s2)
+    B.set_state(s2)
+    for _ in range(3):
+        A.step_auto(0.7)
+        B.step(B.cfl_dt(0.7))
+    A.status()
+    assert np.array_equal(A.get_state(), B.get_state())
+    assert A.time() == B.time()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_cfl_carries_a_nonphysical_record(M, prec):
+    """a non-physical state stops every step; the record survives the
+    fused-CFL hand-over between steps, and a new state clears the path"""
+    n = (32, 32, 32)
+    say(f"case: fused CFL non-physical record {prec}")
+    s = I.random_smooth(n, seed=6)
+    bad = s.copy()
+    bad[4, 3, 5, 7] = -1.0          # negative energy: p < 0
+    S = M.Solver(n, prec=prec)
+    S.set_state(bad)
+    before = S.get_state()
+    for _ in range(3):
+        S.step_auto(0.7)
+    with pytest.raises(M.NonPhysicalState):
+        S.status()
+    assert np.array_equal(S.get_state(), before)
+    S.set_state(s)
+    host, _, _ = gpu_run(M, s, n, prec, 2)
+    for _ in range(2):
+        S.step_auto(0.7)
+    assert S.status() == 2
+    assert np.array_equal(S.get_state(), host)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_restriction_parity(M, prec):
     say(f"case: restrict {prec}")
     nf, r = (64, 32, 32), 4
