@@ -318,6 +318,7 @@ def main():
     ap.add_argument("--cfl", type=float, default=0.7)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in march chunks")
     ap.add_argument("--closure-weights", default=None, help="trained closure (.npz) for closure128")
     ap.add_argument("--closure-eval", action="store_true",
                     help="closure128: also evaluate learned vs plain against the 1024^3 solution")
@@ -347,6 +348,10 @@ def main():
     S.set_state_tensor(st)
     del st
     torch.cuda.synchronize()
+    if not args.no_tune:
+        from paper_1004_1680_amd import autotune
+        chunks = autotune.tune_solver(S, args.cfl, use_cache=False)
+        log(f"[bench] autotuned march chunks (y, z): {chunks[1]}, {chunks[2]}")
     log("[bench] state resident; warm-up")
 
     for _ in range(args.warmup):
@@ -426,6 +431,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "grid": [n, n, n], "cfl": args.cfl,
                    "step": "CFL (FP64) + F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x",
+                   "march_chunks": [S.chunk(1), S.chunk(2)],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
