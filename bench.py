@@ -409,8 +409,8 @@ def main():
         tpath = os.path.join(ROOT, "profiles", f"sweeps_{args.workload}_hbm_traffic.md")
     from paper_1004_1680_amd.profile_summary import read_traffic
     tmap = read_traffic(tpath)
-    tname = {"x": "{op}_x_kernel<{t}>", "y": "{op}_march_kernel<{t}, 1>",
-             "z": "{op}_march_kernel<{t}, 2>"}[dom[-1]].format(
+    tname = {"x": "fluid_x_kernel<{t}, false>" if op == "fluid" else "mag_x_kernel<{t}>",
+             "y": "{op}_march_kernel<{t}, 1>", "z": "{op}_march_kernel<{t}, 2>"}[dom[-1]].format(
         op="fluid" if op == "fluid" else "mag", t="double" if esize == 8 else "float")
     if tname in tmap:
         traffic = tmap[tname]

@@ -95,15 +95,22 @@ hipError_t launch_pack_weights(const float* w, int cin, int cout, int flip, uint
 
 // Output tile of a workgroup: 16 (x) x 4 (y) x 4 (z) cells; wave w takes
 // the z plane w, its 4 MFMA column blocks the 4 rows y, lane r the cell x.
-// The input halo (18 x 6 x 6 cells, periodic) is staged once in LDS with a
-// cell stride of CIN + 8 bf16 for CIN = 32 (80 bytes: the 16-byte reads of
-// 16 consecutive cells then spread over all banks), and every one of the 27
-// offsets reads its B fragments from there.
+// The input halo (18 x 6 x 6 cells, periodic) is staged once in LDS and
+// every one of the 27 offsets reads its B fragments from there.  A B read
+// has 16 lanes on 16 consecutive cells reading the same 16-byte chunk; with
+// 64-byte cells (CIN = 32) the chunks of cells h and h + 4 would share
+// banks, so chunk q of cell h is stored at position q ^ 2 ((h >> 2) & 1):
+// any 8 consecutive cells then fall on distinct bank groups (measured on
+// gfx950: a lane stride that is an odd multiple of 32 bytes modulo 256, or
+// this swizzle, is conflict-free; 64 or 80 bytes costs two passes).
 constexpr int CT_X = 16, CT_Y = 4, CT_Z = 4;
 constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2, CH_CELLS = CH_X * CH_Y * CH_Z;
 
 template <int CIN>
-__host__ __device__ constexpr int conv_cell_stride() { return CIN == 8 ? 8 : CIN + 8; }
+__host__ __device__ constexpr int conv_cell_stride() { return CIN; }
+// position (in 8-bf16 chunks) of chunk q of halo cell h
+template <int CIN>
+__device__ __forceinline__ int conv_chunk(int h, int q) { return CIN == 32 ? (q ^ (((h >> 2) & 1) << 1)) : q; }
 
 template <int CIN, int COUT, int EPI>
 __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
@@ -148,7 +155,7 @@ __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
         const int t = threadIdx.x + 256 * f;
         if (t < CH_CELLS * PARTS) {
             const int h = t / PARTS, q = t % PARTS;
-            *reinterpret_cast<uint4*>(tile + h * CS + 8 * q) = fv[f];
+            *reinterpret_cast<uint4*>(tile + h * CS + 8 * conv_chunk<CIN>(h, q)) = fv[f];
         }
     }
     __syncthreads();
@@ -175,7 +182,8 @@ __global__ void __launch_bounds__(256) conv3d_kernel(ConvArgs A)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (o < 27) v = *reinterpret_cast<const uint4*>(tile + (h0 + nb * CH_X) * CS + c0);
+            const int h = h0 + nb * CH_X;
+            if (o < 27) v = *reinterpret_cast<const uint4*>(tile + h * CS + 8 * conv_chunk<CIN>(h, c0 / 8));
             bv[nb] = as_bf8(v);
         }
     };
@@ -300,10 +308,12 @@ template <int CI, int CO>
 __global__ void __launch_bounds__(576) conv3d_wgrad_kernel(WgradArgs A)
 {
     constexpr int MB = (CO + 15) / 16, NBI = (CI + 15) / 16;
-    constexpr int KSTEPS = WT_Y * WT_Z, DYS = KSTEPS * WT_X + 8;   // dy row of a channel, padded
-    // x channel stride padded by 8 bf16: the 16 channels of a fragment read
-    // then start 4 banks apart instead of on the same bank
-    constexpr int XCS = WL_Z * WL_Y * WL_X + 8;
+    // channel strides of the dy rows and of the x tile padded to an odd
+    // multiple of 32 bytes modulo 256: the 16 channels of a fragment read
+    // are then conflict-free (measured; an unpadded 2304-byte stride costs
+    // 8 passes, a 16-byte pad 2)
+    constexpr int KSTEPS = WT_Y * WT_Z, DYS = KSTEPS * WT_X + 16;
+    constexpr int XCS = WL_Z * WL_Y * WL_X + 16;
     __shared__ __align__(16) uint16_t xs[CI * XCS];
     __shared__ __align__(16) uint16_t dys[CO * DYS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

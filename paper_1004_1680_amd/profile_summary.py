@@ -4,6 +4,9 @@
   python -m paper_1004_1680_amd.profile_summary traffic <fetch.csv> <write.csv> <ncell> <esize> <command...>
 
 ``stats`` prints a per-kernel table (calls, average / min / max duration).
+``counters`` turns two ``rocprofv3 --pmc`` runs of SQ counters and a kernel
+trace into a per-kernel table for the MFMA kernels: MFMA-busy fraction of
+the kernel's SIMD-cycles and LDS bank-conflict cycles per LDS-active cycle.
 ``traffic`` turns the FETCH_SIZE and WRITE_SIZE counters (KiB per dispatch)
 of two ``rocprofv3 --pmc`` runs into HBM bytes per launch, scaled by what
 the same counters read for the plain 1 GiB copy that ``bench.py
@@ -90,6 +93,34 @@ def traffic(fetch_csv, write_csv, ncell, esize, command):
     return "\n".join(out)
 
 
+SIMDS, CLOCK_HZ = 1024, 2.4e9     # MI355X: 256 CUs x 4 SIMDs
+
+
+def counters(pmc1_csv, pmc2_csv, stats_csv, command):
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in (pmc1_csv, pmc2_csv):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                vals[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    dur = {}
+    with open(stats_csv) as f:
+        for r in csv.DictReader(f):
+            dur[short(r["Name"])] = float(r["AverageNs"]) * 1e-9
+    out = [f"command: {command}", "",
+           "| kernel | MFMA busy / SIMD-cycles | LDS bank-conflict / LDS-active cycles | VALU insts / wave | LDS insts / wave |",
+           "|---|---|---|---|---|"]
+    for k in sorted(vals):
+        v = {c: sum(x) / len(x) for c, x in vals[k].items()}
+        if not v.get("SQ_VALU_MFMA_BUSY_CYCLES") or k not in dur:
+            continue
+        busy = v["SQ_VALU_MFMA_BUSY_CYCLES"] / (dur[k] * CLOCK_HZ * SIMDS)
+        conf = v.get("SQ_LDS_BANK_CONFLICT", 0.0) / max(v.get("SQ_LDS_IDX_ACTIVE", 0.0), 1.0)
+        waves = max(v.get("SQ_WAVES", 1.0), 1.0)
+        out.append(f"| {k} | {busy:.3f} | {conf:.3f} | {v.get('SQ_INSTS_VALU', 0.0) / waves:.0f} | "
+                   f"{v.get('SQ_INSTS_LDS', 0.0) / waves:.0f} |")
+    return "\n".join(out)
+
+
 def read_traffic(path):
     """{kernel: bytes per launch} from a traffic summary, or {} if the kernel
     sources have changed since it was written"""
@@ -114,5 +145,7 @@ if __name__ == "__main__":
     elif mode == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5]),
                       " ".join(sys.argv[6:])))
+    elif mode == "counters":
+        print(counters(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:])))
     elif mode == "hash":
         print(source_hash())
