@@ -152,3 +152,40 @@ def test_batch_rejects_bad_arguments(M):
         B.set_launch(99, 8)
     with pytest.raises(ValueError):
         B.set_state(0, np.zeros((8, 8, 8, 8)))
+
+
+def test_benchmark_ensemble_sampled_boxes(M):
+    """the benchmark's ensemble (64 boxes of {32..256}^3, 312 M cells) in its
+    launch configuration (persistent launches, graph replay): sampled boxes
+    (the smallest, the largest, one in between) equal single-grid handles
+    of the same box bit for bit after two steps"""
+    from paper_1004_1680_amd import inputs as I
+    say("case: benchmark ensemble, sampled boxes")
+    spec = I.ensemble_spec(nbox=64, seed=4)
+    dims = [(n, n, n) for n, _, _, _ in spec]
+    B = M.Batch(dims, prec="f32")
+    keep = {}
+    sizes = [n for n, _, _, _ in spec]
+    picks = {sizes.index(min(sizes)), sizes.index(max(sizes)), len(spec) // 2}
+    for i, (n, m, b, sd) in enumerate(spec):
+        s = I.turbulence((n, n, n), seed=sd, mach=m, beta=b)
+        B.set_state(i, s)
+        if i in picks:
+            keep[i] = s
+    say("boxes resident; cells", B.ncell)
+    B.run(2, graph=True)
+    steps, nonphys = B.status(raise_on_nonphysical=False)
+    for i, s in keep.items():
+        n = dims[i]
+        S = M.Solver(n, prec="f32")
+        S.set_state(s)
+        say("box", i, n, "steps", int(steps[i]), "record", int(nonphys[i]))
+        if nonphys[i]:
+            with pytest.raises(M.NonPhysicalState):   # the single grid stops too
+                S.run(2)
+        else:
+            S.run(2)
+            assert steps[i] == 2
+            assert np.array_equal(B.get_state(i), S.get_state()), i
+        S.close()
+    B.close()

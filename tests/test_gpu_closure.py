@@ -347,3 +347,34 @@ def test_gated_network_forward_and_gradient_parity(env):
     d0 = cl.forward(ud).cpu().numpy().reshape(8, -1)
     ref0 = C.forward(x, psr, osc, N3)
     assert np.linalg.norm(d0 - ref0) / np.linalg.norm(ref0) < 3e-2
+
+
+def test_consecutive_learned_steps_take_the_cfl_of_the_corrected_state(env):
+    """a learned step changes the state after the plain step, so the next
+    step cannot use the CFL maximum the plain step's last operator found:
+    two learned steps in a row equal one learned step, a reload of its
+    result into a fresh handle, and a second learned step, bit for bit"""
+    torch, mhd = env
+    say("case: closure steps and the fused CFL")
+    n = N3
+    s = I.random_smooth(n, seed=12)
+    prob = closure_problem(seed=2)
+    stream = torch.cuda.current_stream()
+    cl = mhd.Closure(n, stream=stream)
+    cl.set_params(C.flatten(C.init_params(3)).astype(np.float32))
+    cl.set_scales(prob[1], prob[2], np.full(8, 3e-3, dtype=np.float32), np.ones(8))
+    A = mhd.Solver(n, prec="f32", stream=stream)
+    A.set_state(s)
+    cl.step(A)
+    cl.step(A)
+    B = mhd.Solver(n, prec="f32", stream=stream)
+    B.set_state(s)
+    cl.step(B)
+    mid = B.get_state_tensor().clone()
+    Bb = mhd.Solver(n, prec="f32", stream=stream)
+    Bb.set_state_tensor(mid)
+    cl.step(Bb)
+    assert cl.fallbacks() == 0
+    a, b = A.get_state(), Bb.get_state()
+    assert not np.array_equal(a, mid.cpu().numpy())
+    assert np.array_equal(a, b)

@@ -9,7 +9,7 @@ since the scheme's grid spacing is 1 / nx), and the 8^3 interior of each
 window must equal the full-grid result (checked exactly for the oracle
 against its own full-grid step in test_window_margin_is_exact below, on the
 CPU).  Interiors are compared with the FP32 tolerance of the other tests
-(1e-5 of each field family's largest magnitude in the samples).  Windows
+(1e-5 of each field family's largest magnitude in the samples; 1e-12 for the FP64 tier).  Windows
 include ones that wrap around the periodic boundary.  Properties that hold
 at any size are checked on the whole grid: conserved totals (FP64 sums) and
 div b."""
@@ -40,17 +40,20 @@ def cut(a, idx):
     return a[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]]
 
 
+TOL = {"f32": 1e-5, "f64": 1e-12}
+
+
 @pytest.mark.gpu
-@pytest.mark.parametrize("n", [512, 1024])
-def test_full_size_sampled_parity(n):
+@pytest.mark.parametrize("n,prec", [(512, "f32"), (1024, "f32"), (512, "f64")])
+def test_full_size_sampled_parity(n, prec):
     import torch
     from paper_1004_1680_amd import mhd
     mhd.load()
-    say(f"case: {n}^3 FP32 Orszag-Tang, one step, sampled windows")
+    say(f"case: {n}^3 {prec} Orszag-Tang, one step, sampled windows")
     N = (n, n, n)
     stream = torch.cuda.current_stream()
-    S = mhd.Solver(N, prec="f32", stream=stream)
-    u0 = I.orszag_tang_torch(N, seed=0)
+    S = mhd.Solver(N, prec=prec, stream=stream)
+    u0 = I.orszag_tang_torch(N, seed=0, dtype=torch.float64 if prec == "f64" else torch.float32)
     S.set_state_tensor(u0)
     d0 = S.diag()
     dt = S.cfl_dt(0.7)
@@ -77,7 +80,7 @@ def test_full_size_sampled_parity(n):
             scale[q] = max(scale[q], np.abs(b[fam]).max())
     rel = err / scale
     say("family rel err (rho, m, e, b)", rel)
-    assert np.all(rel <= 1e-5)
+    assert np.all(rel <= TOL[prec])
     # whole-grid properties: totals to FP32 rounding, div b stays at rounding
     tot_rel = np.abs(d1[:8] - d0[:8]) / np.maximum(np.abs(d0[:8]), 1e-30)
     say("total changes", tot_rel[:5], "div b", d0[8], d1[8])
