@@ -63,23 +63,63 @@ def advance_to(S, t_end, cfl=0.7, t0=0.0, log=None, every=200):
     return k
 
 
+class PairSet:
+    """Training pairs of one coarse grid, kept as (u_c, u_ref, dt, c): the
+    restricted fine state at t, the restricted fine state at t + 2 dt and
+    the coarse step's dt and relaxation speed (half the memory of storing
+    the plain step as well).  pair(i) runs the plain coarse step (library
+    step on the device) and returns (u_plain, target = u_ref - u_plain,
+    residual kernel)."""
+
+    def __init__(self, cl, nc, stream):
+        self.cl = cl
+        self.C = mhd.Solver((nc,) * 3, prec="f32", stream=stream)
+        self.items = []
+
+    def add(self, u_c, u_ref, dt, c):
+        self.items.append((u_c, u_ref, dt, c))
+
+    def pair(self, i):
+        u_c, u_ref, dt, c = self.items[i]
+        self.C.set_state_tensor(u_c)
+        self.C.set_relaxation_speed(c)
+        self.C.step(dt)
+        u_plain = self.C.get_state_tensor()
+        return u_plain, self.cl.residual(u_ref, u_plain)
+
+    def __len__(self):
+        return len(self.items)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self.pair(j) for j in range(*i.indices(len(self)))]
+        return self.pair(i)
+
+    def __iter__(self):
+        for i in range(len(self)):
+            yield self.pair(i)
+
+    def extend(self, other):
+        self.items.extend(other.items)
+
+
 def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print):
-    """(u_plain, target) device tensor pairs from fine trajectories of the
-    Orszag-Tang family (one per seed); cl: the Closure of the coarse grid,
-    whose residual kernel forms the targets"""
+    """training pairs from fine trajectories of the Orszag-Tang family (one
+    per seed), as a PairSet; cl: the Closure of the coarse grid, whose
+    residual kernel forms the targets"""
     nc = nf // r
     F = mhd.Solver((nf,) * 3, prec="f32", stream=stream)
     C = mhd.Solver((nc,) * 3, prec="f32", stream=stream)
-    pairs = []
+    pairs = PairSet(cl, nc, stream)
     for sd in seeds:
         F.set_state_tensor(I.orszag_tang_torch((nf,) * 3, seed=sd))
         t = 0.0
         for k in range(steps_per_traj):
             try:
                 F.restrict_to(C)
+                u_c = C.get_state_tensor().clone()
                 dtc = C.cfl_dt(cfl)
-                C.step(dtc)
-                u_plain = C.get_state_tensor().clone()
+                c = C.relaxation_speed()
                 nfine = advance_to(F, t + 2.0 * dtc, cfl, t0=t)
             except mhd.NonPhysicalState as e:
                 # the plain scheme does not guarantee positivity: the
@@ -88,8 +128,7 @@ def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print)
                 break
             t += 2.0 * dtc
             F.restrict_to(C)
-            target = cl.residual(C.get_state_tensor(), u_plain)
-            pairs.append((u_plain, target))
+            pairs.add(u_c, C.get_state_tensor().clone(), dtc, c)
             if k % 8 == 0:
                 log(f"[closure] seed {sd} coarse step {k}: dt_c {dtc:.3e}, {nfine} fine steps")
     F.close()
@@ -210,7 +249,8 @@ def train(cl, pairs, val, epochs, lr, log=print, seed=0, lr_min_frac=0.05, scale
             if weighting != "global":
                 set_ts(ps[i])
             f = 0.5 * (1.0 + np.cos(np.pi * step / total))
-            tr.append(cl.train_step(pairs[i][0], pairs[i][1], lr * (lr_min_frac + (1 - lr_min_frac) * f)))
+            u, t = pairs[i]
+            tr.append(cl.train_step(u, t, lr * (lr_min_frac + (1 - lr_min_frac) * f)))
             step += 1
         vl = []
         for j, (u, t) in enumerate(val or []):
@@ -420,7 +460,7 @@ def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, st
     t0 = time.perf_counter()
     pairs = generate_pairs(cl, nf, r, train_seeds, steps_per_traj, stream, cfl, log)
     if short_seeds and short_steps:
-        pairs += generate_pairs(cl, nf, r, short_seeds, short_steps, stream, cfl, log)
+        pairs.extend(generate_pairs(cl, nf, r, short_seeds, short_steps, stream, cfl, log))
     val = generate_pairs(cl, nf, r, (val_seed,), val_steps or steps_per_traj, stream, cfl, log)
     _sync(torch)
     t_data = time.perf_counter() - t0
