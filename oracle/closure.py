@@ -6,9 +6,8 @@ conservative projection (mean-free fluid corrections, discrete curl of an
 edge potential for b) -> delta, and u = u_plain + delta.  Convolutions are
 periodic 3x3x3 with channel-last activations; the loss is the mean squared
 error of delta against the target correction, each channel divided by its
-target scale.  The network output is bounded, tanh(o), and with a
-roughness gate g(u) (gate()) the projection acts on g * tanh(o), cell by
-cell, so no correction exceeds its scale times the local roughness.  Everything here is plain FP64 (C loops in
+target scale.  With a roughness gate g(u) (gate()), the projection acts on
+g * o, cell by cell.  Everything here is plain FP64 (C loops in
 closure_oracle.c, composed in numpy).
 """
 import ctypes
@@ -115,8 +114,7 @@ def forward(x, ps, scale, n, keep=False, g=None):
     z2 = conv3d(a1, w2, b2, n)
     a2 = np.maximum(z2, 0.0)
     o = conv3d(a2, w3, b3, n)
-    th = np.tanh(o)
-    d = project(th if g is None else th * g[:, None], scale, n)
+    d = project(o if g is None else o * g[:, None], scale, n)
     if keep:
         return d, (x, a1, a2, o)
     return d
@@ -132,7 +130,6 @@ def loss_and_grad(x, ps, scale, target, tscale, n, g=None):
     go = project_T(gd, scale, n)
     if g is not None:
         go = go * g[:, None]
-    go = go * (1.0 - np.tanh(o) ** 2)
     w1, b1, w2, b2, w3, b3 = ps
     dw3, db3 = conv3d_wgrad(a2, go, n, 32, 8)
     g2 = conv3d_dgrad(go, w3, n) * (a2 > 0)
