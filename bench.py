@@ -327,7 +327,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design in DESIGN.md, not built)", file=sys.stderr)
+              "(a multi-GPU decomposition is designed, not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch

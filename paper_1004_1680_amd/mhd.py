@@ -41,8 +41,7 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
-            f"HIP library {LIB_PATH} not built: run paper_1004_1680_amd/build.py "
-            "(or __graft_entry__.build())")
+            f"HIP library {LIB_PATH} not built: run python -m paper_1004_1680_amd.build")
     # One HIP runtime per process: torch ships its own libamdhip64.so.7.
     # Loading torch first makes the dynamic loader bind libmhd.so to that
     # same runtime (same soname), so torch's streams and device pointers are

@@ -1,6 +1,6 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
-Tolerances (see the design doc for their derivation):
+Tolerances:
  * FP64 tier: 1e-12 relative to the largest magnitude of each field family
    (rho; m; e; b) -- both sides evaluate the same expressions in the same
    order without fused multiply-adds, so the observed difference is 0 or a
