@@ -2,7 +2,9 @@
 
 A step is one full update of the method: the FP64 CFL max-reduction on the
 device and the 12 operators F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x
-(dt kept on the device, as mhd_step_auto enqueues it).  The default
+(dt kept on the device, as mhd_step_auto enqueues it).  In FP32 each
+reverse-half pair (M_d F_d) runs as one fused kernel, so a step is 9
+launches, and the CFL maximum of the next step is found by the last one.  The default
 workload is the 256^3 FP32 run of seeded random-phase solenoidal turbulence
 (P(k) ~ k^-4, 1 <= k <= 8, rms Mach 1, beta 1, B0 along z).  The state is
 resident in HBM before the timed region starts.
@@ -44,8 +46,9 @@ CLOSURE_FLOP_PER_CELL = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 8)
 # algorithmic bytes per cell of one launch, in units of the element size:
 # fluid reads rho, m (3), e and the three face fields it averages into the
 # cell-centred field, writes rho, m, e; magnetic reads rho, m_d and b (3),
-# writes b (3); the CFL reads the 8 fields.
-ALG_WORDS = {"fluid": 8 + 5, "magnetic": 5 + 3, "cfl": 8}
+# writes b (3); the fused reverse pair (magnetic then fluid) reads and writes
+# the 8 fields; the CFL reads the 8 fields.
+ALG_WORDS = {"fluid": 8 + 5, "magnetic": 5 + 3, "pair": 8 + 8, "cfl": 8}
 STEP_WORDS = 6 * (8 + 8) + 8   # fused-sweep lower bound: 8r + 8w per sweep, + CFL
 
 WORKLOADS = {
@@ -93,8 +96,13 @@ def make_state_device(wl, torch):
 
 def time_operator(S, op, d, dt, reps, stream, torch):
     """average duration (ms) of one launch of an operator kernel, HIP events
-    on the solver's stream around `reps` back-to-back launches"""
-    f = S.fluid if op == "fluid" else S.magnetic
+    on the solver's stream around `reps` back-to-back launches (op "pair":
+    the fused reverse-half pair M_d F_d)"""
+    if op == "pair":
+        def f(d, dt):
+            S.sweep(3 + d, dt)
+    else:
+        f = S.fluid if op == "fluid" else S.magnetic
     f(d, dt)                          # scalars already on the device
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -351,7 +359,7 @@ def main():
     if not args.no_tune:
         from paper_1004_1680_amd import autotune
         chunks = autotune.tune_solver(S, args.cfl, use_cache=False)
-        log(f"[bench] autotuned march chunks (y, z): {chunks[1]}, {chunks[2]}")
+        log(f"[bench] autotuned march chunks: {chunks}")
     log("[bench] state resident; warm-up")
 
     for _ in range(args.warmup):
@@ -376,7 +384,9 @@ def main():
     log("[bench] per-kernel timing")
     saved = S.get_state_tensor()
     kern = {}
-    for op in ("fluid", "magnetic"):
+    fused = S.reverse() == 1
+    ops = ("fluid", "magnetic", "pair") if fused else ("fluid", "magnetic")
+    for op in ops:
         for d in range(3):
             S.set_state_tensor(saved)
             dt = S.cfl_dt(args.cfl) * 0.25
@@ -396,7 +406,8 @@ def main():
     ms_cfl_sync = e0.elapsed_time(e1) / args.kernel_reps
     kern["cfl(sync)"] = {"ms": round(ms_cfl_sync, 5),
                          "alg_GBs": round(ALG_WORDS["cfl"] * esize * ncell / (ms_cfl_sync * 1e-3) / 1e9, 1)}
-    # dominant kernel: largest time per step (each operator runs twice a step)
+    # dominant kernel: largest time per step (with fused reverse pairs every
+    # kernel runs once a step, otherwise each operator runs twice)
     dom = max((k for k in kern if k != "cfl(sync)"), key=lambda k: kern[k]["ms"])
     op = dom.split("_")[0]
     bytes_per_launch = ALG_WORDS[op] * esize * ncell
@@ -409,9 +420,10 @@ def main():
         tpath = os.path.join(ROOT, "profiles", f"sweeps_{args.workload}_hbm_traffic.md")
     from paper_1004_1680_amd.profile_summary import read_traffic
     tmap = read_traffic(tpath)
-    tname = {"x": "fluid_x_kernel<{t}, false>" if op == "fluid" else "mag_x_kernel<{t}>",
+    kname = {"fluid": "fluid", "magnetic": "mag", "pair": "magfluid"}[op]
+    tname = {"x": "{op}_x_kernel<{t}, false>" if op != "magnetic" else "mag_x_kernel<{t}>",
              "y": "{op}_march_kernel<{t}, 1>", "z": "{op}_march_kernel<{t}, 2>"}[dom[-1]].format(
-        op="fluid" if op == "fluid" else "mag", t="double" if esize == 8 else "float")
+        op=kname, t="double" if esize == 8 else "float")
     if tname in tmap:
         traffic = tmap[tname]
     step_alg = STEP_WORDS * esize * ncell / (ms_per_step * 1e-3) / 1e9
@@ -430,8 +442,11 @@ def main():
         "dtype": "f64" if wl["prec"] == "f64" else "f32",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "grid": [n, n, n], "cfl": args.cfl,
-                   "step": "CFL (FP64) + F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x",
+                   "step": ("CFL (FP64) + F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x; "
+                            + ("9 launches: each reverse pair M_d F_d fused, CFL in the last"
+                               if fused else "12 launches")),
                    "march_chunks": [S.chunk(1), S.chunk(2)],
+                   "pair_chunks": [S.pair_chunk(1), S.pair_chunk(2)] if fused else None,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -160,9 +160,16 @@ int mhd_restrict(mhd_ctx *fine, mhd_ctx *coarse);
 /* Launch shape of the y and z sweep kernels: each lane walks one pencil
  * along the sweep axis in chunks of `value` cells (value must divide the
  * axis length and be >= 8; 0 restores the built-in choice).  key: MHD_TUNE_
- * CHUNK_Y or MHD_TUNE_CHUNK_Z.  Results do not depend on the shape.  A
- * launch-shape parameter, not part of the method. */
-enum { MHD_TUNE_CHUNK_Y = 1, MHD_TUNE_CHUNK_Z = 2 };
+ * CHUNK_Y or MHD_TUNE_CHUNK_Z for the single operators, MHD_TUNE_PAIR_
+ * CHUNK_Y or MHD_TUNE_PAIR_CHUNK_Z for the fused reverse-half pairs.
+ * key MHD_TUNE_REVERSE: how the reverse-half pairs M_d F_d of a step and of
+ * mhd_sweep(3..5) run: 1 = one fused launch per pair (the new faces stay
+ * in registers; 9 launches per step), 2 = the two operators in turn (12
+ * launches), 0 = the built-in choice (1 in FP32, 2 in FP64).
+ * Results do not depend on any of these (the fused pair is bitwise the two
+ * operators).  Launch-shape parameters, not part of the method. */
+enum { MHD_TUNE_CHUNK_Y = 1, MHD_TUNE_CHUNK_Z = 2, MHD_TUNE_REVERSE = 3,
+       MHD_TUNE_PAIR_CHUNK_Y = 4, MHD_TUNE_PAIR_CHUNK_Z = 5 };
 int mhd_set_launch(mhd_ctx *h, int key, int value);
 int mhd_get_launch(const mhd_ctx *h, int key, int *value);
 
@@ -207,11 +214,14 @@ int mhd_batch_status(mhd_batch *b, long long *steps, int *nonphys);
 int mhd_batch_time(mhd_batch *b, double *times);
 
 /* Launch shape (results do not depend on it): persistent workgroups of the
- * x, y, z operator launches (multiples of 8), and the target march chunk
- * (each box takes the largest divisor of its axis length <= target, >= 8).
+ * x, y, z operator launches (multiples of 8), the target march chunk (each
+ * box takes the largest divisor of its axis length <= target, >= 8), and
+ * MHD_BATCH_REVERSE as MHD_TUNE_REVERSE of a single grid (1: each
+ * reverse-half pair M_d F_d in one launch, 2: the two operators in turn,
+ * 0: built-in, 1 in FP32 and 2 in FP64).
  * Launch-shape parameters, not part of the method. */
 enum { MHD_BATCH_GRID_X = 10, MHD_BATCH_GRID_Y = 11, MHD_BATCH_GRID_Z = 12,
-       MHD_BATCH_CHUNK = 13 };
+       MHD_BATCH_CHUNK = 13, MHD_BATCH_REVERSE = 14 };
 int mhd_batch_set_launch(mhd_batch *b, int key, int value);
 int mhd_batch_get_launch(const mhd_batch *b, int key, int *value);
 

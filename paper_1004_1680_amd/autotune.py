@@ -6,8 +6,9 @@ the live state and keeps the fastest; choices are cached in a JSON file
 (``$MHD_AUTOTUNE_CACHE``, default ``~/.cache/mhd_autotune.json``) keyed by
 device, problem and precision.
 
-* single grid: the march chunk length along y and z (the x sweeps hold
-  whole rows and have no shape to choose);
+* single grid: the march chunk length along y and z of the single
+  operators and of the fused reverse-half pairs (the x sweeps hold whole
+  rows and have no shape to choose);
 * batched ensemble: the persistent grid of the operator launches and the
   target march chunk.
 
@@ -66,33 +67,49 @@ def chunk_candidates(n):
     return sorted(out)
 
 
-def tune_solver(S, cfl=0.7, steps=3, use_cache=True):
-    """Choose the y and z march chunks of a Solver; returns {axis: chunk}."""
-    key = f"{_device_tag()}:single:{S.n[0]}x{S.n[1]}x{S.n[2]}:{'f64' if S.prec == mhd.MHD_F64 else 'f32'}"
+def tune_solver(S, cfl=0.7, steps=4, repeats=2, use_cache=True):
+    """Choose the march chunks of a Solver along y and z: those of the single
+    operators and, when the reverse-half pairs run fused, those of the fused
+    pairs (one parameter at a time, the others held).  Each candidate is
+    timed over `steps` steps, best of `repeats`.  Returns {key: chunk} with
+    keys (kind, axis), kind "op" or "pair"."""
+    fused = S.reverse() == 1
+    kinds = ("op", "pair") if fused else ("op",)
+    key = (f"{_device_tag()}:single:{S.n[0]}x{S.n[1]}x{S.n[2]}:"
+           f"{'f64' if S.prec == mhd.MHD_F64 else 'f32'}:{'fused' if fused else 'separate'}")
+    setter = {"op": S.set_chunk, "pair": S.set_pair_chunk}
     db = _load()
     if use_cache and key in db:
-        best = db[key]
-        S.set_chunk(1, best["1"])
-        S.set_chunk(2, best["2"])
-        return {1: best["1"], 2: best["2"]}
+        best = {(k, int(a)): v for k, av in db[key].items() for a, v in av.items()}
+        for (k, a), v in best.items():
+            setter[k](a, v)
+        return best
     saved = S.get_state_tensor()
-    best = {}
-    for axis in (1, 2):
-        timings = {}
-        for ch in chunk_candidates(S.n[axis]):
-            S.set_chunk(axis, ch)
-            S.set_state_tensor(saved)
-            S.step_auto(cfl)
-            S.status()
+
+    def timed():
+        S.set_state_tensor(saved)
+        S.step_auto(cfl)
+        S.status()
+        t = float("inf")
+        for _ in range(repeats):
             t0 = time.perf_counter()
             for _ in range(steps):
                 S.step_auto(cfl)
             S.status()
-            timings[ch] = time.perf_counter() - t0
-        best[axis] = min(timings, key=timings.get)
-        S.set_chunk(axis, best[axis])
+            t = min(t, time.perf_counter() - t0)
+        return t
+
+    best = {}
+    for kind in kinds:
+        for axis in (1, 2):
+            timings = {}
+            for ch in chunk_candidates(S.n[axis]):
+                setter[kind](axis, ch)
+                timings[ch] = timed()
+            best[(kind, axis)] = min(timings, key=timings.get)
+            setter[kind](axis, best[(kind, axis)])
     S.set_state_tensor(saved)
-    db[key] = {"1": best[1], "2": best[2]}
+    db[key] = {k: {str(a): v for (kk, a), v in best.items() if kk == k} for k in kinds}
     _store(db)
     return best
 

@@ -47,6 +47,7 @@ struct mhd_batch {
     int* partial_bad;
     int grid[3];
     int chunk_target;
+    bool rev_fused;         // reverse-half pairs M_d F_d in one launch each
     hipGraph_t graph;
     hipGraphExec_t exec;
     double graph_cfl;
@@ -162,6 +163,7 @@ extern "C" mhd_batch* mhd_batch_create(int nbox, const int* dims, double gamma, 
     b->prec = prec;
     b->esize = prec == MHD_F64 ? sizeof(double) : sizeof(float);
     b->chunk_target = 64;
+    b->rev_fused = prec == MHD_F32;
     b->d_boxes = nullptr;
     for (int d = 0; d < 3; ++d) { b->d_items[d] = nullptr; b->grid[d] = 1024; }
     b->buf[0] = b->buf[1] = nullptr;
@@ -332,10 +334,15 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
     HIP_TRY(b, launch_batch_cfl<T>(base, b->d_boxes, b->d_cfl_items, b->n_cfl_items,
                                    b->d_item_first, b->nbox, b->gamma, cfl, b->partial,
                                    b->partial_bad, b->scal, b->flag, b->stream));
-    static const int order[12][2] = { { 0, 0 }, { 1, 0 }, { 0, 1 }, { 1, 1 }, { 0, 2 }, { 1, 2 },
-                                      { 1, 2 }, { 0, 2 }, { 1, 1 }, { 0, 1 }, { 1, 0 }, { 0, 0 } };
-    for (int k = 0; k < 12; ++k) {
-        const int op = order[k][0], d = order[k][1];
+    // (op, d): op 0 fluid, 1 magnetic, 2 the reverse-half pair in one launch
+    static const int separate[12][2] = { { 0, 0 }, { 1, 0 }, { 0, 1 }, { 1, 1 }, { 0, 2 }, { 1, 2 },
+                                         { 1, 2 }, { 0, 2 }, { 1, 1 }, { 0, 1 }, { 1, 0 }, { 0, 0 } };
+    static const int fused[9][2] = { { 0, 0 }, { 1, 0 }, { 0, 1 }, { 1, 1 }, { 0, 2 }, { 1, 2 },
+                                     { 2, 2 }, { 2, 1 }, { 2, 0 } };
+    const int nops = b->rev_fused ? 9 : 12;
+    for (int k = 0; k < nops; ++k) {
+        const int op = b->rev_fused ? fused[k][0] : separate[k][0];
+        const int d = b->rev_fused ? fused[k][1] : separate[k][1];
         BatchParams<T> P;
         for (int q = 0; q < 8; ++q) {
             P.in_base[q] = reinterpret_cast<const T*>(b->buf[b->cur[q]]);
@@ -349,9 +356,9 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
         P.flag = b->flag;
         const int grid = std::max(8, std::min(b->grid[d], (b->nitems[d] + 7) / 8 * 8));
         HIP_TRY(b, launch_batch_op<T>(P, op, d, grid, b->stream));
-        if (op == 0)
+        if (op != 1)
             for (int q = 0; q < 5; ++q) b->cur[q] = 1 - b->cur[q];
-        else
+        if (op != 0)
             for (int q = 5; q < 8; ++q) b->cur[q] = 1 - b->cur[q];
     }
     HIP_TRY(b, launch_batch_advance(b->scal, b->flag, b->nbox, b->stream));
@@ -460,6 +467,13 @@ extern "C" int mhd_batch_set_launch(mhd_batch* b, int key, int value)
         b->chunk_target = value;
         return build_lists(b);
     }
+    if (key == MHD_BATCH_REVERSE) {
+        if (value < 0 || value > 2)
+            return mhd_fail(MHD_EINVAL, "reverse-half choice must be 0, 1 or 2 (got %d)", value);
+        b->rev_fused = value == 0 ? b->prec == MHD_F32 : value == 1;
+        drop_graph(b);
+        return MHD_OK;
+    }
     return mhd_fail(MHD_EINVAL, "unknown launch key %d", key);
 }
 
@@ -470,6 +484,8 @@ extern "C" int mhd_batch_get_launch(const mhd_batch* b, int key, int* value)
         *value = b->grid[key - MHD_BATCH_GRID_X];
     else if (key == MHD_BATCH_CHUNK)
         *value = b->chunk_target;
+    else if (key == MHD_BATCH_REVERSE)
+        *value = b->rev_fused ? 1 : 2;
     else
         return mhd_fail(MHD_EINVAL, "unknown launch key %d", key);
     return MHD_OK;

@@ -220,9 +220,13 @@ __device__ __forceinline__ void signal_speed64(double rho, double mx, double my,
     const double b2 = bx * bx + by * by + bz * bz;
     const double mm = mx * mx + my * my + mz * mz;
     const double p = (gamma - 1.0) * (e - 0.5 * mm / rho - 0.5 * b2);
-    const double vx = fabs(mx / rho), vy = fabs(my / rho), vz = fabs(mz / rho);
-    double vm = vx > vy ? vx : vy;
-    vm = vm > vz ? vm : vz;
+    // max_d |m_d / rho| as one division: for rho > 0 a correctly rounded
+    // division is odd and monotonic in the numerator, so this is the same
+    // value as the largest of the three quotients (rho <= 0 is flagged)
+    const double ax = fabs(mx), ay = fabs(my), az = fabs(mz);
+    double am = ax > ay ? ax : ay;
+    am = am > az ? am : az;
+    const double vm = am / rho;
     const double sp = vm + sqrt((gamma * p + b2) / rho);
     if (!(rho > 0.0) || !(p >= 0.0) || !isfinite(sp) || !isfinite(e) || !isfinite(mm) || !isfinite(b2))
         bad = 1;

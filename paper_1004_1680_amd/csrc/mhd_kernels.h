@@ -22,7 +22,7 @@ struct SweepParams {
     T gamma;
     const double* scal;      // device scalar block (dt, relaxation speed)
     const int* flag;         // if *flag != 0 the operator copies in -> out
-    // fused CFL (x fluid operator only; null: off): the FP64 signal-speed
+    // fused CFL (x fluid operator, alone or fused; null: off): the FP64 signal-speed
     // maximum of the operator's output is accumulated in cfl_acc[0 ..
     // CFL_ACC_SLOTS) (bits of the double, atomic max into the slot of the
     // workgroup, spreading the atomics) and non-physical cells in
@@ -32,9 +32,11 @@ struct SweepParams {
 };
 
 // Launch shape choices of the march kernels: chunk length along y and z
-// (0 = whole pencil).  Index 0 is unused (x sweeps hold whole rows).
+// (0 = whole pencil) of the single operators and of the fused reverse-half
+// pairs.  Index 0 is unused (x sweeps hold whole rows).
 struct LaunchTuning {
     int chunk[3];
+    int pair_chunk[3];
 };
 
 // ---------------------------------------------------------------------------
@@ -64,7 +66,8 @@ struct BatchParams {
     const int* flag;              // per box: FLAG_COUNT ints (null: never skip)
 };
 
-// op 0 fluid, 1 magnetic; d = sweep axis; grid = persistent workgroups (x8)
+// op 0 fluid, 1 magnetic, 2 magnetic then fluid in one pass (the reverse-half
+// pair); d = sweep axis; grid = persistent workgroups (x8)
 template <typename T>
 hipError_t launch_batch_op(const BatchParams<T>& B, int op, int d, int grid, hipStream_t s);
 
@@ -91,6 +94,10 @@ template <typename T>
 bool fused_cfl_possible(int nx);
 template <typename T>
 hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s);
+// M_d then F_d in one pass, bitwise the two operators in turn; P.cfl_acc
+// (d = 0 only) adds the fused CFL epilogue of launch_fluid
+template <typename T>
+hipError_t launch_magfluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s);
 
 // CFL: per-block maxima of the signal speed into partial[], then a final
 // reduction writes scal[SCAL_VMAX], scal[SCAL_C] = vmax, scal[SCAL_DT] =

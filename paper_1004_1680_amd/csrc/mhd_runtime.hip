@@ -66,6 +66,9 @@ struct mhd_ctx {
     unsigned long long* cfl_acc;
     bool acc_valid;
     bool fuse_ok;           // grid shape allows the fused epilogue
+    // reverse-half pairs M_d F_d: one fused launch each (true) or the two
+    // operators in turn; same result bit for bit
+    bool rev_fused;
     double scal_dt, scal_c;
     bool failed;
     LaunchTuning tune;
@@ -96,11 +99,11 @@ static void current_fields(mhd_ctx* h, const T* f[8])
     for (int q = 0; q < 8; ++q) f[q] = field_ptr<T>(h, q, h->cur[q]);
 }
 
-static int largest_chunk(int nd, long npencil)
+static int largest_chunk(int nd, long npencil, int waves_per_simd)
 {
-    // enough lanes to give every SIMD of the 256 CUs several waves, with a
-    // chunk no shorter than 16 cells (the warm-up re-reads 6 cells)
-    const long target = 256L * 4 * 4 * 64;
+    // enough lanes to give every SIMD of the 256 CUs the waves it can hold,
+    // with a chunk no shorter than 16 cells (the warm-up re-reads 6 cells)
+    const long target = 256L * 4 * waves_per_simd * 64;
     int best = nd;
     for (int ch = nd; ch >= 16; --ch) {
         if (nd % ch) continue;
@@ -112,9 +115,19 @@ static int largest_chunk(int nd, long npencil)
 
 static void default_tuning(mhd_ctx* h)
 {
-    h->tune.chunk[0] = 0;
-    h->tune.chunk[1] = largest_chunk(h->n[1], (long)h->n[0] * h->n[2]);
-    h->tune.chunk[2] = largest_chunk(h->n[2], (long)h->n[0] * h->n[1]);
+    // the fused reverse-pair march holds two register windows: half the
+    // waves per SIMD, so half the lanes fill the device
+    h->tune.chunk[0] = h->tune.pair_chunk[0] = 0;
+    for (int d = 1; d < 3; ++d) {
+        const long npencil = (long)h->n[0] * h->n[3 - d];
+        h->tune.chunk[d] = largest_chunk(h->n[d], npencil, 4);
+        h->tune.pair_chunk[d] = largest_chunk(h->n[d], npencil, 2);
+    }
+}
+
+static bool default_rev_fused(int prec)
+{
+    return prec == MHD_F32;
 }
 
 static int sync_stream(mhd_ctx* h)
@@ -191,6 +204,7 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
         return nullptr;
     }
     default_tuning(h);
+    h->rev_fused = default_rev_fused(prec);
     h->fuse_ok = prec == MHD_F64 ? fused_cfl_possible<double>(nx) : fused_cfl_possible<float>(nx);
     h->acc_valid = false;
     return h;
@@ -433,7 +447,8 @@ extern "C" int mhd_get_relaxation_speed(const mhd_ctx* hc, double* c)
 // operators
 // ---------------------------------------------------------------------------
 
-// op 0 = fluid, 1 = magnetic; flag (nullable): skip-and-copy switch
+// op 0 = fluid, 1 = magnetic, 2 = magnetic then fluid in one launch;
+// flag (nullable): skip-and-copy switch
 template <typename T>
 static hipError_t enqueue_op(mhd_ctx* h, int op, int d, const int* flag, unsigned long long* acc)
 {
@@ -449,17 +464,18 @@ static hipError_t enqueue_op(mhd_ctx* h, int op, int d, const int* flag, unsigne
     P.cfl_acc = acc;
     P.gamma64 = h->gamma;
     hipError_t e = op == 0 ? launch_fluid<T>(P, d, h->tune, h->stream)
-                           : launch_magnetic<T>(P, d, h->tune, h->stream);
+                 : op == 1 ? launch_magnetic<T>(P, d, h->tune, h->stream)
+                           : launch_magfluid<T>(P, d, h->tune, h->stream);
     if (e == hipSuccess) {
-        if (op == 0)
+        if (op != 1)
             for (int q = 0; q < 5; ++q) h->cur[q] = 1 - h->cur[q];
-        else
+        if (op != 0)
             for (int q = 5; q < 8; ++q) h->cur[q] = 1 - h->cur[q];
     }
     return e;
 }
 
-// acc (nullable, fluid along x only): fused CFL accumulator
+// acc (nullable; fluid along x, alone or fused): fused CFL accumulator
 static hipError_t op(mhd_ctx* h, int o, int d, const int* flag, unsigned long long* acc = nullptr)
 {
     return h->prec == MHD_F64 ? enqueue_op<double>(h, o, d, flag, acc) : enqueue_op<float>(h, o, d, flag, acc);
@@ -519,6 +535,8 @@ extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
     if (dim < 3) {
         HIP_TRY(h, op(h, 0, d, nullptr));
         HIP_TRY(h, op(h, 1, d, nullptr));
+    } else if (h->rev_fused) {
+        HIP_TRY(h, op(h, 2, d, nullptr));
     } else {
         HIP_TRY(h, op(h, 1, d, nullptr));
         HIP_TRY(h, op(h, 0, d, nullptr));
@@ -527,8 +545,9 @@ extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
 }
 
 // the 12 operators of a full step: x, y, z forward (fluid, magnetic), then
-// z, y, x reverse (magnetic, fluid).  acc (nullable): the last operator
-// (F_x) also accumulates the CFL maximum of the state it leaves.
+// z, y, x reverse (magnetic, fluid), each reverse pair in one launch when
+// rev_fused (9 launches).  acc (nullable): the last operator (F_x) also
+// accumulates the CFL maximum of the state it leaves.
 static int enqueue_step_ops(mhd_ctx* h, const int* flag, unsigned long long* acc)
 {
     for (int d = 0; d < 3; ++d) {
@@ -536,8 +555,12 @@ static int enqueue_step_ops(mhd_ctx* h, const int* flag, unsigned long long* acc
         HIP_TRY(h, op(h, 1, d, flag));
     }
     for (int d = 2; d >= 0; --d) {
-        HIP_TRY(h, op(h, 1, d, flag));
-        HIP_TRY(h, op(h, 0, d, flag, d == 0 ? acc : nullptr));
+        if (h->rev_fused) {
+            HIP_TRY(h, op(h, 2, d, flag, d == 0 ? acc : nullptr));
+        } else {
+            HIP_TRY(h, op(h, 1, d, flag));
+            HIP_TRY(h, op(h, 0, d, flag, d == 0 ? acc : nullptr));
+        }
     }
     return MHD_OK;
 }
@@ -679,24 +702,42 @@ extern "C" int mhd_set_launch(mhd_ctx* h, int key, int value)
 {
     int r = check_handle(h);
     if (r) return r;
-    if (key != MHD_TUNE_CHUNK_Y && key != MHD_TUNE_CHUNK_Z)
+    if (key == MHD_TUNE_REVERSE) {
+        if (value < 0 || value > 2)
+            return fail(MHD_EINVAL, "reverse-half choice must be 0, 1 or 2 (got %d)", value);
+        h->rev_fused = value == 0 ? default_rev_fused(h->prec) : value == 1;
+        return MHD_OK;
+    }
+    const bool pair = key == MHD_TUNE_PAIR_CHUNK_Y || key == MHD_TUNE_PAIR_CHUNK_Z;
+    if (key != MHD_TUNE_CHUNK_Y && key != MHD_TUNE_CHUNK_Z && !pair)
         return fail(MHD_EINVAL, "unknown launch key %d", key);
-    const int d = key;   // MHD_TUNE_CHUNK_Y = 1 (y), MHD_TUNE_CHUNK_Z = 2 (z)
+    const int d = pair ? key - MHD_TUNE_PAIR_CHUNK_Y + 1 : key;   // axis 1 (y) or 2 (z)
+    int* slot = pair ? &h->tune.pair_chunk[d] : &h->tune.chunk[d];
     if (value == 0) {
-        const int keep = h->tune.chunk[3 - d];
+        const LaunchTuning keep = h->tune;
         default_tuning(h);
-        h->tune.chunk[3 - d] = keep;
+        const int v = *slot;
+        h->tune = keep;
+        *slot = v;
         return MHD_OK;
     }
     if (value < 8 || h->n[d] % value)
         return fail(MHD_EINVAL, "chunk %d must be >= 8 and divide the axis length %d", value, h->n[d]);
-    h->tune.chunk[d] = value;
+    *slot = value;
     return MHD_OK;
 }
 
 extern "C" int mhd_get_launch(const mhd_ctx* h, int key, int* value)
 {
     if (!h || !value) return fail(MHD_EINVAL, "null argument");
+    if (key == MHD_TUNE_REVERSE) {
+        *value = h->rev_fused ? 1 : 2;
+        return MHD_OK;
+    }
+    if (key == MHD_TUNE_PAIR_CHUNK_Y || key == MHD_TUNE_PAIR_CHUNK_Z) {
+        *value = h->tune.pair_chunk[key - MHD_TUNE_PAIR_CHUNK_Y + 1];
+        return MHD_OK;
+    }
     if (key != MHD_TUNE_CHUNK_Y && key != MHD_TUNE_CHUNK_Z)
         return fail(MHD_EINVAL, "unknown launch key %d", key);
     *value = h->tune.chunk[key];

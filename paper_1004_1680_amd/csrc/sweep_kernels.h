@@ -83,88 +83,48 @@ __device__ __forceinline__ void step_scalars(const SweepParams<T>& P, T& tau, T&
 // ---------------------------------------------------------------------------
 // Launch: blockDim = rows_per_wg * tpr threads (tpr = nx/4 threads per row),
 // grid = ceil(ny*nz / rows_per_wg) workgroups; dynamic LDS = 25 * blockDim
-// values of T (fluid) or 16 * blockDim (magnetic).
+// values of T (fluid, and the fused magnetic-fluid pair) or 16 * blockDim
+// (magnetic).
 
-// One tile of rows_per_wg rows of one grid; every thread of the workgroup
-// calls it (it holds barriers).  Threads beyond rows_per_wg * tpr idle.
-// CFL = true: also the fused CFL epilogue (FP64 signal speed of every output
-// cell, maximum per wave, atomic maximum into P.cfl_acc); needs full waves
-// (blockDim.x a multiple of 64).
-template <typename T, bool CFL = false>
-__device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
-                                             int rows_per_wg, T* const A)
+// Row geometry of one thread: row of the grid, position in it, neighbours
+// in the row (for the LDS exchanges).  Idle threads (rloc >= rows_per_wg)
+// exchange with themselves, so every LDS index stays below blockDim.x.
+struct RowThread {
+    int t, tprev, tnext, i0, y, z;
+    bool active;
+    __device__ __forceinline__ RowThread(int tile, int tpr, int rows_per_wg, int ny, int nz)
+    {
+        t = threadIdx.x;
+        const int rloc = t / tpr, tr = t - rloc * tpr;
+        const int row = tile * rows_per_wg + rloc;
+        active = rloc < rows_per_wg && row < ny * nz;
+        y = active ? row % ny : 0;
+        z = active ? row / ny : 0;
+        const bool inrow = rloc < rows_per_wg;
+        tprev = inrow ? rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1) : t;
+        tnext = inrow ? rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1) : t;
+        i0 = 4 * tr;
+    }
+};
+
+// x fluid operator from given inputs: U of the thread's 4 cells, the frozen
+// Bbar, and (CFL) the raw face values (own, next) of b_x, b_y, b_z for the
+// fused CFL epilogue.  Stores the new U.  A: LDS of 25 values per thread.
+// Every thread of the workgroup calls it (it holds barriers).
+// CFL = true: the FP64 signal speed of every output cell, maximum per wave,
+// atomic maximum into P.cfl_acc; needs full waves (blockDim.x a multiple of
+// 64).
+template <typename T, bool CFL>
+__device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowThread& R, size_t base,
+                                             const T (&u)[4][5], const T (&bb)[4][3],
+                                             const T (&fb)[CFL ? 4 : 1][6], T* const A)
 {
     T* const B = A + 20 * blockDim.x;                       // A: 20, B: 5 values / thread
     const int nt = blockDim.x;
-    const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const int t = threadIdx.x;
-    const int rloc = t / tpr, tr = t - rloc * tpr;
-    const int row = tile * rows_per_wg + rloc;
-    const bool active = rloc < rows_per_wg && row < ny * nz;
-    const int y = active ? row % ny : 0, z = active ? row / ny : 0;
-    // idle threads (rloc >= rows_per_wg) exchange with themselves, so every
-    // LDS index stays below blockDim.x
-    const bool inrow = rloc < rows_per_wg;
-    const int tprev = inrow ? rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1) : t;
-    const int tnext = inrow ? rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1) : t;
-    const size_t base = (size_t)nx * ((size_t)y + (size_t)ny * z);
-    const size_t base_yp = (size_t)nx * ((size_t)(y + 1 == ny ? 0 : y + 1) + (size_t)ny * z);
-    const size_t base_zp = (size_t)nx * ((size_t)y + (size_t)ny * (z + 1 == nz ? 0 : z + 1));
-    const int i0 = 4 * tr;
-
-    if (P.flag && *P.flag) {      // non-physical state recorded: keep the state
-        if (active)
-            for (int f = 0; f < 5; ++f) {
-                T v[4];
-                vec4<T>::load(P.in[f] + base + i0, v);
-                vec4<T>::store(P.out[f] + base + i0, v);
-            }
-        if constexpr (CFL)
-            if (threadIdx.x == 0) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, 1ull);
-        return;
-    }
-
+    const int t = R.t, tprev = R.tprev, tnext = R.tnext;
     T tau, halftau, c;
     step_scalars(P, tau, halftau, c);
     const T gamma = P.gamma;
-
-    T u[4][5], bb[4][3];
-    double fb[CFL ? 4 : 1][6];    // fused CFL: raw face values (own, next) of b_x, b_y, b_z
-    {
-        T tmp[4], tmp2[4];
-        for (int q = 0; q < 5; ++q) {
-            if (active) vec4<T>::load(P.in[q] + base + i0, tmp);
-            else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(1);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) u[k][q] = tmp[k];
-        }
-        // Bbar_x: faces i and i+1 along the row
-        T bxn = T(0);
-        if (active) {
-            vec4<T>::load(P.in[BX] + base + i0, tmp);
-            bxn = P.in[BX][base + (i0 + 4 == nx ? 0 : i0 + 4)];
-        } else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) bb[k][0] = T(0.5) * (tmp[k] + (k < 3 ? tmp[k + 1] : bxn));
-        if constexpr (CFL)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { fb[k][0] = (double)tmp[k]; fb[k][1] = (double)(k < 3 ? tmp[k + 1] : bxn); }
-        // Bbar_y: faces at y and y+1; Bbar_z: faces at z and z+1
-        if (active) { vec4<T>::load(P.in[BY] + base + i0, tmp); vec4<T>::load(P.in[BY] + base_yp + i0, tmp2); }
-        else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) bb[k][1] = T(0.5) * (tmp[k] + tmp2[k]);
-        if constexpr (CFL)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { fb[k][2] = (double)tmp[k]; fb[k][3] = (double)tmp2[k]; }
-        if (active) { vec4<T>::load(P.in[BZ] + base + i0, tmp); vec4<T>::load(P.in[BZ] + base_zp + i0, tmp2); }
-        else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) bb[k][2] = T(0.5) * (tmp[k] + tmp2[k]);
-        if constexpr (CFL)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) { fb[k][4] = (double)tmp[k]; fb[k][5] = (double)tmp2[k]; }
-    }
 
     // stage 1: relaxed split and first-order upwind interface fluxes
     T fr[4][5], fl[4][5];
@@ -229,17 +189,17 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
     for (int q = 0; q < 5; ++q) B[q * nt + t] = phi[3][q];
     __syncthreads();
     if constexpr (!CFL) {
-        if (!active) return;
+        if (!R.active) return;
     }
     T onew[CFL ? 4 : 1][5];
-    if (active) {
+    if (R.active) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             const T phiprev = B[q * nt + tprev];
             T o[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) o[k] = sub_scaled(u[k][q], tau, phi[k][q] - (k > 0 ? phi[k - 1][q] : phiprev));
-            vec4<T>::store(P.out[q] + base + i0, o);
+            vec4<T>::store(P.out[q] + base + R.i0, o);
             if constexpr (CFL)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) onew[k][q] = o[k];
@@ -250,12 +210,12 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
         // from the values as stored; every lane of the wave takes part
         double vmax = 0.0;
         int bad = 0;
-        if (active)
+        if (R.active)
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 signal_speed64((double)onew[k][0], (double)onew[k][1], (double)onew[k][2], (double)onew[k][3],
-                               (double)onew[k][4], fb[k][0], fb[k][1], fb[k][2], fb[k][3], fb[k][4], fb[k][5],
-                               P.gamma64, vmax, bad);
+                               (double)onew[k][4], (double)fb[k][0], (double)fb[k][1], (double)fb[k][2],
+                               (double)fb[k][3], (double)fb[k][4], (double)fb[k][5], P.gamma64, vmax, bad);
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
@@ -271,6 +231,80 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
     }
 }
 
+// U of the thread's 4 cells (inactive threads: rho = 1, a harmless state)
+template <typename T>
+__device__ __forceinline__ void load_u4(const SweepParams<T>& P, const RowThread& R, size_t base, T (&u)[4][5])
+{
+    T tmp[4];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        if (R.active) vec4<T>::load(P.in[q] + base + R.i0, tmp);
+        else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[k][q] = tmp[k];
+    }
+}
+
+// One tile of rows_per_wg rows of one grid: fluid operator F_x.
+template <typename T, bool CFL = false>
+__device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
+                                             int rows_per_wg, T* const A)
+{
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    const RowThread R(tile, tpr, rows_per_wg, ny, nz);
+    const int y = R.y, z = R.z, i0 = R.i0;
+    const bool active = R.active;
+    const size_t base = (size_t)nx * ((size_t)y + (size_t)ny * z);
+    const size_t base_yp = (size_t)nx * ((size_t)(y + 1 == ny ? 0 : y + 1) + (size_t)ny * z);
+    const size_t base_zp = (size_t)nx * ((size_t)y + (size_t)ny * (z + 1 == nz ? 0 : z + 1));
+
+    if (P.flag && *P.flag) {      // non-physical state recorded: keep the state
+        if (active)
+            for (int f = 0; f < 5; ++f) {
+                T v[4];
+                vec4<T>::load(P.in[f] + base + i0, v);
+                vec4<T>::store(P.out[f] + base + i0, v);
+            }
+        if constexpr (CFL)
+            if (threadIdx.x == 0) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, 1ull);
+        return;
+    }
+
+    T u[4][5], bb[4][3];
+    T fb[CFL ? 4 : 1][6];         // fused CFL: raw face values (own, next) of b_x, b_y, b_z
+    load_u4(P, R, base, u);
+    {
+        T tmp[4], tmp2[4];
+        // Bbar_x: faces i and i+1 along the row
+        T bxn = T(0);
+        if (active) {
+            vec4<T>::load(P.in[BX] + base + i0, tmp);
+            bxn = P.in[BX][base + (i0 + 4 == nx ? 0 : i0 + 4)];
+        } else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bb[k][0] = T(0.5) * (tmp[k] + (k < 3 ? tmp[k + 1] : bxn));
+        if constexpr (CFL)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { fb[k][0] = tmp[k]; fb[k][1] = k < 3 ? tmp[k + 1] : bxn; }
+        // Bbar_y: faces at y and y+1; Bbar_z: faces at z and z+1
+        if (active) { vec4<T>::load(P.in[BY] + base + i0, tmp); vec4<T>::load(P.in[BY] + base_yp + i0, tmp2); }
+        else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bb[k][1] = T(0.5) * (tmp[k] + tmp2[k]);
+        if constexpr (CFL)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { fb[k][2] = tmp[k]; fb[k][3] = tmp2[k]; }
+        if (active) { vec4<T>::load(P.in[BZ] + base + i0, tmp); vec4<T>::load(P.in[BZ] + base_zp + i0, tmp2); }
+        else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bb[k][2] = T(0.5) * (tmp[k] + tmp2[k]);
+        if constexpr (CFL)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { fb[k][4] = tmp[k]; fb[k][5] = tmp2[k]; }
+    }
+    fluid_x_core<T, CFL>(P, R, base, u, bb, fb, A);
+}
+
 template <typename T, bool CFL>
 __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
 {
@@ -278,44 +312,29 @@ __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr,
     fluid_x_tile<T, CFL>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
-// Magnetic sweep along x: e = y then z.  For each e two edge-flux chains
-// are evaluated: "own" (edges of this row, velocity from rows P and P-e)
-// and "plus" (edges of row P+e, velocity from rows P+e and P), the latter
-// for the constraint update of b_x.
+// Magnetic operator along x (e = y then z) of the thread's 4 cells.  For
+// each e two edge-flux chains are evaluated: "own" (edges of this row,
+// velocity from rows P and P-e) and "plus" (edges of row P+e, velocity from
+// rows P+e and P), the latter for the constraint update of b_x; a plus
+// chain is the own chain of the neighbour row, evaluated identically.
+// Gives the new faces nb = (b_y of P, b_y of P+y, b_z of P, b_z of P+z, b_x
+// of P) of the 4 cells; stores nothing.  A: LDS of 16 values per thread.
+// Every thread of the workgroup calls it (it holds barriers).
 template <typename T>
-__device__ __forceinline__ void mag_x_tile(const SweepParams<T>& P, int tile, int tpr,
-                                           int rows_per_wg, T* const A)
+__device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThread& R, T (&nb)[5][4],
+                                           T* const A)
 {
     T* const B = A + 12 * blockDim.x;                       // A: 12, B: 4 values / thread
     const int nt = blockDim.x;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const int t = threadIdx.x;
-    const int rloc = t / tpr, tr = t - rloc * tpr;
-    const int row = tile * rows_per_wg + rloc;
-    const bool active = rloc < rows_per_wg && row < ny * nz;
-    const int y = active ? row % ny : 0, z = active ? row / ny : 0;
-    // idle threads (rloc >= rows_per_wg) exchange with themselves, so every
-    // LDS index stays below blockDim.x
-    const bool inrow = rloc < rows_per_wg;
-    const int tprev = inrow ? rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1) : t;
-    const int tnext = inrow ? rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1) : t;
-    const int i0 = 4 * tr;
+    const int t = R.t, tprev = R.tprev, tnext = R.tnext, i0 = R.i0, y = R.y, z = R.z;
+    const bool active = R.active;
     const int inext = (i0 + 4 == nx) ? 0 : i0 + 4;
     auto rbase = [&](int yy, int zz) -> size_t {
         yy = wrapi(yy, ny); zz = wrapi(zz, nz);
         return (size_t)nx * ((size_t)yy + (size_t)ny * zz);
     };
     const size_t b0 = rbase(y, z);
-
-    if (P.flag && *P.flag) {
-        if (active)
-            for (int f = BX; f <= BZ; ++f) {
-                T v[4];
-                vec4<T>::load(P.in[f] + b0 + i0, v);
-                vec4<T>::store(P.out[f] + b0 + i0, v);
-            }
-        return;
-    }
     T tau, halftau, cdummy;
     step_scalars(P, tau, halftau, cdummy);
 
@@ -415,27 +434,51 @@ __device__ __forceinline__ void mag_x_tile(const SweepParams<T>& P, int tile, in
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) B[ch * nt + t] = f[ch][3];
     __syncthreads();
-    if (!active) return;
     T fprev[4];
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) fprev[ch] = B[ch * nt + tprev];
     T bx[4];
-    vec4<T>::load(P.in[BX] + b0 + i0, bx);
-    T oy[4], oz[4];
+    if (active) vec4<T>::load(P.in[BX] + b0 + i0, bx);
+    else bx[0] = bx[1] = bx[2] = bx[3] = T(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const T fo_y = k > 0 ? f[0][k - 1] : fprev[0];
         const T fp_y = k > 0 ? f[1][k - 1] : fprev[1];
         const T fo_z = k > 0 ? f[2][k - 1] : fprev[2];
         const T fp_z = k > 0 ? f[3][k - 1] : fprev[3];
-        oy[k] = sub_scaled(q[0][k], tau, f[0][k] - fo_y);
-        oz[k] = sub_scaled(q[2][k], tau, f[2][k] - fo_z);
-        T b = add_scaled(bx[k], tau, fp_y - fo_y);
-        bx[k] = add_scaled(b, tau, fp_z - fo_z);
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const T fo = k > 0 ? f[ch][k - 1] : fprev[ch];
+            nb[ch][k] = sub_scaled(q[ch][k], tau, f[ch][k] - fo);
+        }
+        const T b = add_scaled(bx[k], tau, fp_y - fo_y);
+        nb[4][k] = add_scaled(b, tau, fp_z - fo_z);
     }
-    vec4<T>::store(P.out[BY] + b0 + i0, oy);
-    vec4<T>::store(P.out[BZ] + b0 + i0, oz);
-    vec4<T>::store(P.out[BX] + b0 + i0, bx);
+}
+
+// One tile of rows_per_wg rows of one grid: magnetic operator M_x.
+template <typename T>
+__device__ __forceinline__ void mag_x_tile(const SweepParams<T>& P, int tile, int tpr,
+                                           int rows_per_wg, T* const A)
+{
+    const int nx = P.nx, ny = P.ny;
+    const RowThread R(tile, tpr, rows_per_wg, ny, P.nz);
+    const size_t b0 = (size_t)nx * ((size_t)R.y + (size_t)ny * R.z);
+    if (P.flag && *P.flag) {
+        if (R.active)
+            for (int f = BX; f <= BZ; ++f) {
+                T v[4];
+                vec4<T>::load(P.in[f] + b0 + R.i0, v);
+                vec4<T>::store(P.out[f] + b0 + R.i0, v);
+            }
+        return;
+    }
+    T nb[5][4];
+    mag_x_core(P, R, nb, A);
+    if (!R.active) return;
+    vec4<T>::store(P.out[BY] + b0 + R.i0, nb[0]);
+    vec4<T>::store(P.out[BZ] + b0 + R.i0, nb[2]);
+    vec4<T>::store(P.out[BX] + b0 + R.i0, nb[4]);
 }
 
 template <typename T>
@@ -443,6 +486,69 @@ __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, i
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     mag_x_tile(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+}
+
+// One tile of rows: the reverse-half pair M_x then F_x in one pass.  The new
+// faces stay in registers: Bbar_y and Bbar_z take b_y, b_z of rows P+y, P+z
+// from the plus chains, Bbar_x takes the next cell's new b_x through LDS.
+// Same device functions in the same order as mag_x_tile followed by
+// fluid_x_tile, so the result is bitwise that of the two operators.  A: LDS
+// of 25 values per thread (the magnetic part uses the first 16; the b_x
+// exchange uses values 20..21, which the fluid part first writes after a
+// barrier that follows its last read).
+template <typename T, bool CFL = false>
+__device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
+                                                int rows_per_wg, T* const A)
+{
+    const int nx = P.nx, ny = P.ny;
+    const RowThread R(tile, tpr, rows_per_wg, ny, P.nz);
+    const size_t base = (size_t)nx * ((size_t)R.y + (size_t)ny * R.z);
+    if (P.flag && *P.flag) {
+        if (R.active)
+            for (int f = 0; f < NFIELD; ++f) {
+                T v[4];
+                vec4<T>::load(P.in[f] + base + R.i0, v);
+                vec4<T>::store(P.out[f] + base + R.i0, v);
+            }
+        if constexpr (CFL)
+            if (threadIdx.x == 0) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, 1ull);
+        return;
+    }
+    T nb[5][4];
+    mag_x_core(P, R, nb, A);
+    // new b_x of the first cell -> previous thread
+    T* const X = A + 20 * blockDim.x;
+    X[R.t] = nb[4][0];
+    __syncthreads();
+    const T bxn = X[R.tnext];
+    if (R.active) {
+        vec4<T>::store(P.out[BY] + base + R.i0, nb[0]);
+        vec4<T>::store(P.out[BZ] + base + R.i0, nb[2]);
+        vec4<T>::store(P.out[BX] + base + R.i0, nb[4]);
+    }
+    T u[4][5], bb[4][3];
+    T fb[CFL ? 4 : 1][6];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const T bx1 = k < 3 ? nb[4][k + 1] : bxn;
+        bb[k][0] = T(0.5) * (nb[4][k] + bx1);
+        bb[k][1] = T(0.5) * (nb[0][k] + nb[1][k]);
+        bb[k][2] = T(0.5) * (nb[2][k] + nb[3][k]);
+        if constexpr (CFL) {
+            fb[k][0] = nb[4][k]; fb[k][1] = bx1;
+            fb[k][2] = nb[0][k]; fb[k][3] = nb[1][k];
+            fb[k][4] = nb[2][k]; fb[k][5] = nb[3][k];
+        }
+    }
+    load_u4(P, R, base, u);
+    fluid_x_core<T, CFL>(P, R, base, u, bb, fb, A);
+}
+
+template <typename T, bool CFL>
+__global__ void __launch_bounds__(256) magfluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    magfluid_x_tile<T, CFL>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -495,18 +601,147 @@ __device__ __forceinline__ int march_start(int j0, int chunk)
     return j0 - 3 - ((U - (total % U)) % U);
 }
 
-// One lane (pencil chunk gid) of a grid.
+// Register window of the fluid march (two-stage relaxing TVD along the
+// pencil).  push() takes U and the frozen Bbar at the look-ahead position L
+// and gives the new U of cell L-3; it needs U and Bbar at L-3 .. L+3, so
+// pushes 6 positions before a chunk warm the window up (their results are
+// not used).
+template <typename T>
+struct FluidWindow {
+    T u3[5], u2[5], u1[5];            // U at L-3, L-2, L-1
+    T bbm[3];                         // Bbar at L-1
+    T frm[5];                         // stage-1 F^R at L-1
+    T f1m[5];                         // stage-1 interface flux at L-3/2
+    T r4[5], r3[5], r2[5];            // stage-2 F^R at L-4, L-3, L-2
+    T l3[5], l2[5];                   // stage-2 F^L at L-3, L-2
+    T phim[5];                        // net flux at interface (L-3)-1/2
+
+    __device__ __forceinline__ void init()
+    {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            u3[q] = u2[q] = u1[q] = T(0);
+            frm[q] = f1m[q] = r4[q] = r3[q] = r2[q] = l3[q] = l2[q] = phim[q] = T(0);
+        }
+        bbm[0] = bbm[1] = bbm[2] = T(0);
+    }
+
+    __device__ __forceinline__ void push(const T u0[5], const T bb0[3], T gamma, T c, T tau,
+                                         T halftau, T unew[5])
+    {
+        // stage 1 at L: split, interface flux at L-1/2, half step at L-1
+        T fr0[5], fl0[5], f1[5], uh[5];
+        relax_split(u0, bb0, gamma, c, fr0, fl0);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            f1[q] = frm[q] - fl0[q];
+            uh[q] = sub_scaled(u1[q], halftau, f1[q] - f1m[q]);
+        }
+        // stage 2 at L-1
+        T r1[5], l1[5];
+        relax_split(uh, bbm, gamma, c, r1, l1);
+        // net flux at interface (L-3)+1/2 and the update of cell L-3
+        T phi[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            phi[q] = limited_right(r4[q], r3[q], r2[q]) - limited_left(l3[q], l2[q], l1[q]);
+            unew[q] = sub_scaled(u3[q], tau, phi[q] - phim[q]);
+        }
+        // shift the window
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            phim[q] = phi[q];
+            r4[q] = r3[q]; r3[q] = r2[q]; r2[q] = r1[q];
+            l3[q] = l2[q]; l2[q] = l1[q];
+            frm[q] = fr0[q]; f1m[q] = f1[q];
+            u3[q] = u2[q]; u2[q] = u1[q]; u1[q] = u0[q];
+        }
+        bbm[0] = bb0[0]; bbm[1] = bb0[1]; bbm[2] = bb0[2];
+    }
+};
+
+// Register window of the constrained-transport march.  Four edge-flux
+// chains: 0 own-t1 (b_t1 of this pencil, velocity from P and P-t1), 1
+// plus-t1 (b_t1 of pencil P+t1, velocity from P+t1 and P), 2 own-t2, 3
+// plus-t2; a plus chain is the own chain of the neighbour pencil, evaluated
+// identically, and feeds the constraint update of b_n.  push() takes the
+// velocities v_n of the pencils (P, P-t1, P+t1, P-t2, P+t2), the chain
+// fields and b_n at the look-ahead position L and gives the new faces at
+// L-3: nb = (b_t1 of P, b_t1 of P+t1, b_t2 of P, b_t2 of P+t2, b_n of P).
+// It needs inputs at L-3 .. L+3 (6 warm-up pushes, like the fluid window).
+template <typename T>
+struct MagWindow {
+    T wm[4];                 // face velocity at L-1
+    T a3[4], a2[4];          // edge velocity at L-3, L-2
+    T q3[4], q2[4], q1[4];   // q at L-3, L-2, L-1
+    T gm[4];                 // first-order flux at L-2
+    T h4[4], h3[4], h2[4];   // half-step q at L-4, L-3, L-2
+    T fm[4];                 // edge flux at L-4
+    T bnw[3];                // b_n at L-3, L-2, L-1
+
+    __device__ __forceinline__ void init()
+    {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            wm[ch] = a3[ch] = a2[ch] = T(0);
+            q3[ch] = q2[ch] = q1[ch] = gm[ch] = h4[ch] = h3[ch] = h2[ch] = fm[ch] = T(0);
+        }
+        bnw[0] = bnw[1] = bnw[2] = T(0);
+    }
+
+    __device__ __forceinline__ void push(const T v[5], const T q0[4], T bn0, T tau, T halftau, T nb[5])
+    {
+        // velocity pencils of each chain: (chain pencil, chain pencil - e)
+        constexpr int vr0[4] = { 0, 2, 0, 4 };
+        constexpr int vr1[4] = { 1, 0, 3, 0 };
+        T f[4];
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const T w0 = face_avg(v[vr0[ch]], v[vr1[ch]]);       // w at L
+            const T a1 = edge_avg(wm[ch], w0);                   // a at L-1
+            const T g1 = upwind_flux1(a1, q1[ch], q0[ch]);      // G1 at L-1
+            const T hq1 = sub_scaled(q1[ch], halftau, g1 - gm[ch]);   // qh at L-1
+            // edge flux at L-3 from a(L-3) and qh at L-4..L-1
+            f[ch] = upwind_flux2(a3[ch], h4[ch], h3[ch], h2[ch], hq1);
+            wm[ch] = w0;
+            a3[ch] = a2[ch]; a2[ch] = a1;
+            gm[ch] = g1;
+            h4[ch] = h3[ch]; h3[ch] = h2[ch]; h2[ch] = hq1;
+        }
+        // advection of b_t1, b_t2 (own and plus pencils); constraint on b_n
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) nb[ch] = sub_scaled(q3[ch], tau, f[ch] - fm[ch]);
+        const T b = add_scaled(bnw[0], tau, fm[1] - fm[0]);
+        nb[4] = add_scaled(b, tau, fm[3] - fm[2]);
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            fm[ch] = f[ch];
+            q3[ch] = q2[ch]; q2[ch] = q1[ch]; q1[ch] = q0[ch];
+        }
+        bnw[0] = bnw[1]; bnw[1] = bnw[2]; bnw[2] = bn0;
+    }
+};
+
+// Lane -> (pencil p, chunk start j0) of a grid; false beyond the last lane.
+template <int D>
+__device__ __forceinline__ bool march_lane_of(int nx, int ny, int nz, long gid, int chunk, int& p, int& j0)
+{
+    const int npencil = nx * (D == 1 ? nz : ny);
+    const int nchunk = (D == 1 ? ny : nz) / chunk;
+    if (gid >= (long)npencil * nchunk) return false;
+    p = (int)(gid % npencil);
+    j0 = (int)(gid / npencil) * chunk;
+    return true;
+}
+
+// One lane (pencil chunk gid) of a grid: fluid operator F_d.
 template <typename T, int D>
 __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-    const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const int npencil = nx * (D == 1 ? nz : ny);
-    const int nchunk = (D == 1 ? ny : nz) / chunk;
-    if (gid >= (long)npencil * nchunk) return;
-    const int p = (int)(gid % npencil);
-    const int j0 = (int)(gid / npencil) * chunk;
-    const MarchGeom<D> G(nx, ny, nz, p);
+    int p, j0;
+    if (!march_lane_of<D>(P.nx, P.ny, P.nz, gid, chunk, p, j0)) return;
+    const MarchGeom<D> G(P.nx, P.ny, P.nz, p);
     const int nd = G.nd;
     const T* __restrict__ in_u[5] = { P.in[RHO], P.in[MX + N_], P.in[MX + T1], P.in[MX + T2], P.in[EN] };
     T* out_u[5] = { P.out[RHO], P.out[MX + N_], P.out[MX + T1], P.out[MX + T2], P.out[EN] };
@@ -525,20 +760,8 @@ __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long g
     step_scalars(P, tau, halftau, c);
     const T gamma = P.gamma;
 
-    // register window (index relative to the look-ahead position L)
-    T u3[5], u2[5], u1[5];            // U at L-3, L-2, L-1
-    T bbm[3];                         // Bbar at L-1
-    T frm[5];                         // stage-1 F^R at L-1
-    T f1m[5];                         // stage-1 interface flux at L-3/2
-    T r4[5], r3[5], r2[5];            // stage-2 F^R at L-4, L-3, L-2
-    T l3[5], l2[5];                   // stage-2 F^L at L-3, L-2
-    T phim[5];                        // net flux at interface (L-3)-1/2
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        u3[q] = u2[q] = u1[q] = T(0);
-        frm[q] = f1m[q] = r4[q] = r3[q] = r2[q] = l3[q] = l2[q] = phim[q] = T(0);
-    }
-    bbm[0] = bbm[1] = bbm[2] = T(0);
+    FluidWindow<T> W;
+    W.init();
     constexpr int U = march_unroll<T>();
     const int Lstart = march_start<U>(j0, chunk);
     int jl = Lstart < 0 ? Lstart + nd : Lstart;
@@ -573,39 +796,14 @@ __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long g
             bn_cur = bn_next;
             jl = jl + 1 == nd ? 0 : jl + 1;
             prefetch(jl);
-
-            // stage 1 at L: split, interface flux at L-1/2, half step at L-1
-            T fr0[5], fl0[5], f1[5], uh[5];
-            relax_split(u0, bb0, gamma, c, fr0, fl0);
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                f1[q] = frm[q] - fl0[q];
-                uh[q] = sub_scaled(u1[q], halftau, f1[q] - f1m[q]);
-            }
-            // stage 2 at L-1
-            T r1[5], l1[5];
-            relax_split(uh, bbm, gamma, c, r1, l1);
-            // net flux at interface (L-3)+1/2 and the update of cell L-3
+            T unew[5];
+            W.push(u0, bb0, gamma, c, tau, halftau, unew);
             const int j = L - 3;
-            T phi[5];
-#pragma unroll
-            for (int q = 0; q < 5; ++q)
-                phi[q] = limited_right(r4[q], r3[q], r2[q]) - limited_left(l3[q], l2[q], l1[q]);
             if (j >= j0) {
                 const unsigned oj = G.base + G.sd * (unsigned)j;
 #pragma unroll
-                for (int q = 0; q < 5; ++q) out_u[q][oj] = sub_scaled(u3[q], tau, phi[q] - phim[q]);
+                for (int q = 0; q < 5; ++q) out_u[q][oj] = unew[q];
             }
-            // shift the window
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                phim[q] = phi[q];
-                r4[q] = r3[q]; r3[q] = r2[q]; r2[q] = r1[q];
-                l3[q] = l2[q]; l2[q] = l1[q];
-                frm[q] = fr0[q]; f1m[q] = f1[q];
-                u3[q] = u2[q]; u2[q] = u1[q]; u1[q] = u0[q];
-            }
-            bbm[0] = bb0[0]; bbm[1] = bb0[1]; bbm[2] = bb0[2];
         }
     }
 }
@@ -619,23 +817,60 @@ __global__ void __launch_bounds__(256, march_waves<T>()) fluid_march_kernel(Swee
     fluid_march_lane<T, D>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
 
+// Inputs of the magnetic window at one position: v_n of the 5 pencils, the
+// 4 chain fields and b_n.
+template <typename T, int D>
+struct MagLoads {
+    const T* __restrict__ rho;
+    const T* __restrict__ mn;
+    const T* __restrict__ bq1;
+    const T* __restrict__ bq2;
+    const T* __restrict__ bnin;
+    unsigned pb[5];          // pencils: 0 P, 1 P-t1, 2 P+t1, 3 P-t2, 4 P+t2
+    unsigned qb[4];          // chain pencils
+    T nrho[5], nm[5], nq[4], nbn;
+
+    __device__ __forceinline__ MagLoads(const SweepParams<T>& P, const MarchGeom<D>& G)
+    {
+        constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+        rho = P.in[RHO]; mn = P.in[MX + N_];
+        bq1 = P.in[BX + T1]; bq2 = P.in[BX + T2]; bnin = P.in[BX + N_];
+        pb[0] = G.base; pb[1] = G.b_t1m; pb[2] = G.b_t1p; pb[3] = G.b_t2m; pb[4] = G.b_t2p;
+        qb[0] = G.base; qb[1] = G.b_t1p; qb[2] = G.base; qb[3] = G.b_t2p;
+    }
+    __device__ __forceinline__ void load(unsigned off)
+    {
+#pragma unroll
+        for (int r = 0; r < 5; ++r) {
+            nrho[r] = rho[pb[r] + off];
+            nm[r] = mn[pb[r] + off];
+        }
+        nq[0] = bq1[qb[0] + off];
+        nq[1] = bq1[qb[1] + off];
+        nq[2] = bq2[qb[2] + off];
+        nq[3] = bq2[qb[3] + off];
+        nbn = bnin[pb[0] + off];
+    }
+    // hand the loaded values to the window (before the next load)
+    __device__ __forceinline__ void take(T v[5], T q0[4], T& bn0) const
+    {
+#pragma unroll
+        for (int r = 0; r < 5; ++r) v[r] = velocity(nm[r], nrho[r]);
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) q0[ch] = nq[ch];
+        bn0 = nbn;
+    }
+};
+
+// One lane of a grid: magnetic operator M_d.
 template <typename T, int D>
 __device__ __forceinline__ void mag_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-    const int nx = P.nx, ny = P.ny, nz = P.nz;
-    const int npencil = nx * (D == 1 ? nz : ny);
-    const int nchunk = (D == 1 ? ny : nz) / chunk;
-    if (gid >= (long)npencil * nchunk) return;
-    const int p = (int)(gid % npencil);
-    const int j0 = (int)(gid / npencil) * chunk;
-    const MarchGeom<D> G(nx, ny, nz, p);
+    int p, j0;
+    if (!march_lane_of<D>(P.nx, P.ny, P.nz, gid, chunk, p, j0)) return;
+    const MarchGeom<D> G(P.nx, P.ny, P.nz, p);
     const int nd = G.nd;
-    const T* __restrict__ rho = P.in[RHO];
-    const T* __restrict__ mn = P.in[MX + N_];
-    const T* __restrict__ bq1 = P.in[BX + T1];
-    const T* __restrict__ bq2 = P.in[BX + T2];
-    const T* __restrict__ bnin = P.in[BX + N_];
 
     if (P.flag && *P.flag) {
         for (int j = j0; j < j0 + chunk; ++j) {
@@ -649,91 +884,30 @@ __device__ __forceinline__ void mag_march_lane(const SweepParams<T>& P, long gid
     T tau, halftau, cdummy;
     step_scalars(P, tau, halftau, cdummy);
 
-    // pencils: 0 P, 1 P-t1, 2 P+t1, 3 P-t2, 4 P+t2
-    const unsigned pb[5] = { G.base, G.b_t1m, G.b_t1p, G.b_t2m, G.b_t2p };
-    // chains: 0 own-t1, 1 plus-t1, 2 own-t2, 3 plus-t2; velocity pencils
-    // (chain pencil, chain pencil - e), field q = b_e at the chain pencil
-    constexpr int vr0[4] = { 0, 2, 0, 4 };
-    constexpr int vr1[4] = { 1, 0, 3, 0 };
-    const unsigned qb[4] = { G.base, G.b_t1p, G.base, G.b_t2p };
-
-    // register window, relative to the look-ahead position L at the start
-    // of a step; the edge flux f is produced for j = L-3
-    T wm[4];                 // face velocity at L-1
-    T a3[4], a2[4];          // edge velocity at L-3, L-2
-    T q3[4], q2[4], q1[4];   // q at L-3, L-2, L-1
-    T gm[4];                 // first-order flux at L-2
-    T h4[4], h3[4], h2[4];   // half-step q at L-4, L-3, L-2
-    T fm[4];                 // edge flux at L-4 (= j-1)
-    T bnw[3];                // b_n at L-3, L-2, L-1
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-        wm[ch] = a3[ch] = a2[ch] = T(0);
-        q3[ch] = q2[ch] = q1[ch] = gm[ch] = h4[ch] = h3[ch] = h2[ch] = fm[ch] = T(0);
-    }
-    bnw[0] = bnw[1] = bnw[2] = T(0);
+    MagWindow<T> W;
+    W.init();
+    MagLoads<T, D> in(P, G);
     constexpr int U = march_unroll<T>();
     const int Lstart = march_start<U>(j0, chunk);
     int jl = Lstart < 0 ? Lstart + nd : Lstart;
-    // inputs of the next position, loaded one step ahead
-    T nrho[5], nm[5], nq[4], nbn;
-    auto prefetch = [&](int jpos) {
-        const unsigned off = G.sd * jpos;
-#pragma unroll
-        for (int r = 0; r < 5; ++r) {
-            nrho[r] = rho[pb[r] + off];
-            nm[r] = mn[pb[r] + off];
-        }
-        nq[0] = bq1[qb[0] + off];
-        nq[1] = bq1[qb[1] + off];
-        nq[2] = bq2[qb[2] + off];
-        nq[3] = bq2[qb[3] + off];
-        nbn = bnin[G.base + off];
-    };
-    prefetch(jl);
+    in.load(G.sd * jl);
     for (int L0 = Lstart; L0 <= j0 + chunk + 2; L0 += U) {
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int L = L0 + k;
-            T v[5];
-#pragma unroll
-            for (int r = 0; r < 5; ++r) v[r] = velocity(nm[r], nrho[r]);
-            T q0[4];
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) q0[ch] = nq[ch];
-            const T bn0 = nbn;
+            T v[5], q0[4], bn0;
+            in.take(v, q0, bn0);
             jl = jl + 1 == nd ? 0 : jl + 1;
-            prefetch(jl);
-
-            T f[4];
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                const T w0 = face_avg(v[vr0[ch]], v[vr1[ch]]);       // w at L
-                const T a1 = edge_avg(wm[ch], w0);                   // a at L-1
-                const T g1 = upwind_flux1(a1, q1[ch], q0[ch]);      // G1 at L-1
-                const T hq1 = sub_scaled(q1[ch], halftau, g1 - gm[ch]);   // qh at L-1
-                // edge flux at j = L-3 from a(L-3) and qh at L-4..L-1
-                f[ch] = upwind_flux2(a3[ch], h4[ch], h3[ch], h2[ch], hq1);
-                wm[ch] = w0;
-                a3[ch] = a2[ch]; a2[ch] = a1;
-                gm[ch] = g1;
-                h4[ch] = h3[ch]; h3[ch] = h2[ch]; h2[ch] = hq1;
-            }
+            in.load(G.sd * jl);
+            T nb[5];
+            W.push(v, q0, bn0, tau, halftau, nb);
             const int j = L - 3;
             if (j >= j0) {
                 const unsigned oj = G.base + G.sd * (unsigned)j;
-                // advection of b_t1, b_t2 on this pencil; constraint on b_n
-                P.out[BX + T1][oj] = sub_scaled(q3[0], tau, f[0] - fm[0]);
-                P.out[BX + T2][oj] = sub_scaled(q3[2], tau, f[2] - fm[2]);
-                const T b = add_scaled(bnw[0], tau, fm[1] - fm[0]);
-                P.out[BX + N_][oj] = add_scaled(b, tau, fm[3] - fm[2]);
+                P.out[BX + T1][oj] = nb[0];
+                P.out[BX + T2][oj] = nb[2];
+                P.out[BX + N_][oj] = nb[4];
             }
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                fm[ch] = f[ch];
-                q3[ch] = q2[ch]; q2[ch] = q1[ch]; q1[ch] = q0[ch];
-            }
-            bnw[0] = bnw[1]; bnw[1] = bnw[2]; bnw[2] = bn0;
         }
     }
 }
@@ -742,6 +916,116 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256, march_waves<T>()) mag_march_kernel(SweepParams<T> P, int chunk)
 {
     mag_march_lane<T, D>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+}
+
+// One lane of a grid: the reverse-half pair M_d then F_d in one pass.  The
+// magnetic window runs 4 positions ahead of the fluid window, whose frozen
+// Bbar comes from the new faces in registers (b_t1, b_t2 of pencils P+t1,
+// P+t2 from the plus chains) instead of from memory.  Same device functions
+// in the same order as mag_march_lane followed by fluid_march_lane, so the
+// result is bitwise that of the two operators, with the state read and
+// written once.
+//   magnetic look-ahead s: new faces at s-3;
+//   fluid look-ahead s-4 (Bbar_n needs the new b_n at s-4 and s-3): new U
+//   at s-7.
+// Fluid outputs j0 .. j0+chunk-1 need new faces at j0-3 .. j0+chunk+3, which
+// need magnetic inputs from j0-6: chunk + 13 positions.
+// positions unrolled per group, as in the single-operator marches
+template <typename T> constexpr int magfluid_unroll() { return march_unroll<T>(); }
+
+template <typename T, int D>
+__device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, long gid, int chunk)
+{
+    constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    int p, j0;
+    if (!march_lane_of<D>(P.nx, P.ny, P.nz, gid, chunk, p, j0)) return;
+    const MarchGeom<D> G(P.nx, P.ny, P.nz, p);
+    const int nd = G.nd;
+    const T* __restrict__ in_u[5] = { P.in[RHO], P.in[MX + N_], P.in[MX + T1], P.in[MX + T2], P.in[EN] };
+    T* out_u[5] = { P.out[RHO], P.out[MX + N_], P.out[MX + T1], P.out[MX + T2], P.out[EN] };
+
+    if (P.flag && *P.flag) {
+        for (int j = j0; j < j0 + chunk; ++j) {
+            const unsigned o = G.base + G.sd * j;
+            for (int q = 0; q < NFIELD; ++q) P.out[q][o] = P.in[q][o];
+        }
+        return;
+    }
+    T tau, halftau, c;
+    step_scalars(P, tau, halftau, c);
+    const T gamma = P.gamma;
+
+    MagWindow<T> WM;
+    WM.init();
+    FluidWindow<T> WF;
+    WF.init();
+    MagLoads<T, D> in(P, G);
+    constexpr int U = magfluid_unroll<T>();
+    const int total = chunk + 13;
+    const int Sstart = j0 - 6 - ((U - (total % U)) % U);
+    // load positions of the two windows (periodic; Sstart - 4 >= -13 - U)
+    int jm = Sstart % nd;
+    if (jm < 0) jm += nd;
+    int jf = (Sstart - 4) % nd;
+    if (jf < 0) jf += nd;
+    T nu[5];
+    auto load_u = [&](int jpos) {
+        const unsigned o = G.base + G.sd * jpos;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) nu[q] = in_u[q][o];
+    };
+    in.load(G.sd * jm);
+    load_u(jf);
+    // new faces at the previous magnetic output position
+    T pb_t1o = T(0), pb_t1p = T(0), pb_t2o = T(0), pb_t2p = T(0), pb_n = T(0);
+    for (int S0 = Sstart; S0 <= j0 + chunk + 6; S0 += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int s = S0 + k;
+            T v[5], q0[4], bn0, u0[5];
+            in.take(v, q0, bn0);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) u0[q] = nu[q];
+            jm = jm + 1 == nd ? 0 : jm + 1;
+            jf = jf + 1 == nd ? 0 : jf + 1;
+            in.load(G.sd * jm);
+            load_u(jf);
+
+            T nb[5];
+            WM.push(v, q0, bn0, tau, halftau, nb);
+            const int jmo = s - 3;
+            if (jmo >= j0 && jmo < j0 + chunk) {
+                const unsigned oj = G.base + G.sd * (unsigned)jmo;
+                P.out[BX + T1][oj] = nb[0];
+                P.out[BX + T2][oj] = nb[2];
+                P.out[BX + N_][oj] = nb[4];
+            }
+            // fluid at s-4: Bbar from the new faces of s-4 (and b_n of s-3)
+            T bb0[3];
+            bb0[0] = T(0.5) * (pb_n + nb[4]);
+            bb0[1] = T(0.5) * (pb_t1o + pb_t1p);
+            bb0[2] = T(0.5) * (pb_t2o + pb_t2p);
+            pb_t1o = nb[0]; pb_t1p = nb[1]; pb_t2o = nb[2]; pb_t2p = nb[3]; pb_n = nb[4];
+            T unew[5];
+            WF.push(u0, bb0, gamma, c, tau, halftau, unew);
+            const int jfo = s - 7;
+            if (jfo >= j0) {
+                const unsigned oj = G.base + G.sd * (unsigned)jfo;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) out_u[q][oj] = unew[q];
+            }
+        }
+    }
+}
+
+// the fused lane holds both register windows (~220 VGPRs in FP32): 2 waves
+// per SIMD without spills (3 waves spill ~100 VGPRs); FP64 takes 1
+template <typename T> constexpr int magfluid_waves() { return sizeof(T) == 4 ? 2 : 1; }
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256, magfluid_waves<T>()) magfluid_march_kernel(SweepParams<T> P, int chunk)
+{
+    magfluid_march_lane<T, D>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
 
 // ---------------------------------------------------------------------------
@@ -821,6 +1105,39 @@ hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& t
     return hipGetLastError();
 }
 
+// the reverse-half pair M_d then F_d in one launch; P.cfl_acc (x only)
+// adds the fused CFL epilogue
+template <typename T>
+hipError_t launch_magfluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+{
+    if (d == 0) {
+        int tpr, rpw, threads;
+        row_shape<T>(P.nx, tpr, rpw, threads);
+        const int nrows = P.ny * P.nz;
+        const int grid = (nrows + rpw - 1) / rpw;
+        const size_t lds = sizeof(T) * 25 * threads;
+        if (P.cfl_acc) {
+            if (threads % 64) return hipErrorInvalidValue;      // fused CFL needs full waves
+            hipLaunchKernelGGL((magfluid_x_kernel<T, true>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+        } else {
+            hipLaunchKernelGGL((magfluid_x_kernel<T, false>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+        }
+    } else {
+        if (P.cfl_acc) return hipErrorInvalidValue;
+        const int nd = d == 1 ? P.ny : P.nz;
+        const int npencil = P.nx * (d == 1 ? P.nz : P.ny);
+        int chunk = tune.pair_chunk[d];
+        if (chunk <= 0 || nd % chunk) chunk = nd;
+        const long lanes = (long)npencil * (nd / chunk);
+        const int grid = (int)((lanes + 255) / 256);
+        if (d == 1)
+            hipLaunchKernelGGL((magfluid_march_kernel<T, 1>), dim3(grid), dim3(256), 0, s, P, chunk);
+        else
+            hipLaunchKernelGGL((magfluid_march_kernel<T, 2>), dim3(grid), dim3(256), 0, s, P, chunk);
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // batched ensembles: persistent kernels over (box, tile) work items
 // ---------------------------------------------------------------------------
@@ -849,8 +1166,15 @@ __device__ __forceinline__ SweepParams<T> box_params(const BatchParams<T>& B, in
     return P;
 }
 
+// op 0 fluid, 1 magnetic, 2 the fused reverse-half pair (magnetic then fluid)
+template <typename T, int OP>
+constexpr int batch_waves(int d)
+{
+    return d == 0 ? 1 : (OP == 2 ? magfluid_waves<T>() : march_waves<T>());
+}
+
 template <typename T, int OP, int D>
-__global__ void __launch_bounds__(256, D == 0 ? 1 : march_waves<T>()) batch_sweep_kernel(BatchParams<T> B)
+__global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kernel(BatchParams<T> B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int g8 = gridDim.x >> 3;
@@ -865,31 +1189,37 @@ __global__ void __launch_bounds__(256, D == 0 ? 1 : march_waves<T>()) batch_swee
         if constexpr (D == 0) {
             if constexpr (OP == 0)
                 fluid_x_tile(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
-            else
+            else if constexpr (OP == 1)
                 mag_x_tile(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
+            else
+                magfluid_x_tile(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
         } else {
             const long gid = (long)it.y * blockDim.x + threadIdx.x;
             if constexpr (OP == 0)
                 fluid_march_lane<T, D>(P, gid, bd.chunk[D]);
-            else
+            else if constexpr (OP == 1)
                 mag_march_lane<T, D>(P, gid, bd.chunk[D]);
+            else
+                magfluid_march_lane<T, D>(P, gid, bd.chunk[D]);
         }
     }
+}
+
+template <typename T, int OP>
+static void launch_batch_op_dir(const BatchParams<T>& B, int d, int grid, size_t lds, hipStream_t s)
+{
+    if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 0>), dim3(grid), dim3(256), lds, s, B);
+    else if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 1>), dim3(grid), dim3(256), lds, s, B);
+    else hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 2>), dim3(grid), dim3(256), lds, s, B);
 }
 
 template <typename T>
 hipError_t launch_batch_op(const BatchParams<T>& B, int op, int d, int grid, hipStream_t s)
 {
-    const size_t lds = d == 0 ? sizeof(T) * (op == 0 ? 25 : 16) * 256 : 0;
-    if (op == 0) {
-        if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, 0, 0>), dim3(grid), dim3(256), lds, s, B);
-        else if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, 0, 1>), dim3(grid), dim3(256), lds, s, B);
-        else hipLaunchKernelGGL((batch_sweep_kernel<T, 0, 2>), dim3(grid), dim3(256), lds, s, B);
-    } else {
-        if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, 1, 0>), dim3(grid), dim3(256), lds, s, B);
-        else if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, 1, 1>), dim3(grid), dim3(256), lds, s, B);
-        else hipLaunchKernelGGL((batch_sweep_kernel<T, 1, 2>), dim3(grid), dim3(256), lds, s, B);
-    }
+    const size_t lds = d == 0 ? sizeof(T) * (op == 1 ? 16 : 25) * 256 : 0;
+    if (op == 0) launch_batch_op_dir<T, 0>(B, d, grid, lds, s);
+    else if (op == 1) launch_batch_op_dir<T, 1>(B, d, grid, lds, s);
+    else launch_batch_op_dir<T, 2>(B, d, grid, lds, s);
     return hipGetLastError();
 }
 

@@ -18,8 +18,10 @@ LIB_PATH = os.path.join(HERE, "libmhd.so")
 
 MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ENONPHYS, MHD_ESTATE = 0, -1, -2, -3, -4, -5
 MHD_F32, MHD_F64 = 0, 1
-MHD_TUNE_CHUNK_Y, MHD_TUNE_CHUNK_Z = 1, 2
+MHD_TUNE_CHUNK_Y, MHD_TUNE_CHUNK_Z, MHD_TUNE_REVERSE = 1, 2, 3
+MHD_TUNE_PAIR_CHUNK_Y, MHD_TUNE_PAIR_CHUNK_Z = 4, 5
 MHD_BATCH_GRID_X, MHD_BATCH_GRID_Y, MHD_BATCH_GRID_Z, MHD_BATCH_CHUNK = 10, 11, 12, 13
+MHD_BATCH_REVERSE = 14
 
 _lib = None
 
@@ -331,6 +333,26 @@ class Solver:
     def chunk(self, axis):
         v = ctypes.c_int(0)
         check(self.lib.mhd_get_launch(self.h, axis, ctypes.byref(v)))
+        return v.value
+
+    def set_pair_chunk(self, axis, value):
+        """march chunk of the fused reverse-half pair along axis 1 (y) or 2
+        (z); 0 = built-in"""
+        check(self.lib.mhd_set_launch(self.h, MHD_TUNE_PAIR_CHUNK_Y + axis - 1, value))
+
+    def pair_chunk(self, axis):
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_get_launch(self.h, MHD_TUNE_PAIR_CHUNK_Y + axis - 1, ctypes.byref(v)))
+        return v.value
+
+    def set_reverse(self, value):
+        """reverse-half pairs M_d F_d: 1 one fused launch each, 2 the two
+        operators in turn, 0 built-in (same results either way)"""
+        check(self.lib.mhd_set_launch(self.h, MHD_TUNE_REVERSE, value))
+
+    def reverse(self):
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_get_launch(self.h, MHD_TUNE_REVERSE, ctypes.byref(v)))
         return v.value
 
     def restrict_to(self, coarse):

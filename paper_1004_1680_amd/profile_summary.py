@@ -1,9 +1,13 @@
 """Summaries of rocprofv3 output for the MHD kernels.
 
   python -m paper_1004_1680_amd.profile_summary stats  <kernel_stats.csv> <command...>
+  python -m paper_1004_1680_amd.profile_summary trace  <kernel_trace.csv> <command...>
   python -m paper_1004_1680_amd.profile_summary traffic <fetch.csv> <write.csv> <ncell> <esize> <command...>
 
 ``stats`` prints a per-kernel table (calls, average / min / max duration).
+``trace`` does the same from the per-dispatch trace, split by launch grid,
+so that the launches of one tuned shape are averaged apart from the
+autotuner's trial shapes.
 ``counters`` turns two ``rocprofv3 --pmc`` runs of SQ counters and a kernel
 trace into a per-kernel table for the MFMA kernels: MFMA-busy fraction of
 the kernel's SIMD-cycles and LDS bank-conflict cycles per LDS-active cycle.
@@ -24,7 +28,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/sweep_kernels.h", "csrc/mhd_device.h", "csrc/sweep_f32.hip",
                   "csrc/sweep_f64.hip", "csrc/reduce_kernels.hip"]
-ALG_WORDS = {"fluid": 13, "mag": 8, "cfl_partial": 8}
+ALG_WORDS = {"fluid": 13, "mag": 8, "magfluid": 16, "cfl_partial": 8}
 COPY_BYTES = 1 << 30
 
 
@@ -49,6 +53,22 @@ def stats(path, command):
         out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                    f"{float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def trace(path, command):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        key = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+        d[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in d.values())
+    out = [f"command: {command}", "",
+           "| kernel | grid threads | workgroup | calls | avg us | min us | max us | % time |",
+           "|---|---|---|---|---|---|---|---|"]
+    for key in sorted(d, key=lambda k: -sum(d[k])):
+        v = d[key]
+        out.append(f"| {key[0]} | {key[1]} | {key[2]} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | "
+                   f"{max(v):.2f} | {100 * sum(v) / total:.2f} |")
     return "\n".join(out)
 
 
@@ -81,7 +101,8 @@ def traffic(fetch_csv, write_csv, ncell, esize, command):
         if "mhd::" not in k:
             continue
         s = short(k)
-        kind = "fluid" if "fluid" in s else ("mag" if "mag" in s else ("cfl_partial" if "cfl_partial" in s else None))
+        kind = ("magfluid" if "magfluid" in s else "fluid" if "fluid" in s else "mag" if "mag" in s
+                else "cfl_partial" if "cfl_partial" in s else None)
         if kind is None:
             continue
         rd = sum(v for v, g in F[k]) / len(F[k]) * ff
@@ -142,6 +163,8 @@ if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "stats":
         print(stats(sys.argv[2], " ".join(sys.argv[3:])))
+    elif mode == "trace":
+        print(trace(sys.argv[2], " ".join(sys.argv[3:])))
     elif mode == "traffic":
         print(traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5]),
                       " ".join(sys.argv[6:])))

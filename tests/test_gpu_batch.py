@@ -61,6 +61,27 @@ def test_batch_equals_single_boxes(M, prec, graph):
     B.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_reverse_pairs_fused_or_separate(M, prec):
+    """the batch runs each reverse-half pair M_d F_d in one launch or as two
+    operators; either way every box equals its single-grid run, which uses
+    the tier's other default (fused in FP32, separate in FP64)"""
+    say(f"case: batch reverse pairs, {prec}")
+    ss = states(DIMS)
+    ref, _ = single_runs(M, DIMS, ss, prec, 2)
+    B = M.Batch(DIMS, prec=prec)
+    other = 2 if prec == "f32" else 1
+    B.set_launch(M.MHD_BATCH_REVERSE, other)
+    assert B.launch(M.MHD_BATCH_REVERSE) == other
+    for i, s in enumerate(ss):
+        B.set_state(i, s)
+    B.run(2, graph=True)
+    B.status()
+    for i in range(len(DIMS)):
+        assert np.array_equal(B.get_state(i), ref[i]), i
+    B.close()
+
+
 @pytest.mark.parametrize("grid,chunk", [(8, 8), (64, 16), (1024, 64), (2048, 256)])
 def test_batch_launch_shape_invariance(M, grid, chunk):
     say(f"case: batch launch grid={grid} chunk={chunk}")
