@@ -161,7 +161,12 @@ def run_ensemble(args, wl, torch, mhd):
     ms_per_step = el * 1e3 / args.steps
     value = ncell * args.steps / el / 1e6
     step_alg = STEP_WORDS * 4 * ncell / (ms_per_step * 1e-3) / 1e9
-    split = (6 * (ALG_WORDS["fluid"] + ALG_WORDS["magnetic"]) + ALG_WORDS["cfl"]) * 4 * ncell
+    fused = shape["reverse"] == 1
+    # bytes of the launches a step runs: 6 or 3 split operator pairs, 0 or 3
+    # fused reverse pairs, the per-box CFL pass
+    nsplit = 3 if fused else 6
+    split = (nsplit * (ALG_WORDS["fluid"] + ALG_WORDS["magnetic"]) + (6 - nsplit) * ALG_WORDS["pair"]
+             + ALG_WORDS["cfl"]) * 4 * ncell
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -169,7 +174,9 @@ def run_ensemble(args, wl, torch, mhd):
         "data": "synthetic",
         "config": {"workload": wl["desc"], "boxes": len(dims), "cells": ncell, "cfl": args.cfl,
                    "launch": shape, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "kernel": "whole step (split operator kernels)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "whole step (" + ("3 split pairs, 3 fused reverse pairs" if fused
+                                                 else "12 split operators") + ", per-box CFL)",
                      "achieved": round(split / (ms_per_step * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(split / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

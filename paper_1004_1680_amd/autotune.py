@@ -9,8 +9,9 @@ device, problem and precision.
 * single grid: the march chunk length along y and z of the single
   operators and of the fused reverse-half pairs (the x sweeps hold whole
   rows and have no shape to choose);
-* batched ensemble: the persistent grid of the operator launches and the
-  target march chunk.
+* batched ensemble: the persistent grid of the operator launches, the
+  target march chunk and whether the reverse-half pairs run fused (fused
+  pairs pay a 13-cell warm-up per chunk, heavy for small boxes).
 
 The state is saved before tuning and restored afterwards, so tuning does not
 advance the simulation.
@@ -115,37 +116,39 @@ def tune_solver(S, cfl=0.7, steps=4, repeats=2, use_cache=True):
 
 
 def tune_batch(B, cfl=0.7, steps=3, grids=(512, 1024, 2048), chunks=(16, 32, 64, 128),
-               use_cache=True):
-    """Choose the persistent grid and the target chunk of a Batch."""
+               reverse=(1, 2), use_cache=True):
+    """Choose the persistent grid, the target chunk and whether the
+    reverse-half pairs run fused (1) or as two operators (2) for a Batch."""
     sig = ",".join(str(n[0]) + "x" + str(n[1]) + "x" + str(n[2]) for n in B.dims)
     key = f"{_device_tag()}:batch:{hash(sig) & 0xffffffff:08x}:{len(B.dims)}:{'f64' if B.prec == mhd.MHD_F64 else 'f32'}"
     db = _load()
-    if use_cache and key in db:
-        g, c = db[key]["grid"], db[key]["chunk"]
+    def apply(g, c, r):
         for k in (mhd.MHD_BATCH_GRID_X, mhd.MHD_BATCH_GRID_Y, mhd.MHD_BATCH_GRID_Z):
             B.set_launch(k, g)
         B.set_launch(mhd.MHD_BATCH_CHUNK, c)
-        return {"grid": g, "chunk": c}
+        B.set_launch(mhd.MHD_BATCH_REVERSE, r)
+
+    if use_cache and key in db and "reverse" in db[key]:
+        g, c, r = db[key]["grid"], db[key]["chunk"], db[key]["reverse"]
+        apply(g, c, r)
+        return {"grid": g, "chunk": c, "reverse": r}
     saved = [B.get_state(i) for i in range(B.nbox)]
     timings = {}
-    for g in grids:
-        for c in chunks:
-            for k in (mhd.MHD_BATCH_GRID_X, mhd.MHD_BATCH_GRID_Y, mhd.MHD_BATCH_GRID_Z):
-                B.set_launch(k, g)
-            B.set_launch(mhd.MHD_BATCH_CHUNK, c)
-            B.run(1, cfl, graph=True)
-            B.status(raise_on_nonphysical=False)
-            t0 = time.perf_counter()
-            B.run(steps, cfl, graph=True)
-            B.status(raise_on_nonphysical=False)
-            timings[(g, c)] = time.perf_counter() - t0
-    g, c = min(timings, key=timings.get)
-    for k in (mhd.MHD_BATCH_GRID_X, mhd.MHD_BATCH_GRID_Y, mhd.MHD_BATCH_GRID_Z):
-        B.set_launch(k, g)
-    B.set_launch(mhd.MHD_BATCH_CHUNK, c)
+    for r in reverse:
+        for g in grids:
+            for c in chunks:
+                apply(g, c, r)
+                B.run(1, cfl, graph=True)
+                B.status(raise_on_nonphysical=False)
+                t0 = time.perf_counter()
+                B.run(steps, cfl, graph=True)
+                B.status(raise_on_nonphysical=False)
+                timings[(g, c, r)] = time.perf_counter() - t0
+    g, c, r = min(timings, key=timings.get)
+    apply(g, c, r)
     for i, s in enumerate(saved):
         B.set_state(i, s)
-    db[key] = {"grid": g, "chunk": c,
-               "timings_ms": {f"{a}/{b}": round(v * 1e3 / steps, 3) for (a, b), v in timings.items()}}
+    db[key] = {"grid": g, "chunk": c, "reverse": r,
+               "timings_ms": {f"{a}/{b}/{e}": round(v * 1e3 / steps, 3) for (a, b, e), v in timings.items()}}
     _store(db)
-    return {"grid": g, "chunk": c}
+    return {"grid": g, "chunk": c, "reverse": r}
