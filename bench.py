@@ -114,6 +114,44 @@ def time_operator(S, op, d, dt, reps, stream, torch):
     return e0.elapsed_time(e1) / reps
 
 
+def time_components(S, n, prec, stream, reps, torch, mhd):
+    """restriction by 8 (fine -> (n/8)^3, the closure's coarsening) and the
+    conservation / div b diagnostics: average duration (ms, HIP events on
+    the solver's stream) and algorithmic bandwidth.  Restriction reads the 5
+    cell fields and the face values lying on coarse faces (1 in 8 of each
+    face field) and writes the 8 coarse fields; diagnostics read 8 fields."""
+    esize = 8 if prec == "f64" else 4
+    ncell = n ** 3
+    out = {}
+    r = 8
+    if n % (4 * r) == 0:
+        C = mhd.Solver((n // r,) * 3, prec=prec, stream=stream)
+        S.restrict_to(C)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            S.restrict_to(C)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        alg = ((5 + 3 / r) * ncell + 8 * ncell / r ** 3) * esize
+        out[f"restrict_{n}_to_{n // r}"] = {"ms": round(ms, 5), "alg_GBs": round(alg / (ms * 1e-3) / 1e9, 1),
+                                            "alg_bytes": int(alg)}
+        C.close()
+    S.diag()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        S.diag()
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["diag(sync)"] = {"ms": round(ms, 5), "alg_GBs": round(8 * esize * ncell / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
 def cpu_baseline(wl):
     import oracle
     from paper_1004_1680_amd import inputs as I
@@ -413,6 +451,7 @@ def main():
     ms_cfl_sync = e0.elapsed_time(e1) / args.kernel_reps
     kern["cfl(sync)"] = {"ms": round(ms_cfl_sync, 5),
                          "alg_GBs": round(ALG_WORDS["cfl"] * esize * ncell / (ms_cfl_sync * 1e-3) / 1e9, 1)}
+    components = time_components(S, n, wl["prec"], stream, min(args.kernel_reps, 10), torch, mhd)
     # dominant kernel: largest time per step (with fused reverse pairs every
     # kernel runs once a step, otherwise each operator runs twice)
     dom = max((k for k in kern if k != "cfl(sync)"), key=lambda k: kern[k]["ms"])
@@ -461,6 +500,7 @@ def main():
                      "alg_bytes_per_cell": ALG_WORDS[op] * esize},
         "step_hbm_frac": round(step_alg / HBM_PEAK_GBS, 4),
         "kernels": kern,
+        "components": components,
         "steps_completed": nsteps_ok,
     }
     S.close()

@@ -331,18 +331,20 @@ __global__ void __launch_bounds__(RED_THREADS) diag_partial_kernel(
     const T* __restrict__ f3, const T* __restrict__ f4, const T* __restrict__ bx_,
     const T* __restrict__ by_, const T* __restrict__ bz_, int nx, int ny, int nz, double* partial)
 {
-    const size_t N = (size_t)nx * ny * nz;
-    const size_t sy = nx, sz = (size_t)nx * ny;
+    // a field has fewer than 2^31 cells (as in the sweep kernels): 32-bit
+    // cell indices, whose divisions are far cheaper than 64-bit ones
+    const unsigned N = (unsigned)nx * ny * nz;
+    const unsigned sy = nx, sz = (unsigned)nx * ny;
     double acc[8] = { 0, 0, 0, 0, 0, 0, 0, 0 };
     double dmax = 0.0, bmax = 0.0;
-    for (size_t c = (size_t)blockIdx.x * RED_THREADS + threadIdx.x; c < N;
-         c += (size_t)gridDim.x * RED_THREADS) {
-        const int i = (int)(c % nx);
-        const int j = (int)((c / sy) % ny);
-        const int k = (int)(c / sz);
-        const size_t cx = i + 1 == nx ? c - (nx - 1) : c + 1;
-        const size_t cy = j + 1 == ny ? c - (ny - 1) * sy : c + sy;
-        const size_t cz = k + 1 == nz ? c - (size_t)(nz - 1) * sz : c + sz;
+    for (unsigned c = blockIdx.x * RED_THREADS + threadIdx.x; c < N; c += gridDim.x * RED_THREADS) {
+        const unsigned kj = c / sy;
+        const int i = (int)(c - kj * sy);
+        const int k = (int)(kj / ny);
+        const int j = (int)(kj - (unsigned)k * ny);
+        const unsigned cx = i + 1 == nx ? c - (nx - 1) : c + 1;
+        const unsigned cy = j + 1 == ny ? c - (unsigned)(ny - 1) * sy : c + sy;
+        const unsigned cz = k + 1 == nz ? c - (unsigned)(nz - 1) * sz : c + sz;
         const double bx = (double)bx_[c], by = (double)by_[c], bz = (double)bz_[c];
         acc[0] += (double)f0[c];
         acc[1] += (double)f1[c];
@@ -376,17 +378,35 @@ __global__ void __launch_bounds__(RED_THREADS) diag_partial_kernel(
     }
 }
 
-__global__ void diag_final_kernel(const double* partial, int nblocks, double h3, double* out9)
+// One block: thread t folds the partials t, t + 256, ... in that order, then
+// the wave and block combine in a fixed order (deterministic).
+__global__ void __launch_bounds__(RED_THREADS) diag_final_kernel(const double* partial, int nblocks,
+                                                                 double h3, double* out9)
 {
-    const int q = threadIdx.x;
-    if (q >= 10) return;
-    double v = partial[q];
-    for (int b = 1; b < nblocks; ++b) v = q < 8 ? v + partial[10 * b + q] : fmax(v, partial[10 * b + q]);
-    __shared__ double r[10];
-    r[q] = v;
+    double v[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) v[q] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
+#pragma unroll
+        for (int q = 0; q < 10; ++q) v[q] = q < 8 ? v[q] + partial[10 * b + q] : fmax(v[q], partial[10 * b + q]);
+    __shared__ double red[10][RED_THREADS / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        const double x = q < 8 ? wave_sum(v[q]) : wave_max(v[q]);
+        if (lane == 0) red[q][w] = x;
+    }
     __syncthreads();
-    if (q < 8) out9[q] = r[q] * h3;
-    if (q == 8) out9[8] = r[9] > 0.0 ? r[8] / r[9] : 0.0;
+    if (threadIdx.x == 0) {
+        double r[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            r[q] = red[q][0];
+            for (int ww = 1; ww < RED_THREADS / 64; ++ww) r[q] = q < 8 ? r[q] + red[q][ww] : fmax(r[q], red[q][ww]);
+        }
+        for (int q = 0; q < 8; ++q) out9[q] = r[q] * h3;
+        out9[8] = r[9] > 0.0 ? r[8] / r[9] : 0.0;
+    }
 }
 
 template <typename T>
@@ -396,7 +416,7 @@ hipError_t launch_diag(const T* const f[8], int nx, int ny, int nz, double* part
     const double h = 1.0 / (double)nx;
     hipLaunchKernelGGL(diag_partial_kernel<T>, dim3(nblocks), dim3(RED_THREADS), 0, s, f[0], f[1],
                        f[2], f[3], f[4], f[5], f[6], f[7], nx, ny, nz, partial);
-    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(64), 0, s, partial, nblocks, h * h * h, out9);
+    hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(RED_THREADS), 0, s, partial, nblocks, h * h * h, out9);
     return hipGetLastError();
 }
 template hipError_t launch_diag<float>(const float* const[8], int, int, int, double*, int, double*,
@@ -494,11 +514,100 @@ __global__ void __launch_bounds__(256) restrict_kernel(
     }
 }
 
+// R consecutive values of a fine row with 16-byte (or, for R = 2 in FP32,
+// 8-byte) loads; the row offset R * I keeps them aligned (rows start at
+// multiples of 4 values)
+template <typename T, int R>
+__device__ __forceinline__ void load_run(const T* p, T (&v)[R])
+{
+    constexpr int W = 16 / (int)sizeof(T);             // values per 16 bytes
+    if constexpr (R % W == 0) {
+        typedef T V __attribute__((ext_vector_type(W)));
+#pragma unroll
+        for (int q = 0; q < R / W; ++q) {
+            const V t = reinterpret_cast<const V*>(p)[q];
+#pragma unroll
+            for (int w = 0; w < W; ++w) v[q * W + w] = t[w];
+        }
+    } else {
+        typedef T V __attribute__((ext_vector_type(R)));
+        const V t = *reinterpret_cast<const V*>(p);
+#pragma unroll
+        for (int w = 0; w < R; ++w) v[w] = t[w];
+    }
+}
+
+// Restriction by a fixed factor R (2, 4 or 8): one thread per (field,
+// coarse cell), fields outermost so that a wave holds consecutive coarse
+// cells of one field.  A cell field sums the R^3 fine values, issuing the
+// R rows of one fine plane as vector loads before adding them; a face field
+// sums the R^2 fine faces on the coarse face.  Same sums in the same order
+// as restrict_kernel (k, then j, then i; FP64), so the same values.
+struct RestrictArgs {
+    const void* fine[8];
+    void* coarse[8];
+    int nx, ny, nz;
+};
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) restrict_fixed_kernel(RestrictArgs a)
+{
+    const int nx = a.nx, ny = a.ny;
+    const int cx = nx / R, cy = ny / R, cz = a.nz / R;
+    const size_t Nc = (size_t)cx * cy * cz;
+    const size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 8 * Nc) return;
+    const int f = (int)(g / Nc);
+    const size_t C = g - (size_t)f * Nc;
+    const int I = (int)(C % cx), J = (int)((C / cx) % cy), K = (int)(C / ((size_t)cx * cy));
+    const T* in = reinterpret_cast<const T*>(a.fine[f]);
+    T* out = reinterpret_cast<T*>(a.coarse[f]);
+    double acc = 0.0;
+    if (f < 5) {
+        const T* base = in + (size_t)R * I + (size_t)nx * ((size_t)R * J + (size_t)ny * ((size_t)R * K));
+        for (int k = 0; k < R; ++k) {
+            T v[R][R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) load_run<T, R>(base + (size_t)nx * ((size_t)j + (size_t)ny * k), v[j]);
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+#pragma unroll
+                for (int i = 0; i < R; ++i) acc += (double)v[j][i];
+        }
+        out[C] = (T)(acc / ((double)R * R * R));
+    } else {
+        const int d = f - 5, t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+        // strides of the two transverse axes
+        const size_t st[3] = { 1, (size_t)nx, (size_t)nx * ny };
+        const T* base = in + (size_t)R * I + st[1] * ((size_t)R * J) + st[2] * ((size_t)R * K);
+        T v[R][R];
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+#pragma unroll
+            for (int w = 0; w < R; ++w) v[u][w] = base[u * st[t1] + w * st[t2]];
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+#pragma unroll
+            for (int w = 0; w < R; ++w) acc += (double)v[u][w];
+        out[C] = (T)(acc / ((double)R * R));
+    }
+}
+
 template <typename T>
 hipError_t launch_restrict(const T* const fine[8], T* const coarse[8], int nx, int ny, int nz,
                            int r, hipStream_t s)
 {
     const size_t Nc = (size_t)(nx / r) * (ny / r) * (nz / r);
+    if (r == 2 || r == 4 || r == 8) {
+        RestrictArgs a;
+        for (int q = 0; q < 8; ++q) { a.fine[q] = fine[q]; a.coarse[q] = coarse[q]; }
+        a.nx = nx; a.ny = ny; a.nz = nz;
+        const unsigned blocks = (unsigned)((8 * Nc + 255) / 256);
+        if (r == 2) hipLaunchKernelGGL((restrict_fixed_kernel<T, 2>), dim3(blocks), dim3(256), 0, s, a);
+        else if (r == 4) hipLaunchKernelGGL((restrict_fixed_kernel<T, 4>), dim3(blocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((restrict_fixed_kernel<T, 8>), dim3(blocks), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     const unsigned blocks = (unsigned)((Nc + 255) / 256);
     hipLaunchKernelGGL(restrict_kernel<T>, dim3(blocks), dim3(256), 0, s, fine[0], fine[1], fine[2],
                        fine[3], fine[4], fine[5], fine[6], fine[7], coarse[0], coarse[1], coarse[2],

@@ -349,9 +349,11 @@ def test_fused_cfl_carries_a_nonphysical_record(M, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_restriction_parity(M, prec):
-    say(f"case: restrict {prec}")
-    nf, r = (64, 32, 32), 4
+@pytest.mark.parametrize("r", [2, 3, 4, 8])
+def test_restriction_parity(M, prec, r):
+    # r = 2, 4, 8: the fixed-factor kernel; r = 3: the general one
+    say(f"case: restrict by {r} {prec}")
+    nf = (16 * r, 8 * r, 8 * r)
     s = I.random_smooth(nf, seed=6)
     if prec == "f32":
         s = f32_round(s)
