@@ -166,10 +166,13 @@ int mhd_restrict(mhd_ctx *fine, mhd_ctx *coarse);
  * mhd_sweep(3..5) run: 1 = one fused launch per pair (the new faces stay
  * in registers; 9 launches per step), 2 = the two operators in turn (12
  * launches), 0 = the built-in choice (1 in FP32, 2 in FP64).
+ * key MHD_TUNE_WIDE_OFFSETS: 1 makes the y and z sweeps address memory with
+ * 64-bit arithmetic per access, as they must for fields over 4 GiB; 0 (the
+ * default) uses 32-bit byte offsets wherever they fit.
  * Results do not depend on any of these (the fused pair is bitwise the two
  * operators).  Launch-shape parameters, not part of the method. */
 enum { MHD_TUNE_CHUNK_Y = 1, MHD_TUNE_CHUNK_Z = 2, MHD_TUNE_REVERSE = 3,
-       MHD_TUNE_PAIR_CHUNK_Y = 4, MHD_TUNE_PAIR_CHUNK_Z = 5 };
+       MHD_TUNE_PAIR_CHUNK_Y = 4, MHD_TUNE_PAIR_CHUNK_Z = 5, MHD_TUNE_WIDE_OFFSETS = 6 };
 int mhd_set_launch(mhd_ctx *h, int key, int value);
 int mhd_get_launch(const mhd_ctx *h, int key, int *value);
 
@@ -218,10 +221,11 @@ int mhd_batch_time(mhd_batch *b, double *times);
  * box takes the largest divisor of its axis length <= target, >= 8), and
  * MHD_BATCH_REVERSE as MHD_TUNE_REVERSE of a single grid (1: each
  * reverse-half pair M_d F_d in one launch, 2: the two operators in turn,
- * 0: built-in, 1 in FP32 and 2 in FP64).
+ * 0: built-in, 1 in FP32 and 2 in FP64), and MHD_BATCH_WIDE_OFFSETS as
+ * MHD_TUNE_WIDE_OFFSETS.
  * Launch-shape parameters, not part of the method. */
 enum { MHD_BATCH_GRID_X = 10, MHD_BATCH_GRID_Y = 11, MHD_BATCH_GRID_Z = 12,
-       MHD_BATCH_CHUNK = 13, MHD_BATCH_REVERSE = 14 };
+       MHD_BATCH_CHUNK = 13, MHD_BATCH_REVERSE = 14, MHD_BATCH_WIDE_OFFSETS = 15 };
 int mhd_batch_set_launch(mhd_batch *b, int key, int value);
 int mhd_batch_get_launch(const mhd_batch *b, int key, int *value);
 

@@ -48,6 +48,7 @@ struct mhd_batch {
     int grid[3];
     int chunk_target;
     bool rev_fused;         // reverse-half pairs M_d F_d in one launch each
+    bool wide;              // 64-bit addressing in the marches even where 32-bit offsets fit
     hipGraph_t graph;
     hipGraphExec_t exec;
     double graph_cfl;
@@ -164,6 +165,7 @@ extern "C" mhd_batch* mhd_batch_create(int nbox, const int* dims, double gamma, 
     b->esize = prec == MHD_F64 ? sizeof(double) : sizeof(float);
     b->chunk_target = 64;
     b->rev_fused = prec == MHD_F32;
+    b->wide = false;
     b->d_boxes = nullptr;
     for (int d = 0; d < 3; ++d) { b->d_items[d] = nullptr; b->grid[d] = 1024; }
     b->buf[0] = b->buf[1] = nullptr;
@@ -354,6 +356,9 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
         P.gamma = (T)b->gamma;
         P.scal = b->scal;
         P.flag = b->flag;
+        P.offsets32 = !b->wide;
+        for (const BoxDesc& bd : b->boxes)
+            if ((unsigned long long)bd.ncell * (b->prec == MHD_F64 ? 8 : 4) > (1ull << 32)) P.offsets32 = false;
         const int grid = std::max(8, std::min(b->grid[d], (b->nitems[d] + 7) / 8 * 8));
         HIP_TRY(b, launch_batch_op<T>(P, op, d, grid, b->stream));
         if (op != 1)
@@ -467,6 +472,12 @@ extern "C" int mhd_batch_set_launch(mhd_batch* b, int key, int value)
         b->chunk_target = value;
         return build_lists(b);
     }
+    if (key == MHD_BATCH_WIDE_OFFSETS) {
+        if (value < 0 || value > 1) return mhd_fail(MHD_EINVAL, "wide-offset switch must be 0 or 1 (got %d)", value);
+        b->wide = value == 1;
+        drop_graph(b);
+        return MHD_OK;
+    }
     if (key == MHD_BATCH_REVERSE) {
         if (value < 0 || value > 2)
             return mhd_fail(MHD_EINVAL, "reverse-half choice must be 0, 1 or 2 (got %d)", value);
@@ -486,6 +497,8 @@ extern "C" int mhd_batch_get_launch(const mhd_batch* b, int key, int* value)
         *value = b->chunk_target;
     else if (key == MHD_BATCH_REVERSE)
         *value = b->rev_fused ? 1 : 2;
+    else if (key == MHD_BATCH_WIDE_OFFSETS)
+        *value = b->wide ? 1 : 0;
     else
         return mhd_fail(MHD_EINVAL, "unknown launch key %d", key);
     return MHD_OK;

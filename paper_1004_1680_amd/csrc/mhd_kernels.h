@@ -37,6 +37,7 @@ struct SweepParams {
 struct LaunchTuning {
     int chunk[3];
     int pair_chunk[3];
+    int wide;                // 1: 64-bit addressing in the marches even where 32-bit offsets fit
 };
 
 // ---------------------------------------------------------------------------
@@ -64,6 +65,7 @@ struct BatchParams {
     T gamma;
     const double* scal;           // per box: SCAL_COUNT doubles
     const int* flag;              // per box: FLAG_COUNT ints (null: never skip)
+    bool offsets32;               // every box's fields have 32-bit byte offsets
 };
 
 // op 0 fluid, 1 magnetic, 2 magnetic then fluid in one pass (the reverse-half

@@ -118,6 +118,7 @@ static void default_tuning(mhd_ctx* h)
     // the fused reverse-pair march holds two register windows: half the
     // waves per SIMD, so half the lanes fill the device
     h->tune.chunk[0] = h->tune.pair_chunk[0] = 0;
+    h->tune.wide = 0;
     for (int d = 1; d < 3; ++d) {
         const long npencil = (long)h->n[0] * h->n[3 - d];
         h->tune.chunk[d] = largest_chunk(h->n[d], npencil, 4);
@@ -708,6 +709,11 @@ extern "C" int mhd_set_launch(mhd_ctx* h, int key, int value)
         h->rev_fused = value == 0 ? default_rev_fused(h->prec) : value == 1;
         return MHD_OK;
     }
+    if (key == MHD_TUNE_WIDE_OFFSETS) {
+        if (value < 0 || value > 1) return fail(MHD_EINVAL, "wide-offset switch must be 0 or 1 (got %d)", value);
+        h->tune.wide = value;
+        return MHD_OK;
+    }
     const bool pair = key == MHD_TUNE_PAIR_CHUNK_Y || key == MHD_TUNE_PAIR_CHUNK_Z;
     if (key != MHD_TUNE_CHUNK_Y && key != MHD_TUNE_CHUNK_Z && !pair)
         return fail(MHD_EINVAL, "unknown launch key %d", key);
@@ -732,6 +738,10 @@ extern "C" int mhd_get_launch(const mhd_ctx* h, int key, int* value)
     if (!h || !value) return fail(MHD_EINVAL, "null argument");
     if (key == MHD_TUNE_REVERSE) {
         *value = h->rev_fused ? 1 : 2;
+        return MHD_OK;
+    }
+    if (key == MHD_TUNE_WIDE_OFFSETS) {
+        *value = h->tune.wide;
         return MHD_OK;
     }
     if (key == MHD_TUNE_PAIR_CHUNK_Y || key == MHD_TUNE_PAIR_CHUNK_Z) {

@@ -734,11 +734,56 @@ __device__ __forceinline__ bool march_lane_of(int nx, int ny, int nz, long gid, 
     return true;
 }
 
+// Addressing of the march kernels.  W32: every byte offset of a field fits
+// in 32 bits (FP32 grids up to 1024^3), so a load is the field's base (a
+// wave-uniform register pair) plus a 32-bit per-lane byte offset, one add
+// per pencil shared by all fields of that pencil; otherwise element offsets
+// with 64-bit address arithmetic per access.  Offsets along the pencil
+// advance by one stride per position instead of a multiply.
+template <typename T, bool W32>
+struct Addr {
+    static constexpr unsigned scale = W32 ? (unsigned)sizeof(T) : 1u;
+    static __device__ __forceinline__ T ld(const T* __restrict__ p, unsigned off)
+    {
+        if constexpr (W32) return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + off);
+        else return p[off];
+    }
+    static __device__ __forceinline__ void st(T* p, unsigned off, T v)
+    {
+        if constexpr (W32) *reinterpret_cast<T*>(reinterpret_cast<char*>(p) + off) = v;
+        else p[off] = v;
+    }
+};
+
+// a position along the pencil (periodic index j) and its scaled offset
+struct MarchPos {
+    int j;
+    unsigned off;
+    __device__ __forceinline__ void set(int jj, unsigned step)
+    {
+        j = jj;
+        off = (unsigned)jj * step;
+    }
+    __device__ __forceinline__ void next(int nd, unsigned step)
+    {
+        if (++j == nd) { j = 0; off = 0u; }
+        else off += step;
+    }
+};
+
+// the periodic index of a (possibly negative) march position
+__device__ __forceinline__ int wrap_pos(int j, int nd)
+{
+    int m = j % nd;
+    return m < 0 ? m + nd : m;
+}
+
 // One lane (pencil chunk gid) of a grid: fluid operator F_d.
-template <typename T, int D>
+template <typename T, int D, bool W32>
 __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    using A = Addr<T, W32>;
     int p, j0;
     if (!march_lane_of<D>(P.nx, P.ny, P.nz, gid, chunk, p, j0)) return;
     const MarchGeom<D> G(P.nx, P.ny, P.nz, p);
@@ -759,29 +804,35 @@ __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long g
     T tau, halftau, c;
     step_scalars(P, tau, halftau, c);
     const T gamma = P.gamma;
+    const unsigned step = G.sd * A::scale;
+    const unsigned gb = G.base * A::scale, gt1 = G.b_t1p * A::scale, gt2 = G.b_t2p * A::scale;
 
     FluidWindow<T> W;
     W.init();
     constexpr int U = march_unroll<T>();
     const int Lstart = march_start<U>(j0, chunk);
-    int jl = Lstart < 0 ? Lstart + nd : Lstart;
-    T bn_cur = bn[G.base + G.sd * jl];          // b_n at L
+    // load position L and L + 1 (b_n of the next face)
+    MarchPos pl, pn;
+    pl.set(wrap_pos(Lstart, nd), step);
+    pn = pl;
+    pn.next(nd, step);
+    T bn_cur = A::ld(bn, gb + pl.off);          // b_n at L
     // inputs of the next position, loaded one step ahead so that their
     // latency overlaps the arithmetic of the current step
     T nu[5], nbn, nt1a, nt1b, nt2a, nt2b;
-    auto prefetch = [&](int jpos) {
-        const int jn = jpos + 1 == nd ? 0 : jpos + 1;
-        const unsigned off = G.sd * jpos;
-        const unsigned o = G.base + off;
+    auto prefetch = [&]() {
+        const unsigned o = gb + pl.off;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) nu[q] = in_u[q][o];
-        nbn = bn[G.base + G.sd * jn];
-        nt1a = bt1[o];
-        nt1b = bt1[G.b_t1p + off];
-        nt2a = bt2[o];
-        nt2b = bt2[G.b_t2p + off];
+        for (int q = 0; q < 5; ++q) nu[q] = A::ld(in_u[q], o);
+        nbn = A::ld(bn, gb + pn.off);
+        nt1a = A::ld(bt1, o);
+        nt1b = A::ld(bt1, gt1 + pl.off);
+        nt2a = A::ld(bt2, o);
+        nt2b = A::ld(bt2, gt2 + pl.off);
     };
-    prefetch(jl);
+    prefetch();
+    // output offset of cell L - 3 (never wraps: outputs lie in the chunk)
+    unsigned po = gb + (unsigned)(Lstart - 3) * step;
     for (int L0 = Lstart; L0 <= j0 + chunk + 2; L0 += U) {
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -794,16 +845,16 @@ __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long g
             bb0[1] = T(0.5) * (nt1a + nt1b);
             bb0[2] = T(0.5) * (nt2a + nt2b);
             bn_cur = bn_next;
-            jl = jl + 1 == nd ? 0 : jl + 1;
-            prefetch(jl);
+            pl = pn;
+            pn.next(nd, step);
+            prefetch();
             T unew[5];
             W.push(u0, bb0, gamma, c, tau, halftau, unew);
-            const int j = L - 3;
-            if (j >= j0) {
-                const unsigned oj = G.base + G.sd * (unsigned)j;
+            if (L - 3 >= j0) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) out_u[q][oj] = unew[q];
+                for (int q = 0; q < 5; ++q) A::st(out_u[q], po, unew[q]);
             }
+            po += step;
         }
     }
 }
@@ -811,23 +862,23 @@ __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long g
 // at least 4 waves per SIMD for the FP32 march (<= 128 VGPRs), 2 for FP64
 template <typename T> constexpr int march_waves() { return sizeof(T) == 4 ? 4 : 2; }
 
-template <typename T, int D>
+template <typename T, int D, bool W32>
 __global__ void __launch_bounds__(256, march_waves<T>()) fluid_march_kernel(SweepParams<T> P, int chunk)
 {
-    fluid_march_lane<T, D>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+    fluid_march_lane<T, D, W32>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
 
 // Inputs of the magnetic window at one position: v_n of the 5 pencils, the
 // 4 chain fields and b_n.
-template <typename T, int D>
+template <typename T, int D, bool W32>
 struct MagLoads {
+    using A = Addr<T, W32>;
     const T* __restrict__ rho;
     const T* __restrict__ mn;
     const T* __restrict__ bq1;
     const T* __restrict__ bq2;
     const T* __restrict__ bnin;
-    unsigned pb[5];          // pencils: 0 P, 1 P-t1, 2 P+t1, 3 P-t2, 4 P+t2
-    unsigned qb[4];          // chain pencils
+    unsigned pb[5];          // pencils: 0 P, 1 P-t1, 2 P+t1, 3 P-t2, 4 P+t2 (scaled)
     T nrho[5], nm[5], nq[4], nbn;
 
     __device__ __forceinline__ MagLoads(const SweepParams<T>& P, const MarchGeom<D>& G)
@@ -835,21 +886,25 @@ struct MagLoads {
         constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
         rho = P.in[RHO]; mn = P.in[MX + N_];
         bq1 = P.in[BX + T1]; bq2 = P.in[BX + T2]; bnin = P.in[BX + N_];
-        pb[0] = G.base; pb[1] = G.b_t1m; pb[2] = G.b_t1p; pb[3] = G.b_t2m; pb[4] = G.b_t2p;
-        qb[0] = G.base; qb[1] = G.b_t1p; qb[2] = G.base; qb[3] = G.b_t2p;
+        pb[0] = G.base * A::scale; pb[1] = G.b_t1m * A::scale; pb[2] = G.b_t1p * A::scale;
+        pb[3] = G.b_t2m * A::scale; pb[4] = G.b_t2p * A::scale;
     }
+    // chain pencils: own-t1 P, plus-t1 P+t1, own-t2 P, plus-t2 P+t2
     __device__ __forceinline__ void load(unsigned off)
     {
+        unsigned o[5];
+#pragma unroll
+        for (int r = 0; r < 5; ++r) o[r] = pb[r] + off;
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
-            nrho[r] = rho[pb[r] + off];
-            nm[r] = mn[pb[r] + off];
+            nrho[r] = A::ld(rho, o[r]);
+            nm[r] = A::ld(mn, o[r]);
         }
-        nq[0] = bq1[qb[0] + off];
-        nq[1] = bq1[qb[1] + off];
-        nq[2] = bq2[qb[2] + off];
-        nq[3] = bq2[qb[3] + off];
-        nbn = bnin[pb[0] + off];
+        nq[0] = A::ld(bq1, o[0]);
+        nq[1] = A::ld(bq1, o[2]);
+        nq[2] = A::ld(bq2, o[0]);
+        nq[3] = A::ld(bq2, o[4]);
+        nbn = A::ld(bnin, o[0]);
     }
     // hand the loaded values to the window (before the next load)
     __device__ __forceinline__ void take(T v[5], T q0[4], T& bn0) const
@@ -863,10 +918,11 @@ struct MagLoads {
 };
 
 // One lane of a grid: magnetic operator M_d.
-template <typename T, int D>
+template <typename T, int D, bool W32>
 __device__ __forceinline__ void mag_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    using A = Addr<T, W32>;
     int p, j0;
     if (!march_lane_of<D>(P.nx, P.ny, P.nz, gid, chunk, p, j0)) return;
     const MarchGeom<D> G(P.nx, P.ny, P.nz, p);
@@ -883,40 +939,46 @@ __device__ __forceinline__ void mag_march_lane(const SweepParams<T>& P, long gid
     }
     T tau, halftau, cdummy;
     step_scalars(P, tau, halftau, cdummy);
+    const unsigned step = G.sd * A::scale;
+    const unsigned gb = G.base * A::scale;
 
     MagWindow<T> W;
     W.init();
-    MagLoads<T, D> in(P, G);
+    MagLoads<T, D, W32> in(P, G);
     constexpr int U = march_unroll<T>();
     const int Lstart = march_start<U>(j0, chunk);
-    int jl = Lstart < 0 ? Lstart + nd : Lstart;
-    in.load(G.sd * jl);
+    MarchPos pl;
+    pl.set(wrap_pos(Lstart, nd), step);
+    in.load(pl.off);
+    unsigned po = gb + (unsigned)(Lstart - 3) * step;
     for (int L0 = Lstart; L0 <= j0 + chunk + 2; L0 += U) {
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int L = L0 + k;
             T v[5], q0[4], bn0;
             in.take(v, q0, bn0);
-            jl = jl + 1 == nd ? 0 : jl + 1;
-            in.load(G.sd * jl);
+            pl.next(nd, step);
+            in.load(pl.off);
             T nb[5];
             W.push(v, q0, bn0, tau, halftau, nb);
-            const int j = L - 3;
-            if (j >= j0) {
-                const unsigned oj = G.base + G.sd * (unsigned)j;
-                P.out[BX + T1][oj] = nb[0];
-                P.out[BX + T2][oj] = nb[2];
-                P.out[BX + N_][oj] = nb[4];
+            if (L - 3 >= j0) {
+                A::st(P.out[BX + T1], po, nb[0]);
+                A::st(P.out[BX + T2], po, nb[2]);
+                A::st(P.out[BX + N_], po, nb[4]);
             }
+            po += step;
         }
     }
 }
 
-template <typename T, int D>
+template <typename T, int D, bool W32>
 __global__ void __launch_bounds__(256, march_waves<T>()) mag_march_kernel(SweepParams<T> P, int chunk)
 {
-    mag_march_lane<T, D>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+    mag_march_lane<T, D, W32>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
+
+// positions unrolled per group, as in the single-operator marches
+template <typename T> constexpr int magfluid_unroll() { return march_unroll<T>(); }
 
 // One lane of a grid: the reverse-half pair M_d then F_d in one pass.  The
 // magnetic window runs 4 positions ahead of the fluid window, whose frozen
@@ -930,13 +992,11 @@ __global__ void __launch_bounds__(256, march_waves<T>()) mag_march_kernel(SweepP
 //   at s-7.
 // Fluid outputs j0 .. j0+chunk-1 need new faces at j0-3 .. j0+chunk+3, which
 // need magnetic inputs from j0-6: chunk + 13 positions.
-// positions unrolled per group, as in the single-operator marches
-template <typename T> constexpr int magfluid_unroll() { return march_unroll<T>(); }
-
-template <typename T, int D>
+template <typename T, int D, bool W32>
 __device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    using A = Addr<T, W32>;
     int p, j0;
     if (!march_lane_of<D>(P.nx, P.ny, P.nz, gid, chunk, p, j0)) return;
     const MarchGeom<D> G(P.nx, P.ny, P.nz, p);
@@ -954,28 +1014,32 @@ __device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, lon
     T tau, halftau, c;
     step_scalars(P, tau, halftau, c);
     const T gamma = P.gamma;
+    const unsigned step = G.sd * A::scale;
+    const unsigned gb = G.base * A::scale;
 
     MagWindow<T> WM;
     WM.init();
     FluidWindow<T> WF;
     WF.init();
-    MagLoads<T, D> in(P, G);
+    MagLoads<T, D, W32> in(P, G);
     constexpr int U = magfluid_unroll<T>();
     const int total = chunk + 13;
     const int Sstart = j0 - 6 - ((U - (total % U)) % U);
-    // load positions of the two windows (periodic; Sstart - 4 >= -13 - U)
-    int jm = Sstart % nd;
-    if (jm < 0) jm += nd;
-    int jf = (Sstart - 4) % nd;
-    if (jf < 0) jf += nd;
+    // load positions of the two windows (periodic)
+    MarchPos pm, pf;
+    pm.set(wrap_pos(Sstart, nd), step);
+    pf.set(wrap_pos(Sstart - 4, nd), step);
     T nu[5];
-    auto load_u = [&](int jpos) {
-        const unsigned o = G.base + G.sd * jpos;
+    auto load_u = [&]() {
+        const unsigned o = gb + pf.off;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) nu[q] = in_u[q][o];
+        for (int q = 0; q < 5; ++q) nu[q] = A::ld(in_u[q], o);
     };
-    in.load(G.sd * jm);
-    load_u(jf);
+    in.load(pm.off);
+    load_u();
+    // output offsets of the magnetic (s - 3) and fluid (s - 7) positions
+    unsigned pmo = gb + (unsigned)(Sstart - 3) * step;
+    unsigned pfo = gb + (unsigned)(Sstart - 7) * step;
     // new faces at the previous magnetic output position
     T pb_t1o = T(0), pb_t1p = T(0), pb_t2o = T(0), pb_t2p = T(0), pb_n = T(0);
     for (int S0 = Sstart; S0 <= j0 + chunk + 6; S0 += U) {
@@ -986,20 +1050,20 @@ __device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, lon
             in.take(v, q0, bn0);
 #pragma unroll
             for (int q = 0; q < 5; ++q) u0[q] = nu[q];
-            jm = jm + 1 == nd ? 0 : jm + 1;
-            jf = jf + 1 == nd ? 0 : jf + 1;
-            in.load(G.sd * jm);
-            load_u(jf);
+            pm.next(nd, step);
+            pf.next(nd, step);
+            in.load(pm.off);
+            load_u();
 
             T nb[5];
             WM.push(v, q0, bn0, tau, halftau, nb);
             const int jmo = s - 3;
             if (jmo >= j0 && jmo < j0 + chunk) {
-                const unsigned oj = G.base + G.sd * (unsigned)jmo;
-                P.out[BX + T1][oj] = nb[0];
-                P.out[BX + T2][oj] = nb[2];
-                P.out[BX + N_][oj] = nb[4];
+                A::st(P.out[BX + T1], pmo, nb[0]);
+                A::st(P.out[BX + T2], pmo, nb[2]);
+                A::st(P.out[BX + N_], pmo, nb[4]);
             }
+            pmo += step;
             // fluid at s-4: Bbar from the new faces of s-4 (and b_n of s-3)
             T bb0[3];
             bb0[0] = T(0.5) * (pb_n + nb[4]);
@@ -1008,12 +1072,11 @@ __device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, lon
             pb_t1o = nb[0]; pb_t1p = nb[1]; pb_t2o = nb[2]; pb_t2p = nb[3]; pb_n = nb[4];
             T unew[5];
             WF.push(u0, bb0, gamma, c, tau, halftau, unew);
-            const int jfo = s - 7;
-            if (jfo >= j0) {
-                const unsigned oj = G.base + G.sd * (unsigned)jfo;
+            if (s - 7 >= j0) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) out_u[q][oj] = unew[q];
+                for (int q = 0; q < 5; ++q) A::st(out_u[q], pfo, unew[q]);
             }
+            pfo += step;
         }
     }
 }
@@ -1022,10 +1085,10 @@ __device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, lon
 // per SIMD without spills (3 waves spill ~100 VGPRs); FP64 takes 1
 template <typename T> constexpr int magfluid_waves() { return sizeof(T) == 4 ? 2 : 1; }
 
-template <typename T, int D>
+template <typename T, int D, bool W32>
 __global__ void __launch_bounds__(256, magfluid_waves<T>()) magfluid_march_kernel(SweepParams<T> P, int chunk)
 {
-    magfluid_march_lane<T, D>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+    magfluid_march_lane<T, D, W32>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1050,6 +1113,13 @@ bool fused_cfl_possible(int nx)
     return threads % 64 == 0;
 }
 
+// every byte offset of a field fits in 32 bits (the march kernels' W32 path)
+template <typename T>
+inline bool offsets32(const SweepParams<T>& P, const LaunchTuning& tune)
+{
+    return !tune.wide && (unsigned long long)P.nx * P.ny * P.nz * sizeof(T) <= (1ull << 32);
+}
+
 template <typename T>
 hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
@@ -1072,10 +1142,13 @@ hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune
         if (chunk <= 0 || nd % chunk) chunk = nd;
         const long lanes = (long)npencil * (nd / chunk);
         const int grid = (int)((lanes + 255) / 256);
-        if (d == 1)
-            hipLaunchKernelGGL((fluid_march_kernel<T, 1>), dim3(grid), dim3(256), 0, s, P, chunk);
-        else
-            hipLaunchKernelGGL((fluid_march_kernel<T, 2>), dim3(grid), dim3(256), 0, s, P, chunk);
+        if (offsets32<T>(P, tune)) {
+            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+        } else {
+            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+        }
     }
     return hipGetLastError();
 }
@@ -1097,10 +1170,13 @@ hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& t
         if (chunk <= 0 || nd % chunk) chunk = nd;
         const long lanes = (long)npencil * (nd / chunk);
         const int grid = (int)((lanes + 255) / 256);
-        if (d == 1)
-            hipLaunchKernelGGL((mag_march_kernel<T, 1>), dim3(grid), dim3(256), 0, s, P, chunk);
-        else
-            hipLaunchKernelGGL((mag_march_kernel<T, 2>), dim3(grid), dim3(256), 0, s, P, chunk);
+        if (offsets32<T>(P, tune)) {
+            if (d == 1) hipLaunchKernelGGL((mag_march_kernel<T, 1, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((mag_march_kernel<T, 2, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+        } else {
+            if (d == 1) hipLaunchKernelGGL((mag_march_kernel<T, 1, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((mag_march_kernel<T, 2, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+        }
     }
     return hipGetLastError();
 }
@@ -1130,10 +1206,13 @@ hipError_t launch_magfluid(const SweepParams<T>& P, int d, const LaunchTuning& t
         if (chunk <= 0 || nd % chunk) chunk = nd;
         const long lanes = (long)npencil * (nd / chunk);
         const int grid = (int)((lanes + 255) / 256);
-        if (d == 1)
-            hipLaunchKernelGGL((magfluid_march_kernel<T, 1>), dim3(grid), dim3(256), 0, s, P, chunk);
-        else
-            hipLaunchKernelGGL((magfluid_march_kernel<T, 2>), dim3(grid), dim3(256), 0, s, P, chunk);
+        if (offsets32<T>(P, tune)) {
+            if (d == 1) hipLaunchKernelGGL((magfluid_march_kernel<T, 1, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((magfluid_march_kernel<T, 2, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+        } else {
+            if (d == 1) hipLaunchKernelGGL((magfluid_march_kernel<T, 1, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((magfluid_march_kernel<T, 2, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+        }
     }
     return hipGetLastError();
 }
@@ -1173,7 +1252,8 @@ constexpr int batch_waves(int d)
     return d == 0 ? 1 : (OP == 2 ? magfluid_waves<T>() : march_waves<T>());
 }
 
-template <typename T, int OP, int D>
+// W32: every box's fields have 32-bit byte offsets (see Addr)
+template <typename T, int OP, int D, bool W32>
 __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kernel(BatchParams<T> B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1196,11 +1276,11 @@ __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kern
         } else {
             const long gid = (long)it.y * blockDim.x + threadIdx.x;
             if constexpr (OP == 0)
-                fluid_march_lane<T, D>(P, gid, bd.chunk[D]);
+                fluid_march_lane<T, D, W32>(P, gid, bd.chunk[D]);
             else if constexpr (OP == 1)
-                mag_march_lane<T, D>(P, gid, bd.chunk[D]);
+                mag_march_lane<T, D, W32>(P, gid, bd.chunk[D]);
             else
-                magfluid_march_lane<T, D>(P, gid, bd.chunk[D]);
+                magfluid_march_lane<T, D, W32>(P, gid, bd.chunk[D]);
         }
     }
 }
@@ -1208,9 +1288,15 @@ __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kern
 template <typename T, int OP>
 static void launch_batch_op_dir(const BatchParams<T>& B, int d, int grid, size_t lds, hipStream_t s)
 {
-    if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 0>), dim3(grid), dim3(256), lds, s, B);
-    else if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 1>), dim3(grid), dim3(256), lds, s, B);
-    else hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 2>), dim3(grid), dim3(256), lds, s, B);
+    // x tiles have no march addressing: one instantiation
+    if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 0, true>), dim3(grid), dim3(256), lds, s, B);
+    else if (B.offsets32) {
+        if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 1, true>), dim3(grid), dim3(256), lds, s, B);
+        else hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 2, true>), dim3(grid), dim3(256), lds, s, B);
+    } else {
+        if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 1, false>), dim3(grid), dim3(256), lds, s, B);
+        else hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 2, false>), dim3(grid), dim3(256), lds, s, B);
+    }
 }
 
 template <typename T>

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(HERE, "libmhd.so")
 MHD_OK, MHD_EINVAL, MHD_ENOMEM, MHD_EDEVICE, MHD_ENONPHYS, MHD_ESTATE = 0, -1, -2, -3, -4, -5
 MHD_F32, MHD_F64 = 0, 1
 MHD_TUNE_CHUNK_Y, MHD_TUNE_CHUNK_Z, MHD_TUNE_REVERSE = 1, 2, 3
-MHD_TUNE_PAIR_CHUNK_Y, MHD_TUNE_PAIR_CHUNK_Z = 4, 5
+MHD_TUNE_PAIR_CHUNK_Y, MHD_TUNE_PAIR_CHUNK_Z, MHD_TUNE_WIDE_OFFSETS = 4, 5, 6
 MHD_BATCH_GRID_X, MHD_BATCH_GRID_Y, MHD_BATCH_GRID_Z, MHD_BATCH_CHUNK = 10, 11, 12, 13
-MHD_BATCH_REVERSE = 14
+MHD_BATCH_REVERSE, MHD_BATCH_WIDE_OFFSETS = 14, 15
 
 _lib = None
 
@@ -333,6 +333,15 @@ class Solver:
     def chunk(self, axis):
         v = ctypes.c_int(0)
         check(self.lib.mhd_get_launch(self.h, axis, ctypes.byref(v)))
+        return v.value
+
+    def set_launch(self, key, value):
+        """any MHD_TUNE_* launch-shape key (results do not depend on them)"""
+        check(self.lib.mhd_set_launch(self.h, key, value))
+
+    def launch(self, key):
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_get_launch(self.h, key, ctypes.byref(v)))
         return v.value
 
     def set_pair_chunk(self, axis, value):

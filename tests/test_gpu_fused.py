@@ -180,3 +180,45 @@ def test_reverse_key_checks(M):
     S = M.Solver((16, 16, 16), prec="f64")
     assert S.reverse() == SEPARATE
     S.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("mode", [FUSED, SEPARATE])
+def test_wide_offsets_give_the_same_steps(M, prec, mode):
+    """the y and z sweeps address memory with 32-bit byte offsets where every
+    offset fits (all grids here) and with 64-bit arithmetic otherwise (fields
+    over 4 GiB); forcing the second path gives the same steps bit for bit"""
+    n = (32, 24, 40)
+    say(f"case: wide offsets {prec} reverse={mode}")
+    s = I.random_smooth(n, seed=8)
+    outs = []
+    for wide in (0, 1):
+        S = solver(M, n, prec, mode, chunk=8)
+        S.set_launch(M.MHD_TUNE_WIDE_OFFSETS, wide)
+        assert S.launch(M.MHD_TUNE_WIDE_OFFSETS) == wide
+        S.set_state(s)
+        for _ in range(3):
+            S.step_auto(0.7)
+        S.status()
+        outs.append(S.get_state())
+        S.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_batch_wide_offsets_give_the_same_steps(M):
+    dims = [(16, 16, 16), (24, 16, 32), (8, 12, 16)]
+    say("case: batch wide offsets")
+    ss = [I.random_smooth(n, seed=50 + i) for i, n in enumerate(dims)]
+    outs = []
+    for wide in (0, 1):
+        B = M.Batch(dims, prec="f32")
+        B.set_launch(M.MHD_BATCH_WIDE_OFFSETS, wide)
+        assert B.launch(M.MHD_BATCH_WIDE_OFFSETS) == wide
+        for i, st in enumerate(ss):
+            B.set_state(i, st)
+        B.run(2, graph=True)
+        B.status()
+        outs.append([B.get_state(i) for i in range(len(dims))])
+        B.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
