@@ -234,4 +234,36 @@ __device__ __forceinline__ void signal_speed64(double rho, double mx, double my,
         vmax = sp;
 }
 
+// FP32 screen of one cell for the fused CFL of the FP32 tier: bounds
+// lb <= speed <= ub of the FP64 signal speed that signal_speed64 finds for
+// the same (float) inputs, and whether the cell is surely physical there
+// (rho > 0, p > 0, everything finite; lb is meaningful only then).  Margins: the pressure of the cell may differ
+// from its FP64 value by dp = 1e-4 (gamma - 1)(|e| + m^2/(2 rho) + |B|^2/2),
+// about 100 times what the FP32 rounding of this expression can do (a few
+// units of 2^-24 of the largest term it cancels), and the other factors
+// by 1e-5 relative (each FP32 operation, the hardware reciprocal included,
+// is within 2^-23).  A cell that is surely physical and whose upper bound is
+// below a speed already found, or below the lower bound of another such
+// cell, cannot be the maximum.
+__device__ __forceinline__ void screen_speed32(float rho, float mx, float my, float mz, float e,
+                                               float bx0, float bx1, float by0, float by1, float bz0,
+                                               float bz1, float gamma, float& lb, float& ub, bool& sure)
+{
+    const float bx = 0.5f * (bx0 + bx1);
+    const float by = 0.5f * (by0 + by1);
+    const float bz = 0.5f * (bz0 + bz1);
+    const float b2 = bx * bx + by * by + bz * bz;
+    const float mm = mx * mx + my * my + mz * mz;
+    const float inv = __builtin_amdgcn_rcpf(rho);
+    const float ke = 0.5f * mm * inv, me = 0.5f * b2;
+    const float p = (gamma - 1.0f) * (e - ke - me);
+    const float dp = 1e-4f * (gamma - 1.0f) * (fabsf(e) + ke + me);
+    const float am = fmaxf(fabsf(mx), fmaxf(fabsf(my), fabsf(mz)));
+    const float x = gamma * (fmaxf(p, 0.0f) + dp) + b2;
+    const float xl = fmaxf(gamma * (p - dp) + b2, 0.0f);
+    ub = (am * inv + sqrtf(x * inv)) * 1.00001f;
+    lb = (am * inv + sqrtf(xl * inv)) * 0.99999f;
+    sure = rho > 0.0f && p > dp && isfinite(ub) && isfinite(e) && isfinite(mm) && isfinite(b2);
+}
+
 }  // namespace mhd

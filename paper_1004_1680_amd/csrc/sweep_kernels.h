@@ -191,7 +191,7 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
     if constexpr (!CFL) {
         if (!R.active) return;
     }
-    T onew[CFL ? 4 : 1][5];
+    T onew[CFL ? 4 : 1][5] = {};
     if (R.active) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
@@ -210,12 +210,42 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
         // from the values as stored; every lane of the wave takes part
         double vmax = 0.0;
         int bad = 0;
+        const int slot = blockIdx.x & (CFL_ACC_SLOTS - 1);
+        // FP32 tier: cells that surely cannot raise the maximum already in
+        // this workgroup's slot (a speed found for this state, at most the
+        // final maximum), nor exceed a cell of the wave that is evaluated,
+        // skip the FP64 evaluation; every cell that is not surely physical
+        // is evaluated, so the flag is exact too
+        double tslot = 0.0, thr = 0.0;
+        float ub[4];
+        bool sure[4];
+        if constexpr (sizeof(T) == 4) {
+            tslot = __longlong_as_double((long long)__hip_atomic_load(P.cfl_acc + slot, __ATOMIC_RELAXED,
+                                                                      __HIP_MEMORY_SCOPE_AGENT));
+            // and the largest lower bound of a surely physical cell of the wave
+            float wlb = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float lb;
+                screen_speed32(onew[k][0], onew[k][1], onew[k][2], onew[k][3], onew[k][4], fb[k][0], fb[k][1],
+                               fb[k][2], fb[k][3], fb[k][4], fb[k][5], (float)P.gamma, lb, ub[k], sure[k]);
+                sure[k] = sure[k] && R.active;
+                if (sure[k]) wlb = fmaxf(wlb, lb);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) wlb = fmaxf(wlb, __shfl_xor(wlb, o, 64));
+            thr = fmax(tslot, (double)wlb);
+        }
         if (R.active)
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                signal_speed64((double)onew[k][0], (double)onew[k][1], (double)onew[k][2], (double)onew[k][3],
-                               (double)onew[k][4], (double)fb[k][0], (double)fb[k][1], (double)fb[k][2],
-                               (double)fb[k][3], (double)fb[k][4], (double)fb[k][5], P.gamma64, vmax, bad);
+            for (int k = 0; k < 4; ++k) {
+                bool need = true;
+                if constexpr (sizeof(T) == 4) need = !sure[k] || (double)ub[k] >= thr;
+                if (need)
+                    signal_speed64((double)onew[k][0], (double)onew[k][1], (double)onew[k][2], (double)onew[k][3],
+                                   (double)onew[k][4], (double)fb[k][0], (double)fb[k][1], (double)fb[k][2],
+                                   (double)fb[k][3], (double)fb[k][4], (double)fb[k][5], P.gamma64, vmax, bad);
+            }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
@@ -223,9 +253,8 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
         }
         if ((threadIdx.x & 63) == 0) {
             // a non-negative double orders like its bit pattern
-            if (vmax > 0.0)
-                atomicMax(P.cfl_acc + (blockIdx.x & (CFL_ACC_SLOTS - 1)),
-                          (unsigned long long)__double_as_longlong(vmax));
+            if (vmax > tslot)
+                atomicMax(P.cfl_acc + slot, (unsigned long long)__double_as_longlong(vmax));
             if (bad) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, 1ull);
         }
     }

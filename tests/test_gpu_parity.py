@@ -323,6 +323,39 @@ def test_fused_cfl_follows_state_changes(M, prec):
     assert A.time() == B.time()
 
 
+SCREEN_STATES = {
+    # every cell ties for the largest signal speed
+    "uniform": lambda n: I.uniform(n, rho=1.3, v=(0.4, -0.7, 0.2), p=0.8, b=(0.5, 0.3, -0.2)),
+    # p about 1e-7 of e: the FP32 screen is never sure, every cell takes FP64
+    "cold": lambda n: I.uniform(n, rho=1.0, v=(1.0, 0.5, 0.0), p=1e-7, b=(0.0, 0.0, 0.0)),
+    # shorter waves and larger amplitudes than the default smooth state
+    "rough": lambda n: I.random_smooth(n, seed=21, amp_v=0.25, amp_b=0.2, kmax=2),
+}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kind", sorted(SCREEN_STATES))
+def test_fused_cfl_screen_is_exact(M, prec, kind):
+    """the fused CFL of the FP32 tier evaluates in FP64 only the cells that
+    may raise the running maximum or may be non-physical; the maximum and
+    the steps stay those of the full FP64 reduction, bit for bit"""
+    n = (32, 24, 16)
+    say(f"case: fused CFL screen {kind} {prec}")
+    s = SCREEN_STATES[kind](n)
+    A = M.Solver(n, prec=prec)
+    B = M.Solver(n, prec=prec)
+    A.set_state(s)
+    B.set_state(s)
+    for _ in range(4):
+        A.step_auto(0.7)
+        B.step(B.cfl_dt(0.7))
+    assert A.status() == 4
+    assert np.array_equal(A.get_state(), B.get_state())
+    assert A.time() == B.time()
+    A.close()
+    B.close()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_fused_cfl_carries_a_nonphysical_record(M, prec):
     """a non-physical state stops every step; the record survives the
