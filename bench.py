@@ -167,10 +167,40 @@ def cpu_baseline(wl):
     oracle.step(s, dt, vmax)
     el = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return {"value": round(ncell / el / 1e6, 4), "unit": "Mcell-updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"1 full step (CFL + 12 operators) of the same initial state at {n}^3, "
-                      f"FP64, OpenMP over pencils; {el:.2f} s wall"}
+    out = {"value": round(ncell / el / 1e6, 4), "unit": "Mcell-updates/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"1 full step (CFL + 12 operators) of the same initial state at {n}^3, "
+                     f"FP64, OpenMP over pencils; {el:.2f} s wall"}
+    out["single_thread"] = cpu_baseline_single_thread(wl)
+    return out
+
+
+def cpu_baseline_single_thread(wl, n=128):
+    """the oracle on one host thread, one full step of the same family at
+    128^3 (a single-core reference like the paper's one-core x86 figure),
+    in a child process started with OMP_NUM_THREADS=1"""
+    import subprocess
+    code = (
+        "import sys, time\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "import oracle\n"
+        "from paper_1004_1680_amd import inputs as I\n"
+        f"n = {n}\n"
+        + ("s = I.turbulence((n, n, n), seed=2)\n" if wl["ic"] == "turbulence" else "s = I.orszag_tang((n, n, n))\n")
+        + "oracle.load()\n"
+        "t0 = time.perf_counter()\n"
+        "dt, vmax = oracle.cfl(s)\n"
+        "oracle.step(s, dt, vmax)\n"
+        "print(time.perf_counter() - t0)\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=120, check=True)
+        el = float(r.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError) as e:
+        return {"error": str(e)[:200]}
+    return {"value": round(n ** 3 / el / 1e6, 4), "unit": "Mcell-updates/s", "cores": 1,
+            "sample": f"1 full step at {n}^3, FP64, one thread; {el:.2f} s wall"}
 
 
 def run_ensemble(args, wl, torch, mhd):
