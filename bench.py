@@ -497,9 +497,12 @@ def main():
     from paper_1004_1680_amd.profile_summary import read_traffic
     tmap = read_traffic(tpath)
     kname = {"fluid": "fluid", "magnetic": "mag", "pair": "magfluid"}[op]
+    # march kernels carry their addressing (32-bit byte offsets when a field
+    # is under 4 GiB) as a third template argument
+    w32 = "true" if ncell * esize <= 2 ** 32 else "false"
     tname = {"x": "{op}_x_kernel<{t}, false>" if op != "magnetic" else "mag_x_kernel<{t}>",
-             "y": "{op}_march_kernel<{t}, 1>", "z": "{op}_march_kernel<{t}, 2>"}[dom[-1]].format(
-        op=kname, t="double" if esize == 8 else "float")
+             "y": "{op}_march_kernel<{t}, 1, {w}>", "z": "{op}_march_kernel<{t}, 2, {w}>"}[dom[-1]].format(
+        op=kname, t="double" if esize == 8 else "float", w=w32)
     if tname in tmap:
         traffic = tmap[tname]
     step_alg = STEP_WORDS * esize * ncell / (ms_per_step * 1e-3) / 1e9
