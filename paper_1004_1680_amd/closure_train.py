@@ -103,17 +103,26 @@ class PairSet:
         self.items.extend(other.items)
 
 
-def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print):
+def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print, rollout=False):
     """training pairs from fine trajectories of the Orszag-Tang family (one
     per seed), as a PairSet; cl: the Closure of the coarse grid, whose
-    residual kernel forms the targets"""
+    residual kernel forms the targets.
+
+    rollout: also pairs whose input is the state of a plain coarse run
+    started from the restricted initial state and stepped with the same
+    coarse time steps (and relaxation speeds), paired with the same
+    restricted fine state: the coarse states a rollout actually visits,
+    whose correction includes pulling the accumulated error back toward the
+    fine solution."""
     nc = nf // r
     F = mhd.Solver((nf,) * 3, prec="f32", stream=stream)
     C = mhd.Solver((nc,) * 3, prec="f32", stream=stream)
+    Rr = mhd.Solver((nc,) * 3, prec="f32", stream=stream) if rollout else None
     pairs = PairSet(cl, nc, stream)
     for sd in seeds:
         F.set_state_tensor(I.orszag_tang_torch((nf,) * 3, seed=sd))
         t = 0.0
+        roll_alive = rollout
         for k in range(steps_per_traj):
             try:
                 F.restrict_to(C)
@@ -128,11 +137,27 @@ def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print)
                 break
             t += 2.0 * dtc
             F.restrict_to(C)
-            pairs.add(u_c, C.get_state_tensor().clone(), dtc, c)
+            u_ref = C.get_state_tensor().clone()
+            pairs.add(u_c, u_ref, dtc, c)
+            if roll_alive:
+                if k == 0:
+                    Rr.set_state_tensor(u_c)
+                else:
+                    try:
+                        Rr.cfl_dt(cfl)             # raises once the plain run is non-physical
+                        pairs.add(Rr.get_state_tensor().clone(), u_ref, dtc, c)
+                    except mhd.NonPhysicalState:
+                        log(f"[closure] seed {sd}: plain coarse rollout non-physical at step {k}")
+                        roll_alive = False
+                if roll_alive:
+                    Rr.set_relaxation_speed(c)
+                    Rr.step(dtc)
             if k % 8 == 0:
                 log(f"[closure] seed {sd} coarse step {k}: dt_c {dtc:.3e}, {nfine} fine steps")
     F.close()
     C.close()
+    if Rr is not None:
+        Rr.close()
     return pairs
 
 
@@ -449,7 +474,7 @@ def load(path, n, stream=None):
 
 def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, steps_per_traj=24,
                   val_steps=None, epochs=10, lr=1e-3, cfl=0.7, scale_mode="family", log=print,
-                  weighting="global", gate=False, short_seeds=(), short_steps=0):
+                  weighting="global", gate=False, short_seeds=(), short_steps=0, rollout=False):
     """data generation and training; returns (closure, scales, info).
     short_seeds / short_steps: further trajectories of short_steps pairs
     each, which weight the early, smooth part of the flow more."""
@@ -458,7 +483,7 @@ def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, st
     nc = nf // r
     cl = mhd.Closure((nc,) * 3, stream=stream)
     t0 = time.perf_counter()
-    pairs = generate_pairs(cl, nf, r, train_seeds, steps_per_traj, stream, cfl, log)
+    pairs = generate_pairs(cl, nf, r, train_seeds, steps_per_traj, stream, cfl, log, rollout)
     if short_seeds and short_steps:
         pairs.extend(generate_pairs(cl, nf, r, short_seeds, short_steps, stream, cfl, log))
     val = generate_pairs(cl, nf, r, (val_seed,), val_steps or steps_per_traj, stream, cfl, log)
@@ -481,7 +506,7 @@ def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, st
             "pairs": len(pairs), "data_s": t_data, "train_s": t_train, "epochs": epochs, "lr": lr,
             "train_steps": epochs * len(pairs), "val_loss_untrained": val_loss0, "history": hist,
             "val_field_residual": fe.tolist(), "scale_mode": scale_mode, "weighting": weighting,
-            "gate": None if R is None else R.tolist()}
+            "gate": None if R is None else R.tolist(), "rollout": rollout}
     del pairs, val
     return cl, scales, info
 
@@ -516,6 +541,8 @@ if __name__ == "__main__":
     t.add_argument("--gate", action="store_true", help="roughness gate on the correction")
     t.add_argument("--short-seeds", type=int, default=0, help="extra short trajectories")
     t.add_argument("--short-steps", type=int, default=0)
+    t.add_argument("--rollout", action="store_true",
+                   help="also pairs from plain coarse rollouts (the states a rollout visits)")
     t.add_argument("--out", required=True, help=".npz file for the trained closure")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
@@ -532,7 +559,7 @@ if __name__ == "__main__":
                                          epochs=args.epochs, lr=args.lr, log=say,
                                          weighting=args.weighting, gate=args.gate,
                                          short_seeds=tuple(range(args.seeds + 1, args.seeds + 1 + args.short_seeds)),
-                                         short_steps=args.short_steps)
+                                         short_steps=args.short_steps, rollout=args.rollout)
         save(args.out, cl, scales, info, info["gate"])
         print(json.dumps(info))
     else:
