@@ -221,11 +221,13 @@ int mhd_batch_time(mhd_batch *b, double *times);
  * box takes the largest divisor of its axis length <= target, >= 8), and
  * MHD_BATCH_REVERSE as MHD_TUNE_REVERSE of a single grid (1: each
  * reverse-half pair M_d F_d in one launch, 2: the two operators in turn,
- * 0: built-in, 1 in FP32 and 2 in FP64), and MHD_BATCH_WIDE_OFFSETS as
- * MHD_TUNE_WIDE_OFFSETS.
+ * 0: built-in, 1 in FP32 and 2 in FP64), the target march chunk of the
+ * fused pairs (MHD_BATCH_PAIR_CHUNK, default 128), and MHD_BATCH_WIDE_OFFSETS
+ * as MHD_TUNE_WIDE_OFFSETS.
  * Launch-shape parameters, not part of the method. */
 enum { MHD_BATCH_GRID_X = 10, MHD_BATCH_GRID_Y = 11, MHD_BATCH_GRID_Z = 12,
-       MHD_BATCH_CHUNK = 13, MHD_BATCH_REVERSE = 14, MHD_BATCH_WIDE_OFFSETS = 15 };
+       MHD_BATCH_CHUNK = 13, MHD_BATCH_REVERSE = 14, MHD_BATCH_WIDE_OFFSETS = 15,
+       MHD_BATCH_PAIR_CHUNK = 16 };
 int mhd_batch_set_launch(mhd_batch *b, int key, int value);
 int mhd_batch_get_launch(const mhd_batch *b, int key, int *value);
 

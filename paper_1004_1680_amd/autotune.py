@@ -116,39 +116,43 @@ def tune_solver(S, cfl=0.7, steps=4, repeats=2, use_cache=True):
 
 
 def tune_batch(B, cfl=0.7, steps=3, grids=(512, 1024, 2048), chunks=(16, 32, 64, 128),
-               reverse=(1, 2), use_cache=True):
-    """Choose the persistent grid, the target chunk and whether the
-    reverse-half pairs run fused (1) or as two operators (2) for a Batch."""
+               reverse=(1, 2), pair_chunks=(64, 128, 256), use_cache=True):
+    """Choose the persistent grid, the target chunk, whether the reverse-half
+    pairs run fused (1) or as two operators (2) and, fused, the target chunk
+    of the pairs, for a Batch."""
     sig = ",".join(str(n[0]) + "x" + str(n[1]) + "x" + str(n[2]) for n in B.dims)
     key = f"{_device_tag()}:batch:{hash(sig) & 0xffffffff:08x}:{len(B.dims)}:{'f64' if B.prec == mhd.MHD_F64 else 'f32'}"
     db = _load()
-    def apply(g, c, r):
+    def apply(g, c, r, pc):
         for k in (mhd.MHD_BATCH_GRID_X, mhd.MHD_BATCH_GRID_Y, mhd.MHD_BATCH_GRID_Z):
             B.set_launch(k, g)
         B.set_launch(mhd.MHD_BATCH_CHUNK, c)
         B.set_launch(mhd.MHD_BATCH_REVERSE, r)
+        B.set_launch(mhd.MHD_BATCH_PAIR_CHUNK, pc)
 
-    if use_cache and key in db and "reverse" in db[key]:
-        g, c, r = db[key]["grid"], db[key]["chunk"], db[key]["reverse"]
-        apply(g, c, r)
-        return {"grid": g, "chunk": c, "reverse": r}
+    if use_cache and key in db and "pair_chunk" in db[key]:
+        g, c, r, pc = db[key]["grid"], db[key]["chunk"], db[key]["reverse"], db[key]["pair_chunk"]
+        apply(g, c, r, pc)
+        return {"grid": g, "chunk": c, "reverse": r, "pair_chunk": pc}
     saved = [B.get_state(i) for i in range(B.nbox)]
     timings = {}
     for r in reverse:
         for g in grids:
             for c in chunks:
-                apply(g, c, r)
-                B.run(1, cfl, graph=True)
-                B.status(raise_on_nonphysical=False)
-                t0 = time.perf_counter()
-                B.run(steps, cfl, graph=True)
-                B.status(raise_on_nonphysical=False)
-                timings[(g, c, r)] = time.perf_counter() - t0
-    g, c, r = min(timings, key=timings.get)
-    apply(g, c, r)
+                # the pair chunk matters only when the pairs run fused
+                for pc in (pair_chunks if r == 1 else (pair_chunks[0],)):
+                    apply(g, c, r, pc)
+                    B.run(1, cfl, graph=True)
+                    B.status(raise_on_nonphysical=False)
+                    t0 = time.perf_counter()
+                    B.run(steps, cfl, graph=True)
+                    B.status(raise_on_nonphysical=False)
+                    timings[(g, c, r, pc)] = time.perf_counter() - t0
+    g, c, r, pc = min(timings, key=timings.get)
+    apply(g, c, r, pc)
     for i, s in enumerate(saved):
         B.set_state(i, s)
-    db[key] = {"grid": g, "chunk": c, "reverse": r,
-               "timings_ms": {f"{a}/{b}/{e}": round(v * 1e3 / steps, 3) for (a, b, e), v in timings.items()}}
+    db[key] = {"grid": g, "chunk": c, "reverse": r, "pair_chunk": pc,
+               "timings_ms": {"/".join(map(str, k)): round(v * 1e3 / steps, 3) for k, v in timings.items()}}
     _store(db)
-    return {"grid": g, "chunk": c, "reverse": r}
+    return {"grid": g, "chunk": c, "reverse": r, "pair_chunk": pc}

@@ -40,6 +40,8 @@ struct mhd_batch {
     int* flag;                    // nbox x FLAG_COUNT
     int2* d_items[3];
     int nitems[3];
+    int2* d_pitems[3];            // work lists of the fused pairs along y, z (x: d_items[0])
+    int npitems[3];
     int2* d_cfl_items;
     int n_cfl_items;
     int* d_item_first;
@@ -47,6 +49,7 @@ struct mhd_batch {
     int* partial_bad;
     int grid[3];
     int chunk_target;
+    int pair_chunk_target;
     bool rev_fused;         // reverse-half pairs M_d F_d in one launch each
     bool wide;              // 64-bit addressing in the marches even where 32-bit offsets fit
     hipGraph_t graph;
@@ -69,8 +72,10 @@ static int pick_chunk(int n, int target)
 
 static void free_lists(mhd_batch* b)
 {
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
         if (b->d_items[d]) { (void)hipFree(b->d_items[d]); b->d_items[d] = nullptr; }
+        if (b->d_pitems[d]) { (void)hipFree(b->d_pitems[d]); b->d_pitems[d] = nullptr; }
+    }
     if (b->d_boxes) { (void)hipFree(b->d_boxes); b->d_boxes = nullptr; }
 }
 
@@ -88,12 +93,14 @@ static int build_lists(mhd_batch* b)
 {
     free_lists(b);
     drop_graph(b);
-    std::vector<int2> items[3];
+    std::vector<int2> items[3], pitems[3];
     for (int i = 0; i < b->nbox; ++i) {
         BoxDesc& bd = b->boxes[i];
-        bd.chunk[0] = 0;
+        bd.chunk[0] = bd.pchunk[0] = 0;
         bd.chunk[1] = pick_chunk(bd.n[1], b->chunk_target);
         bd.chunk[2] = pick_chunk(bd.n[2], b->chunk_target);
+        bd.pchunk[1] = pick_chunk(bd.n[1], b->pair_chunk_target);
+        bd.pchunk[2] = pick_chunk(bd.n[2], b->pair_chunk_target);
         bd.tpr = bd.n[0] / 4;
         bd.rpw = std::max(1, 256 / bd.tpr);
         bd.ntile[0] = (bd.n[1] * bd.n[2] + bd.rpw - 1) / bd.rpw;
@@ -103,6 +110,11 @@ static int build_lists(mhd_batch* b)
         }
         for (int d = 0; d < 3; ++d)
             for (int t = 0; t < bd.ntile[d]; ++t) items[d].push_back(make_int2(i, t));
+        for (int d = 1; d < 3; ++d) {
+            const long lanes = (long)bd.n[0] * (d == 1 ? bd.n[2] : bd.n[1]) * (bd.n[d] / bd.pchunk[d]);
+            const int nt = (int)((lanes + 255) / 256);
+            for (int t = 0; t < nt; ++t) pitems[d].push_back(make_int2(i, t));
+        }
     }
     HIP_TRY(b, hipMalloc(&b->d_boxes, sizeof(BoxDesc) * b->nbox));
     HIP_TRY(b, hipMemcpy(b->d_boxes, b->boxes.data(), sizeof(BoxDesc) * b->nbox,
@@ -111,6 +123,12 @@ static int build_lists(mhd_batch* b)
         b->nitems[d] = (int)items[d].size();
         HIP_TRY(b, hipMalloc(&b->d_items[d], sizeof(int2) * items[d].size()));
         HIP_TRY(b, hipMemcpy(b->d_items[d], items[d].data(), sizeof(int2) * items[d].size(),
+                             hipMemcpyHostToDevice));
+    }
+    for (int d = 1; d < 3; ++d) {
+        b->npitems[d] = (int)pitems[d].size();
+        HIP_TRY(b, hipMalloc(&b->d_pitems[d], sizeof(int2) * pitems[d].size()));
+        HIP_TRY(b, hipMemcpy(b->d_pitems[d], pitems[d].data(), sizeof(int2) * pitems[d].size(),
                              hipMemcpyHostToDevice));
     }
     return MHD_OK;
@@ -164,10 +182,15 @@ extern "C" mhd_batch* mhd_batch_create(int nbox, const int* dims, double gamma, 
     b->prec = prec;
     b->esize = prec == MHD_F64 ? sizeof(double) : sizeof(float);
     b->chunk_target = 64;
+    b->pair_chunk_target = 128;
     b->rev_fused = prec == MHD_F32;
     b->wide = false;
     b->d_boxes = nullptr;
-    for (int d = 0; d < 3; ++d) { b->d_items[d] = nullptr; b->grid[d] = 1024; }
+    for (int d = 0; d < 3; ++d) {
+        b->d_items[d] = b->d_pitems[d] = nullptr;
+        b->nitems[d] = b->npitems[d] = 0;
+        b->grid[d] = 1024;
+    }
     b->buf[0] = b->buf[1] = nullptr;
     b->scal = nullptr; b->flag = nullptr;
     b->d_cfl_items = nullptr; b->d_item_first = nullptr;
@@ -351,15 +374,17 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
             P.out_base[q] = reinterpret_cast<T*>(b->buf[1 - b->cur[q]]);
         }
         P.boxes = b->d_boxes;
-        P.items = b->d_items[d];
-        P.nitems = b->nitems[d];
+        // the fused pairs along y and z have work lists of their own chunks
+        const bool pl = op == 2 && d > 0;
+        P.items = pl ? b->d_pitems[d] : b->d_items[d];
+        P.nitems = pl ? b->npitems[d] : b->nitems[d];
         P.gamma = (T)b->gamma;
         P.scal = b->scal;
         P.flag = b->flag;
         P.offsets32 = !b->wide;
         for (const BoxDesc& bd : b->boxes)
             if ((unsigned long long)bd.ncell * (b->prec == MHD_F64 ? 8 : 4) > (1ull << 32)) P.offsets32 = false;
-        const int grid = std::max(8, std::min(b->grid[d], (b->nitems[d] + 7) / 8 * 8));
+        const int grid = std::max(8, std::min(b->grid[d], (P.nitems + 7) / 8 * 8));
         HIP_TRY(b, launch_batch_op<T>(P, op, d, grid, b->stream));
         if (op != 1)
             for (int q = 0; q < 5; ++q) b->cur[q] = 1 - b->cur[q];
@@ -467,9 +492,9 @@ extern "C" int mhd_batch_set_launch(mhd_batch* b, int key, int value)
         drop_graph(b);
         return MHD_OK;
     }
-    if (key == MHD_BATCH_CHUNK) {
+    if (key == MHD_BATCH_CHUNK || key == MHD_BATCH_PAIR_CHUNK) {
         if (value < 8) return mhd_fail(MHD_EINVAL, "chunk target must be >= 8");
-        b->chunk_target = value;
+        (key == MHD_BATCH_CHUNK ? b->chunk_target : b->pair_chunk_target) = value;
         return build_lists(b);
     }
     if (key == MHD_BATCH_WIDE_OFFSETS) {
@@ -495,6 +520,8 @@ extern "C" int mhd_batch_get_launch(const mhd_batch* b, int key, int* value)
         *value = b->grid[key - MHD_BATCH_GRID_X];
     else if (key == MHD_BATCH_CHUNK)
         *value = b->chunk_target;
+    else if (key == MHD_BATCH_PAIR_CHUNK)
+        *value = b->pair_chunk_target;
     else if (key == MHD_BATCH_REVERSE)
         *value = b->rev_fused ? 1 : 2;
     else if (key == MHD_BATCH_WIDE_OFFSETS)

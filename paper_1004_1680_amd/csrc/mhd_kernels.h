@@ -49,6 +49,7 @@ struct LaunchTuning {
 struct BoxDesc {
     int n[3];
     int chunk[3];                 // march chunk along y (1) and z (2)
+    int pchunk[3];                // the same for the fused reverse-half pairs
     int tpr, rpw;                 // row-kernel shape (threads per row, rows per tile)
     int ntile[3];                 // tiles per direction
     unsigned ncell;

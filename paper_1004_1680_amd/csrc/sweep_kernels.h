@@ -1340,7 +1340,7 @@ __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kern
             else if constexpr (OP == 1)
                 mag_march_lane<T, D, W32>(P, gid, bd.chunk[D]);
             else
-                magfluid_march_lane<T, D, W32>(P, gid, bd.chunk[D]);
+                magfluid_march_lane<T, D, W32>(P, gid, bd.pchunk[D]);
         }
     }
 }

@@ -21,7 +21,7 @@ MHD_F32, MHD_F64 = 0, 1
 MHD_TUNE_CHUNK_Y, MHD_TUNE_CHUNK_Z, MHD_TUNE_REVERSE = 1, 2, 3
 MHD_TUNE_PAIR_CHUNK_Y, MHD_TUNE_PAIR_CHUNK_Z, MHD_TUNE_WIDE_OFFSETS = 4, 5, 6
 MHD_BATCH_GRID_X, MHD_BATCH_GRID_Y, MHD_BATCH_GRID_Z, MHD_BATCH_CHUNK = 10, 11, 12, 13
-MHD_BATCH_REVERSE, MHD_BATCH_WIDE_OFFSETS = 14, 15
+MHD_BATCH_REVERSE, MHD_BATCH_WIDE_OFFSETS, MHD_BATCH_PAIR_CHUNK = 14, 15, 16
 
 _lib = None
 

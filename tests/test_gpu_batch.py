@@ -73,6 +73,9 @@ def test_batch_reverse_pairs_fused_or_separate(M, prec):
     other = 2 if prec == "f32" else 1
     B.set_launch(M.MHD_BATCH_REVERSE, other)
     assert B.launch(M.MHD_BATCH_REVERSE) == other
+    # fused pairs with chunks of their own (8: the shortest, below the warm-up)
+    B.set_launch(M.MHD_BATCH_PAIR_CHUNK, 8)
+    assert B.launch(M.MHD_BATCH_PAIR_CHUNK) == 8
     for i, s in enumerate(ss):
         B.set_state(i, s)
     B.run(2, graph=True)
@@ -82,15 +85,16 @@ def test_batch_reverse_pairs_fused_or_separate(M, prec):
     B.close()
 
 
-@pytest.mark.parametrize("grid,chunk", [(8, 8), (64, 16), (1024, 64), (2048, 256)])
-def test_batch_launch_shape_invariance(M, grid, chunk):
-    say(f"case: batch launch grid={grid} chunk={chunk}")
+@pytest.mark.parametrize("grid,chunk,pchunk", [(8, 8, 256), (64, 16, 8), (1024, 64, 128), (2048, 256, 32)])
+def test_batch_launch_shape_invariance(M, grid, chunk, pchunk):
+    say(f"case: batch launch grid={grid} chunk={chunk} pair chunk={pchunk}")
     ss = states(DIMS)
     ref, _ = single_runs(M, DIMS, ss, "f32", 2)
     B = M.Batch(DIMS, prec="f32")
     for key in (M.MHD_BATCH_GRID_X, M.MHD_BATCH_GRID_Y, M.MHD_BATCH_GRID_Z):
         B.set_launch(key, grid)
     B.set_launch(M.MHD_BATCH_CHUNK, chunk)
+    B.set_launch(M.MHD_BATCH_PAIR_CHUNK, pchunk)
     for i, s in enumerate(ss):
         B.set_state(i, s)
     B.run(2, graph=True)
