@@ -119,7 +119,10 @@ int mhd_fluid(mhd_ctx *h, int dim, double dt);
 int mhd_magnetic(mhd_ctx *h, int dim, double dt);
 
 /* One sweep (section II.B): dim 0,1,2 = fluid then magnetic along x, y, z;
- * dim 3,4,5 = magnetic then fluid along x, y, z.  Asynchronous. */
+ * dim 3,4,5 = magnetic then fluid along x, y, z.  dim 6 = dim 3 with the
+ * CFL maximum of the resulting state found on the way (what the last
+ * launch of a step does); the next mhd_step_auto then takes its dt from it
+ * instead of a separate reduction.  Asynchronous. */
 int mhd_sweep(mhd_ctx *h, int dim, double dt);
 
 /* Full step of 2*dt (section II.B; section IV.A): sweeps x, y, z, then

@@ -528,10 +528,23 @@ extern "C" int mhd_magnetic(mhd_ctx* h, int dim, double dt)
 
 extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
 {
-    if (dim < 0 || dim > 5) return fail(MHD_EINVAL, "sweep code must be 0..5 (got %d)", dim);
+    if (dim < 0 || dim > 6) return fail(MHD_EINVAL, "sweep code must be 0..6 (got %d)", dim);
     int r = prepare_host_dt(h, dt, true);
     if (r) return r;
     h->acc_valid = false;
+    if (dim == 6) {
+        // the reverse x pair with the fused CFL of its result
+        unsigned long long* acc = h->fuse_ok ? h->cfl_acc : nullptr;
+        if (acc) HIP_TRY(h, launch_clear_acc(acc, h->stream));
+        if (h->rev_fused) {
+            HIP_TRY(h, op(h, 2, 0, nullptr, acc));
+        } else {
+            HIP_TRY(h, op(h, 1, 0, nullptr));
+            HIP_TRY(h, op(h, 0, 0, nullptr, acc));
+        }
+        h->acc_valid = h->fuse_ok;
+        return MHD_OK;
+    }
     const int d = dim % 3;
     if (dim < 3) {
         HIP_TRY(h, op(h, 0, d, nullptr));

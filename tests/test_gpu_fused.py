@@ -222,3 +222,28 @@ def test_batch_wide_offsets_give_the_same_steps(M):
         B.close()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("mode", [FUSED, SEPARATE])
+def test_sweep_with_fused_cfl(M, prec, mode):
+    """sweep code 6 (the reverse x pair that also finds the CFL maximum of
+    its result, the last launch of a step) followed by device-dt steps equals
+    sweep code 3 followed by the same steps, whose first CFL is then a
+    separate reduction"""
+    n = (32, 24, 16)
+    say(f"case: sweep 6 {prec} reverse={mode}")
+    s = I.random_smooth(n, seed=14)
+    outs = []
+    for code in (6, 3):
+        S = solver(M, n, prec, mode)
+        S.set_state(s)
+        dt = 0.5 * S.cfl_dt(0.7)
+        S.sweep(code, dt)
+        for _ in range(2):
+            S.step_auto(0.7)
+        assert S.status() == 2
+        outs.append((S.get_state(), S.time()))
+        S.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
