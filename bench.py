@@ -155,6 +155,32 @@ def time_components(S, n, prec, stream, reps, torch, mhd):
     return out
 
 
+def step_launches(S, n, esize, fused, w32):
+    """(kernel name, grid threads) of every sweep launch of one step of an
+    n^3 grid, in the profiler's naming"""
+    t = "double" if esize == 8 else "float"
+    tpr = n // 4
+    rpw = max(1, 256 // tpr)
+    xgrid = -(-(n * n) // rpw) * rpw * tpr
+
+    def march(chunk):
+        lanes = n * n * (n // chunk)
+        return -(-lanes // 256) * 256
+
+    fx = (f"fluid_x_kernel<{t}, false>", xgrid)
+    mx = (f"mag_x_kernel<{t}>", xgrid)
+    fy = (f"fluid_march_kernel<{t}, 1, {w32}>", march(S.chunk(1)))
+    my = (f"mag_march_kernel<{t}, 1, {w32}>", march(S.chunk(1)))
+    fz = (f"fluid_march_kernel<{t}, 2, {w32}>", march(S.chunk(2)))
+    mz = (f"mag_march_kernel<{t}, 2, {w32}>", march(S.chunk(2)))
+    if fused:
+        return [fx, mx, fy, my, fz, mz,
+                (f"magfluid_march_kernel<{t}, 2, {w32}>", march(S.pair_chunk(2))),
+                (f"magfluid_march_kernel<{t}, 1, {w32}>", march(S.pair_chunk(1))),
+                (f"magfluid_x_kernel<{t}, true>", xgrid)]
+    return [fx, mx, fy, my, fz, mz, mz, fz, my, fy, mx, (f"fluid_x_kernel<{t}, true>", xgrid)]
+
+
 def cpu_baseline(wl):
     import oracle
     from paper_1004_1680_amd import inputs as I
@@ -520,6 +546,18 @@ def main():
     if tname in tmap:
         traffic = tmap[tname]
     step_alg = STEP_WORDS * esize * ncell / (ms_per_step * 1e-3) / 1e9
+    # measured HBM bytes of a whole step: the profiled traffic of each launch
+    # the step makes, at its launch grid (null if any is missing)
+    step_traffic = None
+    if tmap:
+        tot = 0
+        for name, grid in step_launches(S, n, esize, fused, w32):
+            b = tmap.get(f"{name} @ {grid}", tmap.get(name))
+            if b is None:
+                tot = None
+                break
+            tot += b
+        step_traffic = tot
 
     out = {
         "metric": METRIC,
@@ -546,6 +584,10 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_cell": ALG_WORDS[op] * esize},
         "step_hbm_frac": round(step_alg / HBM_PEAK_GBS, 4),
+        "step_traffic": None if step_traffic is None else {
+            "bytes": int(step_traffic),
+            "achieved_GBs": round(step_traffic / (ms_per_step * 1e-3) / 1e9, 1),
+            "frac": round(step_traffic / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels": kern,
         "components": components,
         "steps_completed": nsteps_ok,

@@ -111,6 +111,12 @@ def traffic(fetch_csv, write_csv, ncell, esize, command):
         out.append(f"| {s} | {rd / 2**20:.1f} | {wr / 2**20:.1f} | {alg / 2**20:.1f} | "
                    f"{(rd + wr) / alg:.3f} |")
         out.append(f"traffic_bytes[{s}] = {int(rd + wr)}")
+        # per launch grid (a march kernel's traffic depends on its chunk length)
+        for grid in sorted({g for v, g in F[k]}):
+            r_g = [v for v, g in F[k] if g == grid]
+            w_g = [v for v, g in W.get(k, []) if g == grid]
+            tot = sum(r_g) / len(r_g) * ff + (sum(w_g) / len(w_g) * fw if w_g else 0.0)
+            out.append(f"traffic_bytes[{s} @ {grid}] = {int(tot)}")
     return "\n".join(out)
 
 
@@ -143,8 +149,9 @@ def counters(pmc1_csv, pmc2_csv, stats_csv, command):
 
 
 def read_traffic(path):
-    """{kernel: bytes per launch} from a traffic summary, or {} if the kernel
-    sources have changed since it was written"""
+    """{kernel: bytes per launch} (also {"kernel @ grid threads": bytes} per
+    launch shape) from a traffic summary, or {} if the kernel sources have
+    changed since it was written"""
     if not os.path.exists(path):
         return {}
     txt = open(path).read()
