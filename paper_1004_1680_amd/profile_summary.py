@@ -81,10 +81,12 @@ def per_kernel(path, counter):
 
 
 def copy_factor(d):
-    """bytes moved / bytes counted for the 1 GiB copy dispatches"""
+    """bytes moved / bytes counted for the 1 GiB copies that bench.py
+    --calibrate-copy makes after all other work: the last three copy
+    dispatches of the run (the median of them)"""
     vals = [v for k, lst in d.items() if "copyBuffer" in k for v, g in lst]
-    big = [v for v in vals if v > 0.25 * COPY_BYTES]
-    ref = max(big) if big else None
+    last = sorted(vals[-3:])
+    ref = last[len(last) // 2] if last else None
     return COPY_BYTES / ref if ref else None
 
 
