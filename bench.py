@@ -25,6 +25,10 @@ plain 128^3 / 256^3 / 512^3 runs (learned vs plain at equal L1).
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
                        [--workload turb256|ot512|ot1024|turb256-f64|ensemble64|closure128]
                        [--no-cpu] [--closure-weights W.npz [--closure-eval]]
+       python bench.py --size-sweep default|16,32,... [--sweep-prec f32|f64]
+           (ms per step against n^3 with the paper's four criteria: code and
+            fractional speed-up against the one-thread oracle, FLOPS and
+            bandwidth fractions from the paper's per-cell counts)
 """
 import argparse
 import json
@@ -421,6 +425,122 @@ def cpu_baseline_closure():
                       f"projection); {el:.2f} s wall"}
 
 
+SWEEP_SIZES = (16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
+ORACLE_1CORE_SIZES = (16, 32, 64, 128)   # the sizes of the paper's one-core x86 column
+
+
+def cpu_baseline_sizes(ic, sizes=ORACLE_1CORE_SIZES):
+    """the oracle on one host thread, one full step at each size (the
+    counterpart of the paper's one-core x86 times), in a child process
+    started with OMP_NUM_THREADS=1; returns {n: ms}"""
+    import subprocess
+    code = (
+        "import sys, time\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "import oracle\n"
+        "from paper_1004_1680_amd import inputs as I\n"
+        "oracle.load()\n"
+        f"for n in {tuple(sizes)!r}:\n"
+        + ("    s = I.turbulence((n, n, n), seed=2)\n" if ic == "turbulence"
+           else "    s = I.orszag_tang((n, n, n))\n")
+        + "    t0 = time.perf_counter()\n"
+        "    dt, vmax = oracle.cfl(s)\n"
+        "    oracle.step(s, dt, vmax)\n"
+        "    print(n, (time.perf_counter() - t0) * 1e3, flush=True)\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=300, check=True)
+    except subprocess.SubprocessError as e:
+        log(f"[sweep] one-core oracle failed: {str(e)[:200]}")
+        return {}
+    out = {}
+    for line in r.stdout.splitlines():
+        a = line.split()
+        if len(a) == 2:
+            out[int(a[0])] = float(a[1])
+    return out
+
+
+def run_size_sweep(args, torch, mhd):
+    """Time per full step against box length n^3 (the paper's Fig. 1 and
+    Table 3) with the four criteria of its section IV.A at each size."""
+    from paper_1004_1680_amd import autotune
+    from paper_1004_1680_amd import criteria as C
+    prec = args.sweep_prec
+    esize = 8 if prec == "f64" else 4
+    sizes = SWEEP_SIZES if args.size_sweep == "default" else tuple(int(x) for x in args.size_sweep.split(","))
+    stream = torch.cuda.current_stream()
+    peak = C.FP64_VECTOR_PEAK_GFLOPS if prec == "f64" else C.FP32_VECTOR_PEAK_GFLOPS
+    core_peak, core_desc = C.host_core_peak_gflops()
+    one_core = {} if args.no_cpu else cpu_baseline_sizes("orszag_tang")
+    recs = []
+    for n in sizes:
+        ncell = n ** 3
+        log(f"[sweep] n={n} {prec}")
+        S = mhd.Solver((n, n, n), prec=prec, stream=stream)
+        st = make_state_device(dict(n=n, prec=prec, ic="orszag_tang"), torch)
+        S.set_state_tensor(st)
+        torch.cuda.synchronize()
+        if not args.no_tune:
+            autotune.tune_solver(S, args.cfl, use_cache=False)
+        S.set_state_tensor(st)
+        for _ in range(3):
+            S.step_auto(args.cfl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            S.step_auto(args.cfl)
+        torch.cuda.synchronize()
+        est = (time.perf_counter() - t0) / 3
+        k = int(min(500, max(10, args.sweep_seconds / est)))
+        # timed in blocks of at most 50 steps, each from the initial state
+        # (restored outside the timed region; its first step makes a separate
+        # CFL pass): the Orszag-Tang flow stays smooth over a block, while
+        # hundreds of steps carry a small box into its current-sheet phase
+        el, done = 0.0, 0
+        while done < k:
+            b = min(50, k - done)
+            S.set_state_tensor(st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(b):
+                S.step_auto(args.cfl)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            S.status()
+            done += b
+        S.close()
+        del st
+        torch.cuda.empty_cache()
+        ms = el * 1e3 / k
+        t1 = one_core.get(n)
+        c = C.criteria(ms, t1, ncell, peak, C.HBM_PEAK_GBS, core_peak,
+                       bytes_per_cell=esize * C.PAPER_FLOATS_PER_CELL_STEP)
+        recs.append({"n": n, "steps": k, "ms_per_step": ms, "mcell_s": ncell * k / el / 1e6,
+                     "alg_hbm_frac": STEP_WORDS * esize * ncell / (ms * 1e-3) / 1e9 / C.HBM_PEAK_GBS,
+                     "oracle_1core_ms": t1, "criteria": c})
+        log(f"[sweep] n={n}: {ms:.4f} ms/step over {k} steps")
+    big = [r for r in recs if r["n"] >= args.sweep_slope_from]
+    rec = {
+        "command": "python3 bench.py " + " ".join(sys.argv[1:]),
+        "workload": "3D Orszag-Tang-type state at each n^3",
+        "dtype": prec,
+        "sizes": recs,
+        "slope_all": C.size_slope([r["n"] for r in recs], [r["ms_per_step"] for r in recs]) if len(recs) > 1 else None,
+        "slope_from": args.sweep_slope_from,
+        "slope_large": C.size_slope([r["n"] for r in big], [r["ms_per_step"] for r in big]) if len(big) > 1 else None,
+        "peak_gflops": peak, "peak_gbs": C.HBM_PEAK_GBS,
+        "host_core": core_desc, "host_core_gflops": core_peak,
+        "units": "decimal (1e9) throughout; the paper's own totals use 2^30",
+    }
+    out = {"metric": "ms per full step vs box size; the paper's four criteria", "unit": "ms/step",
+           "higher_is_better": False, "n_gpus": 1, "dtype": prec, "data": "synthetic",
+           "config": {"workload": rec["workload"], "sizes": list(sizes), "cfl": args.cfl},
+           "size_sweep": rec}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,6 +556,14 @@ def main():
                     help="closure128: also evaluate learned vs plain against the 1024^3 solution")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--size-sweep", default=None, metavar="SIZES",
+                    help="time a full step at each n^3 (comma list, or 'default': "
+                         + ",".join(map(str, SWEEP_SIZES)) + ") with the paper's four criteria")
+    ap.add_argument("--sweep-prec", default="f32", choices=("f32", "f64"))
+    ap.add_argument("--sweep-seconds", type=float, default=0.5,
+                    help="size sweep: timed seconds per size (10..500 steps)")
+    ap.add_argument("--sweep-slope-from", type=int, default=128,
+                    help="size sweep: smallest n of the large-box slope fit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -445,6 +573,8 @@ def main():
     import torch
     from paper_1004_1680_amd import mhd
 
+    if args.size_sweep:
+        return run_size_sweep(args, torch, mhd)
     wl = WORKLOADS[args.workload]
     if wl["ic"] == "ensemble":
         return run_ensemble(args, wl, torch, mhd)

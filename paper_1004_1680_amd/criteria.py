@@ -1,0 +1,141 @@
+"""The paper's four performance criteria and its time-vs-box-size fit
+(section IV.A, Table 5 and Fig. 1), applied to measured step times.
+
+* code speed-up: one-core x86 time of a step / the architecture's time;
+* fractional speed-up: code speed-up / (peak FLOPS of the architecture /
+  peak FLOPS of the one x86 core);
+* FLOPS fraction: achieved FLOPS / peak, with the paper's count of
+  operations per cell and step (466 additions, 598 subtractions, 1174
+  multiplications, 125 divisions and 3 square roots, each counted as one
+  flop: 2366 per cell for CFL + 6 fluid + 6 magnetic updates);
+* bandwidth fraction: achieved bytes per second / peak bandwidth, with the
+  paper's count of floats moved per cell and step (CFL 11 reads, fluid 10
+  reads + 5 writes, magnetic 14 reads + 6 writes, memory transpose 8 reads +
+  8 writes; 6 fluid, 6 magnetic and 4 transposes: 285 floats).
+
+The paper's "Giga" in its operation and byte totals is 2^30 (2366 x 128^3 /
+2^30 = 4.62 and 285 x 4 x 128^3 / 2^30 = 2.23), while the peaks it divides
+by are decimal; `giga` selects the unit, 1e9 for consistent fractions.
+
+Also: a least-squares slope of log(time) against log(box length) (the
+paper's figure fits slope 3, the cost of N^3 cells).
+
+Measurement helper only: no part of the solver path.
+"""
+import math
+import os
+
+PAPER_FLOP_PER_CELL_STEP = 466 + 598 + 1174 + 125 + 3
+PAPER_FLOATS_PER_CELL_STEP = 11 + 6 * (10 + 5) + 6 * (14 + 6) + 4 * (8 + 8)
+
+# MI355X published peaks
+FP32_VECTOR_PEAK_GFLOPS = 157300.0
+FP64_VECTOR_PEAK_GFLOPS = 78600.0
+HBM_PEAK_GBS = 8000.0
+
+
+def criteria(t_ms, t_ref_ms, ncell, peak_gflops, peak_gbs, ref_peak_gflops,
+             flop_per_cell=PAPER_FLOP_PER_CELL_STEP,
+             bytes_per_cell=4 * PAPER_FLOATS_PER_CELL_STEP, giga=1e9):
+    """The four criteria of one step that takes t_ms on the architecture and
+    t_ref_ms on one x86 core (t_ref_ms None: the two speed-ups are None)."""
+    gflops = flop_per_cell * ncell / giga / (t_ms * 1e-3)
+    gbs = bytes_per_cell * ncell / giga / (t_ms * 1e-3)
+    out = {"gflops": gflops, "flops_fraction": gflops / peak_gflops,
+           "gbs": gbs, "bandwidth_fraction": gbs / peak_gbs,
+           "code_speedup": None, "fractional_speedup": None}
+    if t_ref_ms is not None:
+        s = t_ref_ms / t_ms
+        out["code_speedup"] = s
+        if ref_peak_gflops:
+            out["fractional_speedup"] = s / (peak_gflops / ref_peak_gflops)
+    return out
+
+
+def size_slope(ns, ts):
+    """least-squares slope of log t against log n"""
+    if len(ns) < 2:
+        raise ValueError("need two sizes")
+    xs = [math.log(n) for n in ns]
+    ys = [math.log(t) for t in ts]
+    mx = sum(xs) / len(xs)
+    my = sum(ys) / len(ys)
+    sxx = sum((x - mx) ** 2 for x in xs)
+    if sxx == 0:
+        raise ValueError("sizes must differ")
+    return sum((x - mx) * (y - my) for x, y in zip(xs, ys)) / sxx
+
+
+def host_core_peak_gflops(cpuinfo="/proc/cpuinfo",
+                          freq="/sys/devices/system/cpu/cpu0/cpufreq/cpuinfo_max_freq"):
+    """An estimate of one host core's FP32 peak: clock x 2 FMA pipes x SIMD
+    lanes (16 with AVX-512, 8 with AVX2, 4 otherwise) x 2 flops per FMA.
+    Returns (gflops, description); gflops None when nothing is readable."""
+    model, flags, mhz = "unknown", set(), []
+    try:
+        with open(cpuinfo) as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k == "model name" and model == "unknown":
+                    model = v.strip()
+                elif k == "flags" and not flags:
+                    flags = set(v.split())
+                elif k == "cpu MHz":
+                    try:
+                        mhz.append(float(v))
+                    except ValueError:
+                        pass
+    except OSError:
+        return None, "no /proc/cpuinfo"
+    ghz, src = None, None
+    if os.path.exists(freq):
+        try:
+            with open(freq) as f:
+                ghz, src = int(f.read().strip()) / 1e6, "cpufreq max"
+        except (OSError, ValueError):
+            ghz = None
+    if ghz is None and mhz:
+        ghz, src = max(mhz) / 1e3, "max cpu MHz in /proc/cpuinfo"
+    if ghz is None:
+        return None, f"{model}: no clock readable"
+    lanes = 16 if "avx512f" in flags else 8 if "avx2" in flags else 4
+    fl = ghz * 2 * lanes * 2
+    return fl, (f"{model}: {ghz:.2f} GHz ({src}) x 2 FMA pipes x {lanes} FP32 lanes x 2 "
+                f"= {fl:.0f} GFLOP/s (estimate)")
+
+
+def markdown(rec):
+    """a size sweep record (bench.py --size-sweep) as a markdown summary"""
+    lines = [f"Command: {rec['command']}", "",
+             f"State: {rec['workload']}; {rec['dtype']}; time per full step (CFL + 12 operators), "
+             f"wall clock over K back-to-back device-dt steps after warm-up.", "",
+             "| n | steps | ms/step | Mcell-updates/s | GFLOP/s (2366/cell) | FLOPS frac | "
+             "GB/s (paper 1140 B model) | BW frac | alg. HBM frac | 1-core oracle ms | code speed-up | "
+             "fractional speed-up |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+
+    def f(x, fmt):
+        return "-" if x is None else format(x, fmt)
+    for r in rec["sizes"]:
+        c = r["criteria"]
+        lines.append(f"| {r['n']} | {r['steps']} | {r['ms_per_step']:.4f} | {r['mcell_s']:.1f} | "
+                     f"{c['gflops']:.0f} | {c['flops_fraction']:.4f} | {c['gbs']:.0f} | "
+                     f"{c['bandwidth_fraction']:.3f} | {r['alg_hbm_frac']:.3f} | "
+                     f"{f(r.get('oracle_1core_ms'), '.1f')} | {f(c['code_speedup'], '.0f')} | "
+                     f"{f(c['fractional_speedup'], '.2f')} |")
+    lines += ["", f"Slope of log(ms/step) vs log(n): all sizes {rec['slope_all']:.3f}; "
+              f"n >= {rec['slope_from']}: {rec['slope_large']:.3f} (N^3 work: 3).",
+              f"Peaks: {rec['peak_gflops']:.0f} GFLOP/s vector, {rec['peak_gbs']:.0f} GB/s HBM; "
+              f"one host core: {rec['host_core']}."]
+    return "\n".join(lines) + "\n"
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+    with open(sys.argv[1]) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("{") and '"size_sweep"' in line:
+                sys.stdout.write(markdown(json.loads(line)["size_sweep"]))
