@@ -888,11 +888,17 @@ __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long g
     }
 }
 
-// at least 4 waves per SIMD for the FP32 march (<= 128 VGPRs), 2 for FP64
+// at least 4 waves per SIMD for the FP32 magnetic march (<= 128 VGPRs), 2 for FP64
 template <typename T> constexpr int march_waves() { return sizeof(T) == 4 ? 4 : 2; }
 
+// the FP32 fluid window needs ~130 VGPRs: 3 waves per SIMD without spills
+// (a 4-wave bound spills 3 registers per lane and made the z march 9% slower
+// at 256^3, no faster at 512^3; the persistent ensemble kernel keeps 4 waves,
+// where 3 made the ensemble step 12% slower)
+template <typename T> constexpr int fluid_march_waves() { return sizeof(T) == 4 ? 3 : 2; }
+
 template <typename T, int D, bool W32>
-__global__ void __launch_bounds__(256, march_waves<T>()) fluid_march_kernel(SweepParams<T> P, int chunk)
+__global__ void __launch_bounds__(256, fluid_march_waves<T>()) fluid_march_kernel(SweepParams<T> P, int chunk)
 {
     fluid_march_lane<T, D, W32>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
