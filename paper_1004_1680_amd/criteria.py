@@ -109,7 +109,8 @@ def markdown(rec):
     """a size sweep record (bench.py --size-sweep) as a markdown summary"""
     lines = [f"Command: {rec['command']}", "",
              f"State: {rec['workload']}; {rec['dtype']}; time per full step (CFL + 12 operators), "
-             f"wall clock over K back-to-back device-dt steps after warm-up.", "",
+             f"wall clock over K device-dt steps after warm-up, timed in blocks of at most 50 "
+             f"steps that each start from the initial state.", "",
              "| n | steps | ms/step | Mcell-updates/s | GFLOP/s (2366/cell) | FLOPS frac | "
              "GB/s (paper 1140 B model) | BW frac | alg. HBM frac | 1-core oracle ms | code speed-up | "
              "fractional speed-up |",
@@ -124,8 +125,8 @@ def markdown(rec):
                      f"{c['bandwidth_fraction']:.3f} | {r['alg_hbm_frac']:.3f} | "
                      f"{f(r.get('oracle_1core_ms'), '.1f')} | {f(c['code_speedup'], '.0f')} | "
                      f"{f(c['fractional_speedup'], '.2f')} |")
-    lines += ["", f"Slope of log(ms/step) vs log(n): all sizes {rec['slope_all']:.3f}; "
-              f"n >= {rec['slope_from']}: {rec['slope_large']:.3f} (N^3 work: 3).",
+    lines += ["", f"Slope of log(ms/step) vs log(n): all sizes {f(rec['slope_all'], '.3f')}; "
+              f"n >= {rec['slope_from']}: {f(rec['slope_large'], '.3f')} (N^3 work: 3).",
               f"Peaks: {rec['peak_gflops']:.0f} GFLOP/s vector, {rec['peak_gbs']:.0f} GB/s HBM; "
               f"one host core: {rec['host_core']}."]
     return "\n".join(lines) + "\n"
