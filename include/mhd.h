@@ -68,11 +68,25 @@ enum { MHD_F32 = 0, MHD_F64 = 1 };
  * (message in mhd_last_error()).  The state is zero until mhd_set_state. */
 mhd_ctx *mhd_create(int nx, int ny, int nz, double gamma);
 
-/* As mhd_create, with precision tier prec (MHD_F32 / MHD_F64) and a HIP
- * stream (hipStream_t passed as void*, NULL = default stream) on which every
- * kernel of the handle is enqueued.  The stream must outlive the handle. */
+/* As mhd_create, with precision tier prec (MHD_F32 / MHD_F64), a HIP stream
+ * (hipStream_t passed as void*, NULL = default stream) on which every kernel
+ * of the handle is enqueued, and optionally the two state buffers (the
+ * ping-pong pair the operators read from and write to; each field lives in
+ * one of them at a time).
+ *
+ * dev_buf_a, dev_buf_b: both NULL (the library allocates and frees them) or
+ * both device memory of the current device, owned by the caller (for
+ * instance from a caching allocator), each at least 8*nx*ny*nz elements of
+ * the tier's type inside its allocation, 256-byte aligned, not overlapping;
+ * they are zeroed here, hold the state between calls, and must outlive the
+ * handle, which never frees them.  Read the state with mhd_get_state or
+ * mhd_get_state_device, not from the buffers (which one holds a field
+ * changes from operator to operator).  Violations of these conditions that
+ * the runtime can see (one buffer NULL, host or managed memory, another
+ * device, misalignment, an allocation too short, overlap) give NULL with
+ * MHD_EINVAL in mhd_last_error.  The stream must outlive the handle. */
 mhd_ctx *mhd_create_ex(int nx, int ny, int nz, double gamma, int prec,
-                       void *hip_stream);
+                       void *hip_stream, void *dev_buf_a, void *dev_buf_b);
 
 /* Free the handle and its device memory (synchronises its stream). */
 void mhd_destroy(mhd_ctx *h);

@@ -49,6 +49,7 @@ struct mhd_ctx {
     hipStream_t stream;
     int device;
     void* buf[2];
+    bool own_buf;           // buf[] allocated here (false: the caller's, never freed here)
     int cur[8];
     double* scal;           // device SCAL_COUNT doubles
     int* flag;              // device FLAG_COUNT ints
@@ -141,7 +142,34 @@ static int sync_stream(mhd_ctx* h)
 // lifetime
 // ---------------------------------------------------------------------------
 
-extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec, void* hip_stream)
+// a caller's state buffer: device memory of this device, 256-byte aligned,
+// at least `bytes` long inside its allocation
+static int check_user_buffer(const void* p, size_t bytes, int device, const char* name)
+{
+    if (reinterpret_cast<uintptr_t>(p) % 256)
+        return fail(MHD_EINVAL, "%s: a state buffer must be 256-byte aligned", name);
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MHD_EINVAL, "%s: not memory known to HIP", name);
+    }
+    if (a.type != hipMemoryTypeDevice || a.isManaged)
+        return fail(MHD_EINVAL, "%s: not device memory", name);
+    if (a.device != device)
+        return fail(MHD_EINVAL, "%s: memory of device %d, handle on device %d", name, a.device, device);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MHD_EINVAL, "%s: allocation range unknown", name);
+    }
+    if (static_cast<const char*>(p) + bytes > static_cast<const char*>(base) + size)
+        return fail(MHD_EINVAL, "%s: allocation shorter than 8*nx*ny*nz elements", name);
+    return MHD_OK;
+}
+
+extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec, void* hip_stream,
+                                   void* dev_buf_a, void* dev_buf_b)
 {
     const int n[3] = { nx, ny, nz };
     for (int d = 0; d < 3; ++d)
@@ -161,6 +189,10 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
         fail(MHD_EINVAL, "precision must be MHD_F32 or MHD_F64 (got %d)", prec);
         return nullptr;
     }
+    if ((dev_buf_a == nullptr) != (dev_buf_b == nullptr)) {
+        fail(MHD_EINVAL, "give both state buffers or neither");
+        return nullptr;
+    }
     mhd_ctx* h = new mhd_ctx();
     memset(h, 0, sizeof *h);
     h->n[0] = nx; h->n[1] = ny; h->n[2] = nz;
@@ -178,9 +210,32 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
     h->nblk_cfl = cfl_blocks(h->N);
     h->nblk_diag = diag_blocks(h->N);
     const int npart = std::max(h->nblk_cfl, 10 * h->nblk_diag);
-    bool ok = hipMalloc(&h->buf[0], bytes) == hipSuccess &&
-              hipMalloc(&h->buf[1], bytes) == hipSuccess &&
-              hipMalloc(&h->scal, SCAL_COUNT * sizeof(double)) == hipSuccess &&
+    if (dev_buf_a) {
+        const char* a = static_cast<const char*>(dev_buf_a);
+        const char* b = static_cast<const char*>(dev_buf_b);
+        if (check_user_buffer(dev_buf_a, bytes, h->device, "dev_buf_a") ||
+            check_user_buffer(dev_buf_b, bytes, h->device, "dev_buf_b")) {
+            delete h;
+            return nullptr;
+        }
+        if (a < b + bytes && b < a + bytes) {
+            fail(MHD_EINVAL, "the two state buffers overlap");
+            delete h;
+            return nullptr;
+        }
+        h->buf[0] = dev_buf_a;
+        h->buf[1] = dev_buf_b;
+        h->own_buf = false;
+    } else {
+        h->own_buf = true;
+        if (hipMalloc(&h->buf[0], bytes) != hipSuccess || hipMalloc(&h->buf[1], bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(MHD_ENOMEM, "device allocation of 2 x %zu bytes failed", bytes);
+            mhd_destroy(h);
+            return nullptr;
+        }
+    }
+    bool ok = hipMalloc(&h->scal, SCAL_COUNT * sizeof(double)) == hipSuccess &&
               hipMalloc(&h->flag, FLAG_COUNT * sizeof(int)) == hipSuccess &&
               hipMalloc(&h->partial, npart * sizeof(double)) == hipSuccess &&
               hipMalloc(&h->partial_bad, h->nblk_cfl * sizeof(int)) == hipSuccess &&
@@ -189,7 +244,7 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
               hipHostMalloc(&h->pinned, 16 * sizeof(double), hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
-        fail(MHD_ENOMEM, "device allocation of 2 x %zu bytes failed", bytes);
+        fail(MHD_ENOMEM, "device allocation of the handle's scratch failed");
         mhd_destroy(h);
         return nullptr;
     }
@@ -213,15 +268,17 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
 
 extern "C" mhd_ctx* mhd_create(int nx, int ny, int nz, double gamma)
 {
-    return mhd_create_ex(nx, ny, nz, gamma, MHD_F32, nullptr);
+    return mhd_create_ex(nx, ny, nz, gamma, MHD_F32, nullptr, nullptr, nullptr);
 }
 
 extern "C" void mhd_destroy(mhd_ctx* h)
 {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
-    if (h->buf[0]) (void)hipFree(h->buf[0]);
-    if (h->buf[1]) (void)hipFree(h->buf[1]);
+    if (h->own_buf) {
+        if (h->buf[0]) (void)hipFree(h->buf[0]);
+        if (h->buf[1]) (void)hipFree(h->buf[1]);
+    }
     if (h->scal) (void)hipFree(h->scal);
     if (h->flag) (void)hipFree(h->flag);
     if (h->partial) (void)hipFree(h->partial);

@@ -57,7 +57,7 @@ def load():
     fp = ctypes.POINTER(ctypes.c_float)
     sig = {
         "mhd_create": (vp, [i, i, i, d]),
-        "mhd_create_ex": (vp, [i, i, i, d, i, vp]),
+        "mhd_create_ex": (vp, [i, i, i, d, i, vp, vp, vp]),
         "mhd_destroy": (None, [vp]),
         "mhd_info": (i, [vp, ip, ip]),
         "mhd_set_state": (i, [vp, dp, sz]),
@@ -155,8 +155,8 @@ def mhd_create(nx, ny, nz, gamma):
     return load().mhd_create(nx, ny, nz, gamma)
 
 
-def mhd_create_ex(nx, ny, nz, gamma, prec, stream=None):
-    return load().mhd_create_ex(nx, ny, nz, gamma, prec, stream)
+def mhd_create_ex(nx, ny, nz, gamma, prec, stream=None, dev_buf_a=None, dev_buf_b=None):
+    return load().mhd_create_ex(nx, ny, nz, gamma, prec, stream, dev_buf_a, dev_buf_b)
 
 
 def mhd_destroy(h):
@@ -222,22 +222,40 @@ class Solver:
     """One periodic grid of n = (nx, ny, nz) cells on the current HIP device.
 
     prec: "f32" or "f64".  stream: a torch.cuda.Stream (or raw handle) on
-    which every kernel is enqueued; None = the default stream."""
+    which every kernel is enqueued; None = the default stream.  buffers: None
+    (the library allocates the two state buffers) or two contiguous device
+    tensors of the tier's dtype with at least 8*nx*ny*nz elements each; the
+    Solver keeps references to them until it is closed."""
 
-    def __init__(self, n, gamma=5.0 / 3.0, prec="f32", stream=None):
+    def __init__(self, n, gamma=5.0 / 3.0, prec="f32", stream=None, buffers=None):
         self.lib = load()
         self.n = tuple(int(v) for v in n)
         self.gamma = float(gamma)
         self.prec = {"f32": MHD_F32, "f64": MHD_F64}[prec]
+        self._buffers = None
+        ptrs = (None, None)
+        if buffers is not None:
+            import torch
+            a, b = buffers
+            want = torch.float64 if self.prec == MHD_F64 else torch.float32
+            need = 8 * self.n[0] * self.n[1] * self.n[2]
+            for t in (a, b):
+                if not (t.is_cuda and t.is_contiguous() and t.dtype == want and t.numel() >= need):
+                    raise ValueError(f"state buffers: contiguous {want} device tensors of at least "
+                                     f"{need} elements")
+            self._buffers = (a, b)
+            ptrs = (a.data_ptr(), b.data_ptr())
         self.h = self.lib.mhd_create_ex(self.n[0], self.n[1], self.n[2], self.gamma, self.prec,
-                                        _torch_stream(stream))
+                                        _torch_stream(stream), *ptrs)
         if not self.h:
+            self._buffers = None
             raise MHDError(MHD_EINVAL, last_error())
 
     def close(self):
         if self.h:
             self.lib.mhd_destroy(self.h)
             self.h = None
+        self._buffers = None
 
     def __del__(self):
         try:

@@ -48,8 +48,17 @@ def test_bad_gamma_rejected(gamma):
 
 def test_bad_precision_rejected():
     from paper_1004_1680_amd import mhd
-    assert not mhd.load().mhd_create_ex(8, 8, 8, 5.0 / 3.0, 7, None)
+    assert not mhd.load().mhd_create_ex(8, 8, 8, 5.0 / 3.0, 7, None, None, None)
     assert "precision" in mhd.last_error()
+
+
+def test_one_state_buffer_rejected():
+    from paper_1004_1680_amd import mhd
+    lib = mhd.load()
+    assert not lib.mhd_create_ex(8, 8, 8, 5.0 / 3.0, 0, None, 1 << 20, None)
+    assert "both state buffers" in mhd.last_error()
+    assert not lib.mhd_create_ex(8, 8, 8, 5.0 / 3.0, 0, None, None, 1 << 20)
+    assert "both state buffers" in mhd.last_error()
 
 
 def test_null_handle_calls_fail_cleanly():
