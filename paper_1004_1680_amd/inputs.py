@@ -283,6 +283,26 @@ def sod(n, axis=0, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), gamma=1.4):
     return assemble(n, rho, v, p, [z, z, z], gamma)
 
 
+def brio_wu(n, axis=0, gamma=2.0):
+    """Double Brio-Wu magnetised shock tube on a periodic box: along `axis`
+    the middle half holds rho = 1, p = 1, b_t = +1 and the rest rho = 0.125,
+    p = 0.1, b_t = -1, with a uniform normal field b_n = 0.75 and v = 0; b_t
+    is the component after `axis` in cyclic order.  b_t varies only along
+    `axis`, so the face field is divergence-free exactly."""
+    nx, ny, nz = n
+    h = 1.0 / nx
+    Lax = (nx, ny, nz)[axis] * h
+    xc = centres(n)[axis] / Lax
+    inside = (xc > 0.25) & (xc < 0.75)
+    rho = np.where(inside, 1.0, 0.125)
+    p = np.where(inside, 1.0, 0.1)
+    z = 0 * xc
+    b = [z, z, z]
+    b[axis] = z + 0.75
+    b[(axis + 1) % 3] = np.where(inside, 1.0, -1.0)
+    return assemble(n, rho, [z, z, z], p, b, gamma)
+
+
 def solenoidal_velocity(n, seed, kmin=1, kmax=8, slope=-4.0):
     """Gaussian random-phase solenoidal velocity field with per-mode power
     |v_k|^2 proportional to k^slope for integer |k| in [kmin, kmax], unit rms.
