@@ -82,6 +82,69 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+class PowerSampler:
+    """Board power of the GPU over a timed region: the amdgpu hwmon reading
+    (power1_average, else power1_input; microwatts) of the device's PCI
+    function, sampled every `period` seconds on a host thread.  result() is
+    None when no such file is readable."""
+
+    def __init__(self, torch, period=0.01):
+        import threading
+        self.period = period
+        self.path = self._find(torch)
+        self.samples = []
+        self._stop = threading.Event()
+        self._thread = None
+
+    @staticmethod
+    def _find(torch):
+        import glob
+        try:
+            p = torch.cuda.get_device_properties(torch.cuda.current_device())
+            dev = f"/sys/bus/pci/devices/{p.pci_domain_id:04x}:{p.pci_bus_id:02x}:{p.pci_device_id:02x}.0"
+        except Exception:
+            return None
+        for name in ("power1_average", "power1_input"):
+            for f in sorted(glob.glob(f"{dev}/hwmon/hwmon*/{name}")):
+                try:
+                    with open(f) as fh:
+                        if int(fh.read().strip()) > 0:
+                            return f
+                except (OSError, ValueError):
+                    continue
+        return None
+
+    def _run(self):
+        while not self._stop.is_set():
+            try:
+                with open(self.path) as fh:
+                    self.samples.append(int(fh.read().strip()) * 1e-6)
+            except (OSError, ValueError):
+                pass
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        import threading
+        if self.path:
+            self._thread = threading.Thread(target=self._run, daemon=True)
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        if self._thread:
+            self._stop.set()
+            self._thread.join()
+
+    def result(self, seconds, steps, cells):
+        if not self.samples:
+            return None
+        w = sum(self.samples) / len(self.samples)
+        return {"avg_W": round(w, 1), "J_per_step": round(w * seconds / steps, 4),
+                "Mcell_updates_per_J": round(cells * steps / (w * seconds) / 1e6, 2),
+                "samples": len(self.samples), "source": self.path,
+                "what": "GPU board power (hwmon), mean over the timed region"}
+
+
 def make_state_device(wl, torch):
     """Initial state as a device tensor: turbulence is built on the host
     (numpy FFTs), the Orszag-Tang-type state directly on the device (equal
@@ -603,11 +666,12 @@ def main():
 
     log(f"[bench] timing {args.steps} steps")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        S.step_auto(args.cfl)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    with PowerSampler(torch) as power:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            S.step_auto(args.cfl)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
     nsteps_ok = S.status()
     ms_per_step = el * 1e3 / args.steps
     value = ncell * args.steps / el / 1e6
@@ -720,6 +784,7 @@ def main():
             "frac": round(step_traffic / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels": kern,
         "components": components,
+        "power": power.result(el, args.steps, ncell),
         "steps_completed": nsteps_ok,
     }
     S.close()

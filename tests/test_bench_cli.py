@@ -13,3 +13,20 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_power_sampler_reads_microwatts(tmp_path):
+    import time
+    sys.path.insert(0, ROOT)
+    import bench
+    f = tmp_path / "power1_average"
+    f.write_text("250000000\n")                      # 250 W in microwatts
+    ps = bench.PowerSampler(object(), period=0.001)  # no device: nothing found
+    assert ps.path is None and ps.result(1.0, 1, 1) is None
+    ps.path = str(f)
+    with ps:
+        time.sleep(0.02)
+    r = ps.result(2.0, 4, 10 ** 9)
+    assert r["samples"] >= 1 and r["avg_W"] == 250.0
+    assert r["J_per_step"] == 125.0                  # 250 W x 2 s / 4 steps
+    assert r["Mcell_updates_per_J"] == 8.0           # 4e9 cell-updates / 500 J
