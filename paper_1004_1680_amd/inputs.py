@@ -303,6 +303,24 @@ def brio_wu(n, axis=0, gamma=2.0):
     return assemble(n, rho, [z, z, z], p, b, gamma)
 
 
+def field_loop(n, amp=1e-3, radius=0.15, v=(1.0, 0.5, 0.0), rho=1.0, p=1.0, gamma=GAMMA):
+    """Advected magnetic field loop (a weak-field CT test in the x-y plane):
+    the z-edge potential A_z = amp (radius - r) inside the circle of the given
+    radius about the middle of the x-y box and 0 outside, b its discrete
+    curl (exactly divergence-free, no b_z), uniform rho, p and velocity v.
+    With v = (1, 1/2) and a box 1 x 1/2 (ny = nx/2) the loop crosses the
+    box diagonally and is back in place at t = 1."""
+    nx, ny, nz = n
+    h = 1.0 / nx
+    xe = (np.arange(nx) * h)[None, None, :]
+    ye = (np.arange(ny) * h)[None, :, None]
+    r = np.sqrt((xe - 0.5 * nx * h) ** 2 + (ye - 0.5 * ny * h) ** 2)
+    Az = np.broadcast_to(np.where(r < radius, amp * (radius - r), 0.0), (nz, ny, nx))
+    z = np.zeros((nz, ny, nx))
+    b = vector_potential_b(n, (z, z, Az))
+    return assemble(n, rho, [np.full((nz, ny, nx), c) for c in v], p, list(b), gamma)
+
+
 def solenoidal_velocity(n, seed, kmin=1, kmax=8, slope=-4.0):
     """Gaussian random-phase solenoidal velocity field with per-mode power
     |v_k|^2 proportional to k^slope for integer |k| in [kmin, kmax], unit rms.

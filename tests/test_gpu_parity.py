@@ -131,6 +131,25 @@ def test_brio_wu_shock_tube_parity(M, prec, axis):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_field_loop_parity(M, prec):
+    """the advected field loop (weak b, jump of b at the loop's edge, b_z = 0):
+    FP64 over 20 steps, FP32 over one step, against the oracle"""
+    n = (64, 32, 8)
+    say(f"case: field loop {n} {prec}")
+    s = I.field_loop(n)
+    steps = 20 if prec == "f64" else 1
+    if prec == "f32":
+        s = f32_round(s)
+    g, gdts, _ = gpu_run(M, s, n, prec, steps)
+    o, _, odts = oracle.run(s, steps)
+    assert np.allclose(gdts, odts, rtol=1e-14 if prec == "f64" else 1e-6, atol=0)
+    err = max_family_err(g, o)
+    say("err", err)
+    assert err <= TOL[prec]
+    assert np.abs(g[7]).max() == 0.0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_chunked_march_is_bitwise_equal(M, prec):
     n = (24, 32, 48)
     say(f"case: chunked march {n} {prec}")
