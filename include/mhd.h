@@ -139,6 +139,21 @@ int mhd_magnetic(mhd_ctx *h, int dim, double dt);
  * instead of a separate reduction.  Asynchronous. */
 int mhd_sweep(mhd_ctx *h, int dim, double dt);
 
+/* Slope limiter of the second-order parts of both operators, a method
+ * variant (the paper's is van Leer's, section II.B).  With a, b the halved
+ * one-sided differences and a b > 0:
+ *   MHD_LIMITER_VANLEER   2ab/(a+b)                          (default)
+ *   MHD_LIMITER_MINMOD    sign(a) min(|a|, |b|)
+ *   MHD_LIMITER_MC        sign(a) min(2|a|, 2|b|, |a+b|/2)
+ *   MHD_LIMITER_SUPERBEE  sign(a) max(min(2|a|, |b|), min(|a|, 2|b|))
+ * and 0 when a b <= 0.  Applies to the handle's operators, sweeps and steps
+ * from the next call on; with a limiter other than van Leer's the reverse
+ * pairs run as two launches each.  MHD_EINVAL for another value.  Ensembles
+ * always use van Leer's. */
+enum { MHD_LIMITER_VANLEER = 0, MHD_LIMITER_MINMOD = 1, MHD_LIMITER_MC = 2, MHD_LIMITER_SUPERBEE = 3 };
+int mhd_set_limiter(mhd_ctx *h, int limiter);
+int mhd_get_limiter(const mhd_ctx *h, int *limiter);
+
 /* Full step of 2*dt (section II.B; section IV.A): sweeps x, y, z, then
  * z, y, x, i.e. F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x, every
  * operator over dt.  Advances the time by 2*dt.  Asynchronous. */

@@ -78,14 +78,53 @@ static size_t cell_shift(const int n[3], int i, int j, int k, int a, int s)
     return cell(n, p[0], p[1], p[2]);
 }
 
-/* van Leer limiter of section II.B: harmonic mean of two one-sided
- * differences when they have the same sign, zero otherwise. */
+/* Slope limiter phi(a, b) of two halved one-sided differences, zero unless
+ * they have the same sign.  Section II.B uses van Leer's, the harmonic mean
+ * 2ab/(a+b); the others are method variants: minmod (the smaller
+ * magnitude), MC (the central value (a+b)/2 limited to twice either one)
+ * and superbee (the larger of min(2|a|, |b|) and min(|a|, 2|b|)).  The
+ * choice is process-wide (oracle_set_limiter), van Leer's by default. */
+enum { LIMITER_VANLEER = 0, LIMITER_MINMOD = 1, LIMITER_MC = 2, LIMITER_SUPERBEE = 3 };
+static int g_limiter = LIMITER_VANLEER;
+
 static double van_leer(double a, double b)
 {
     double ab = a * b;
-    if (ab > 0.0)
-        return 2.0 * ab / (a + b);
-    return 0.0;
+    if (g_limiter == LIMITER_VANLEER) {
+        if (ab > 0.0)
+            return 2.0 * ab / (a + b);
+        return 0.0;
+    }
+    if (!(ab > 0.0))
+        return 0.0;
+    double m;
+    if (g_limiter == LIMITER_MINMOD) {
+        m = fmin(fabs(a), fabs(b));
+    } else if (g_limiter == LIMITER_MC) {
+        double central = 0.5 * fabs(a + b);
+        m = fmin(fmin(2.0 * fabs(a), 2.0 * fabs(b)), central);
+    } else {
+        m = fmax(fmin(2.0 * fabs(a), fabs(b)), fmin(fabs(a), 2.0 * fabs(b)));
+    }
+    return copysign(m, a);
+}
+
+int oracle_set_limiter(int kind)
+{
+    if (kind < LIMITER_VANLEER || kind > LIMITER_SUPERBEE) return -1;
+    g_limiter = kind;
+    return 0;
+}
+
+/* phi(a, b) with limiter `kind` (for tests of the formulas themselves) */
+double oracle_limiter_value(int kind, double a, double b)
+{
+    int saved = g_limiter;
+    double r;
+    g_limiter = kind;
+    r = van_leer(a, b);
+    g_limiter = saved;
+    return r;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -34,6 +34,10 @@ int oracle_step(int nx, int ny, int nz, double gamma, double *s, double dt,
 int oracle_cfl(int nx, int ny, int nz, double gamma, const double *s,
                double cfl, double *dt, double *vmax);
 void oracle_diag(int nx, int ny, int nz, const double *s, double out[9]);
+/* process-wide slope limiter: 0 van Leer (default), 1 minmod, 2 MC,
+ * 3 superbee; -1 for another value */
+int oracle_set_limiter(int kind);
+double oracle_limiter_value(int kind, double a, double b);
 int oracle_restrict(int nx, int ny, int nz, int r, const double *fine,
                     double *coarse);
 

@@ -18,7 +18,8 @@ _LIB = os.path.join(_HERE, "libmhd_oracle.so")
 _lib = None
 
 __all__ = ["build", "load", "fluid_sweep", "mag_sweep", "sweep", "step",
-           "cfl", "cfl_dt", "diag", "restrict", "run", "NonPhysical"]
+           "cfl", "cfl_dt", "diag", "restrict", "run", "NonPhysical",
+           "limiter_value", "VANLEER", "MINMOD", "MC", "SUPERBEE"]
 
 
 class NonPhysical(RuntimeError):
@@ -61,8 +62,11 @@ def load():
     for fn in ("oracle_conv3d", "oracle_conv3d_dgrad", "oracle_conv3d_wgrad",
                "oracle_closure_project", "oracle_closure_project_T", "oracle_closure_gate"):
         getattr(lib, fn).restype = None
+    lib.oracle_set_limiter.argtypes = [i]
+    lib.oracle_limiter_value.argtypes = [i, d, d]
+    lib.oracle_limiter_value.restype = d
     for fn in ("oracle_fluid_sweep", "oracle_mag_sweep", "oracle_sweep",
-               "oracle_step", "oracle_cfl", "oracle_restrict"):
+               "oracle_step", "oracle_cfl", "oracle_restrict", "oracle_set_limiter"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -82,40 +86,67 @@ def _dims(s):
     return s.shape[3], s.shape[2], s.shape[1]
 
 
-def fluid_sweep(s, d, dt, c, gamma=5.0 / 3.0):
+# slope limiters: 0 van Leer (section II.B), 1 minmod, 2 MC, 3 superbee
+VANLEER, MINMOD, MC, SUPERBEE = 0, 1, 2, 3
+
+
+class _Limiter:
+    """the oracle's process-wide limiter for the duration of one call"""
+
+    def __init__(self, kind):
+        self.kind = kind
+
+    def __enter__(self):
+        if load().oracle_set_limiter(self.kind) != 0:
+            raise ValueError(f"unknown limiter {self.kind}")
+
+    def __exit__(self, *exc):
+        load().oracle_set_limiter(VANLEER)
+
+
+def limiter_value(kind, a, b):
+    """phi(a, b) of the limiter `kind` on two halved one-sided differences"""
+    return load().oracle_limiter_value(kind, a, b)
+
+
+def fluid_sweep(s, d, dt, c, gamma=5.0 / 3.0, limiter=VANLEER):
     """Fluid operator along axis d with relaxation speed c."""
     s = _check(s)
     out = np.empty_like(s)
     nx, ny, nz = _dims(s)
-    r = load().oracle_fluid_sweep(nx, ny, nz, gamma, _ptr(s), _ptr(out), d, dt, c)
+    with _Limiter(limiter):
+        r = load().oracle_fluid_sweep(nx, ny, nz, gamma, _ptr(s), _ptr(out), d, dt, c)
     assert r == 0
     return out
 
 
-def mag_sweep(s, d, dt, gamma=5.0 / 3.0):
+def mag_sweep(s, d, dt, gamma=5.0 / 3.0, limiter=VANLEER):
     """Magnetic advection-constraint operator along axis d."""
     s = _check(s)
     out = np.empty_like(s)
     nx, ny, nz = _dims(s)
-    r = load().oracle_mag_sweep(nx, ny, nz, gamma, _ptr(s), _ptr(out), d, dt)
+    with _Limiter(limiter):
+        r = load().oracle_mag_sweep(nx, ny, nz, gamma, _ptr(s), _ptr(out), d, dt)
     assert r == 0
     return out
 
 
-def sweep(s, code, dt, c, gamma=5.0 / 3.0):
+def sweep(s, code, dt, c, gamma=5.0 / 3.0, limiter=VANLEER):
     """code 0..2: fluid then magnetic along code; 3..5: the reverse along
     code-3."""
     s = _check(s).copy()
     nx, ny, nz = _dims(s)
-    assert load().oracle_sweep(nx, ny, nz, gamma, _ptr(s), code, dt, c) == 0
+    with _Limiter(limiter):
+        assert load().oracle_sweep(nx, ny, nz, gamma, _ptr(s), code, dt, c) == 0
     return s
 
 
-def step(s, dt, c, gamma=5.0 / 3.0):
+def step(s, dt, c, gamma=5.0 / 3.0, limiter=VANLEER):
     """Full Strang step (x, y, z, z, y, x) of 2 dt with relaxation speed c."""
     s = _check(s).copy()
     nx, ny, nz = _dims(s)
-    assert load().oracle_step(nx, ny, nz, gamma, _ptr(s), dt, c) == 0
+    with _Limiter(limiter):
+        assert load().oracle_step(nx, ny, nz, gamma, _ptr(s), dt, c) == 0
     return s
 
 
@@ -153,7 +184,7 @@ def restrict(s, r):
     return out
 
 
-def run(s, nsteps, cfl_number=0.7, gamma=5.0 / 3.0, t_end=None):
+def run(s, nsteps, cfl_number=0.7, gamma=5.0 / 3.0, t_end=None, limiter=VANLEER):
     """Advance nsteps full steps with dt from the CFL condition before each
     step.  If t_end is given, stop there, shortening the last step so that
     the run ends exactly at t_end.  Returns (state, time, list of dt)."""
@@ -166,7 +197,7 @@ def run(s, nsteps, cfl_number=0.7, gamma=5.0 / 3.0, t_end=None):
         dt, vmax = cfl(s, cfl_number, gamma)
         if t_end is not None:
             dt = min(dt, 0.5 * (t_end - t))
-        s = step(s, dt, vmax, gamma)
+        s = step(s, dt, vmax, gamma, limiter)
         t += 2.0 * dt
         dts.append(dt)
     return s, t, dts

@@ -157,18 +157,46 @@ __device__ __forceinline__ T plus_vl_half(T x, T d1, T d2)
     }
 }
 
+// Other slope limiters, a method variant (the paper uses van Leer's): with
+// a, b the halved one-sided differences and a b > 0, sign(a) times
+//   minmod:   min(|a|, |b|)
+//   MC:       min(2|a|, 2|b|, |a + b| / 2)   (monotonised central)
+//   superbee: max(min(2|a|, |b|), min(|a|, 2|b|))
+// and 0 otherwise.  Every step but the final sum is exact, in either tier.
+enum { LIM_VANLEER = 0, LIM_MINMOD = 1, LIM_MC = 2, LIM_SUPERBEE = 3 };
+
+template <typename T, int LIM>
+__device__ __forceinline__ T slope_limiter(T a, T b)
+{
+    if (!(a * b > T(0))) return T(0);
+    const T fa = fabs(a), fb = fabs(b);
+    T m;
+    if constexpr (LIM == LIM_MINMOD) m = fmin(fa, fb);
+    else if constexpr (LIM == LIM_MC) m = fmin(fmin(T(2) * fa, T(2) * fb), T(0.5) * fabs(a + b));
+    else m = fmax(fmin(T(2) * fa, fb), fmin(fa, T(2) * fb));
+    return copysign(m, a);
+}
+
+// x + phi(d1/2, d2/2) with the limiter LIM
+template <typename T, int LIM>
+__device__ __forceinline__ T plus_limited_half(T x, T d1, T d2)
+{
+    if constexpr (LIM == LIM_VANLEER) return plus_vl_half(x, d1, d2);
+    else return x + slope_limiter<T, LIM>(T(0.5) * d1, T(0.5) * d2);
+}
+
 // Second-order right-moving part at interface i+1/2 from F^R at i-1, i, i+1.
-template <typename T>
+template <typename T, int LIM = LIM_VANLEER>
 __device__ __forceinline__ T limited_right(T rm, T r0, T rp)
 {
-    return plus_vl_half(r0, r0 - rm, rp - r0);
+    return plus_limited_half<T, LIM>(r0, r0 - rm, rp - r0);
 }
 
 // Second-order left-moving part at interface i+1/2 from F^L at i, i+1, i+2.
-template <typename T>
+template <typename T, int LIM = LIM_VANLEER>
 __device__ __forceinline__ T limited_left(T l0, T lp, T lpp)
 {
-    return plus_vl_half(lp, l0 - lp, lp - lpp);
+    return plus_limited_half<T, LIM>(lp, l0 - lp, lp - lpp);
 }
 
 // Constrained transport (section II.B): edge velocity of v_d on the edge at
@@ -191,14 +219,14 @@ __device__ __forceinline__ T upwind_flux1(T a, T q0, T q1)
 // Upwind cell c (a > 0): q0 + vl(q0 - qm, q1 - q0); upwind cell c+d
 // (a < 0): q1 + vl(q1 - q2, q0 - q1); times a.  The operands are selected
 // first (no divergent branch); a = 0 gives a signed zero.
-template <typename T>
+template <typename T, int LIM = LIM_VANLEER>
 __device__ __forceinline__ T upwind_flux2(T a, T qm, T q0, T q1, T q2)
 {
     const bool right = a > T(0);
     const T up = right ? q0 : q1;
     const T d1 = right ? q0 - qm : q1 - q2;
     const T d2 = right ? q1 - q0 : q0 - q1;
-    return a * plus_vl_half(up, d1, d2);
+    return a * plus_limited_half<T, LIM>(up, d1, d2);
 }
 
 // Index helpers for a periodic [nz][ny][nx] grid.

@@ -29,6 +29,7 @@ struct SweepParams {
     // cfl_acc[CFL_ACC_SLOTS]
     unsigned long long* cfl_acc;
     double gamma64;          // gamma in FP64 for that speed
+    int limiter;             // slope limiter of the single operators (LIM_*; 0: van Leer)
 };
 
 // Launch shape choices of the march kernels: chunk length along y and z

@@ -70,6 +70,7 @@ struct mhd_ctx {
     // reverse-half pairs M_d F_d: one fused launch each (true) or the two
     // operators in turn; same result bit for bit
     bool rev_fused;
+    int limiter;            // slope limiter of the operators (MHD_LIMITER_*)
     double scal_dt, scal_c;
     bool failed;
     LaunchTuning tune;
@@ -521,6 +522,7 @@ static hipError_t enqueue_op(mhd_ctx* h, int op, int d, const int* flag, unsigne
     P.flag = flag;
     P.cfl_acc = acc;
     P.gamma64 = h->gamma;
+    P.limiter = h->limiter;
     hipError_t e = op == 0 ? launch_fluid<T>(P, d, h->tune, h->stream)
                  : op == 1 ? launch_magnetic<T>(P, d, h->tune, h->stream)
                            : launch_magfluid<T>(P, d, h->tune, h->stream);
@@ -583,6 +585,10 @@ extern "C" int mhd_magnetic(mhd_ctx* h, int dim, double dt)
     return MHD_OK;
 }
 
+// the reverse pairs run as one fused launch: when asked for and with van
+// Leer's limiter (the fused kernels have no other)
+static bool pairs_fused(const mhd_ctx* h) { return h->rev_fused && h->limiter == MHD_LIMITER_VANLEER; }
+
 extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
 {
     if (dim < 0 || dim > 6) return fail(MHD_EINVAL, "sweep code must be 0..6 (got %d)", dim);
@@ -593,7 +599,7 @@ extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
         // the reverse x pair with the fused CFL of its result
         unsigned long long* acc = h->fuse_ok ? h->cfl_acc : nullptr;
         if (acc) HIP_TRY(h, launch_clear_acc(acc, h->stream));
-        if (h->rev_fused) {
+        if (pairs_fused(h)) {
             HIP_TRY(h, op(h, 2, 0, nullptr, acc));
         } else {
             HIP_TRY(h, op(h, 1, 0, nullptr));
@@ -606,7 +612,7 @@ extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
     if (dim < 3) {
         HIP_TRY(h, op(h, 0, d, nullptr));
         HIP_TRY(h, op(h, 1, d, nullptr));
-    } else if (h->rev_fused) {
+    } else if (pairs_fused(h)) {
         HIP_TRY(h, op(h, 2, d, nullptr));
     } else {
         HIP_TRY(h, op(h, 1, d, nullptr));
@@ -626,13 +632,32 @@ static int enqueue_step_ops(mhd_ctx* h, const int* flag, unsigned long long* acc
         HIP_TRY(h, op(h, 1, d, flag));
     }
     for (int d = 2; d >= 0; --d) {
-        if (h->rev_fused) {
+        if (pairs_fused(h)) {
             HIP_TRY(h, op(h, 2, d, flag, d == 0 ? acc : nullptr));
         } else {
             HIP_TRY(h, op(h, 1, d, flag));
             HIP_TRY(h, op(h, 0, d, flag, d == 0 ? acc : nullptr));
         }
     }
+    return MHD_OK;
+}
+
+extern "C" int mhd_set_limiter(mhd_ctx* h, int limiter)
+{
+    int r = check_handle(h);
+    if (r) return r;
+    if (limiter < MHD_LIMITER_VANLEER || limiter > MHD_LIMITER_SUPERBEE)
+        return fail(MHD_EINVAL, "limiter must be 0..3 (got %d)", limiter);
+    h->limiter = limiter;
+    return MHD_OK;
+}
+
+extern "C" int mhd_get_limiter(const mhd_ctx* h, int* limiter)
+{
+    int r = check_handle(h);
+    if (r) return r;
+    if (!limiter) return fail(MHD_EINVAL, "null output");
+    *limiter = h->limiter;
     return MHD_OK;
 }
 

@@ -24,10 +24,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mhd.h"
 #include "mhd_device.h"
 #include "mhd_kernels.h"
 
 namespace mhd {
+
+static_assert(LIM_VANLEER == MHD_LIMITER_VANLEER && LIM_MINMOD == MHD_LIMITER_MINMOD && LIM_MC == MHD_LIMITER_MC &&
+                  LIM_SUPERBEE == MHD_LIMITER_SUPERBEE,
+              "device limiter codes are the C ABI's");
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -114,7 +119,7 @@ struct RowThread {
 // CFL = true: the FP64 signal speed of every output cell, maximum per wave,
 // atomic maximum into P.cfl_acc; needs full waves (blockDim.x a multiple of
 // 64).
-template <typename T, bool CFL>
+template <typename T, bool CFL, int LIM = LIM_VANLEER>
 __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowThread& R, size_t base,
                                              const T (&u)[4][5], const T (&bb)[4][3],
                                              const T (&fb)[CFL ? 4 : 1][6], T* const A)
@@ -181,7 +186,7 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
             const T rp = k < 3 ? fr[k + 1][q] : frnext;
             const T lp = k < 3 ? fl[k + 1][q] : flnext0;
             const T lpp = k < 2 ? fl[k + 2][q] : (k == 2 ? flnext0 : flnext1);
-            phi[k][q] = limited_right(rm, fr[k][q], rp) - limited_left(fl[k][q], lp, lpp);
+            phi[k][q] = limited_right<T, LIM>(rm, fr[k][q], rp) - limited_left<T, LIM>(fl[k][q], lp, lpp);
         }
     }
     // exchange 4: net flux of the last interface goes to the next thread
@@ -275,7 +280,7 @@ __device__ __forceinline__ void load_u4(const SweepParams<T>& P, const RowThread
 }
 
 // One tile of rows_per_wg rows of one grid: fluid operator F_x.
-template <typename T, bool CFL = false>
+template <typename T, bool CFL = false, int LIM = LIM_VANLEER>
 __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
                                              int rows_per_wg, T* const A)
 {
@@ -331,14 +336,14 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
 #pragma unroll
             for (int k = 0; k < 4; ++k) { fb[k][4] = tmp[k]; fb[k][5] = tmp2[k]; }
     }
-    fluid_x_core<T, CFL>(P, R, base, u, bb, fb, A);
+    fluid_x_core<T, CFL, LIM>(P, R, base, u, bb, fb, A);
 }
 
-template <typename T, bool CFL>
+template <typename T, bool CFL, int LIM = LIM_VANLEER>
 __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fluid_x_tile<T, CFL>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    fluid_x_tile<T, CFL, LIM>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // Magnetic operator along x (e = y then z) of the thread's 4 cells.  For
@@ -349,7 +354,7 @@ __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr,
 // Gives the new faces nb = (b_y of P, b_y of P+y, b_z of P, b_z of P+z, b_x
 // of P) of the 4 cells; stores nothing.  A: LDS of 16 values per thread.
 // Every thread of the workgroup calls it (it holds barriers).
-template <typename T>
+template <typename T, int LIM = LIM_VANLEER>
 __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThread& R, T (&nb)[5][4],
                                            T* const A)
 {
@@ -455,7 +460,7 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
             const T qm = k > 0 ? qh[ch][k - 1] : qm1;
             const T q1 = k < 3 ? qh[ch][k + 1] : qp0;
             const T q2 = k < 2 ? qh[ch][k + 2] : (k == 2 ? qp0 : qp1);
-            f[ch][k] = upwind_flux2(a[ch][k], qm, qh[ch][k], q1, q2);
+            f[ch][k] = upwind_flux2<T, LIM>(a[ch][k], qm, qh[ch][k], q1, q2);
         }
     }
     // exchange 3: last edge flux -> next thread (region B was last read
@@ -486,7 +491,7 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
 }
 
 // One tile of rows_per_wg rows of one grid: magnetic operator M_x.
-template <typename T>
+template <typename T, int LIM = LIM_VANLEER>
 __device__ __forceinline__ void mag_x_tile(const SweepParams<T>& P, int tile, int tpr,
                                            int rows_per_wg, T* const A)
 {
@@ -503,18 +508,18 @@ __device__ __forceinline__ void mag_x_tile(const SweepParams<T>& P, int tile, in
         return;
     }
     T nb[5][4];
-    mag_x_core(P, R, nb, A);
+    mag_x_core<T, LIM>(P, R, nb, A);
     if (!R.active) return;
     vec4<T>::store(P.out[BY] + b0 + R.i0, nb[0]);
     vec4<T>::store(P.out[BZ] + b0 + R.i0, nb[2]);
     vec4<T>::store(P.out[BX] + b0 + R.i0, nb[4]);
 }
 
-template <typename T>
+template <typename T, int LIM = LIM_VANLEER>
 __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    mag_x_tile(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    mag_x_tile<T, LIM>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // One tile of rows: the reverse-half pair M_x then F_x in one pass.  The new
@@ -635,7 +640,7 @@ __device__ __forceinline__ int march_start(int j0, int chunk)
 // and gives the new U of cell L-3; it needs U and Bbar at L-3 .. L+3, so
 // pushes 6 positions before a chunk warm the window up (their results are
 // not used).
-template <typename T>
+template <typename T, int LIM = LIM_VANLEER>
 struct FluidWindow {
     T u3[5], u2[5], u1[5];            // U at L-3, L-2, L-1
     T bbm[3];                         // Bbar at L-1
@@ -673,7 +678,7 @@ struct FluidWindow {
         T phi[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            phi[q] = limited_right(r4[q], r3[q], r2[q]) - limited_left(l3[q], l2[q], l1[q]);
+            phi[q] = limited_right<T, LIM>(r4[q], r3[q], r2[q]) - limited_left<T, LIM>(l3[q], l2[q], l1[q]);
             unew[q] = sub_scaled(u3[q], tau, phi[q] - phim[q]);
         }
         // shift the window
@@ -698,7 +703,7 @@ struct FluidWindow {
 // fields and b_n at the look-ahead position L and gives the new faces at
 // L-3: nb = (b_t1 of P, b_t1 of P+t1, b_t2 of P, b_t2 of P+t2, b_n of P).
 // It needs inputs at L-3 .. L+3 (6 warm-up pushes, like the fluid window).
-template <typename T>
+template <typename T, int LIM = LIM_VANLEER>
 struct MagWindow {
     T wm[4];                 // face velocity at L-1
     T a3[4], a2[4];          // edge velocity at L-3, L-2
@@ -731,7 +736,7 @@ struct MagWindow {
             const T g1 = upwind_flux1(a1, q1[ch], q0[ch]);      // G1 at L-1
             const T hq1 = sub_scaled(q1[ch], halftau, g1 - gm[ch]);   // qh at L-1
             // edge flux at L-3 from a(L-3) and qh at L-4..L-1
-            f[ch] = upwind_flux2(a3[ch], h4[ch], h3[ch], h2[ch], hq1);
+            f[ch] = upwind_flux2<T, LIM>(a3[ch], h4[ch], h3[ch], h2[ch], hq1);
             wm[ch] = w0;
             a3[ch] = a2[ch]; a2[ch] = a1;
             gm[ch] = g1;
@@ -808,7 +813,7 @@ __device__ __forceinline__ int wrap_pos(int j, int nd)
 }
 
 // One lane (pencil chunk gid) of a grid: fluid operator F_d.
-template <typename T, int D, bool W32>
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
 __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
@@ -836,7 +841,7 @@ __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long g
     const unsigned step = G.sd * A::scale;
     const unsigned gb = G.base * A::scale, gt1 = G.b_t1p * A::scale, gt2 = G.b_t2p * A::scale;
 
-    FluidWindow<T> W;
+    FluidWindow<T, LIM> W;
     W.init();
     constexpr int U = march_unroll<T>();
     const int Lstart = march_start<U>(j0, chunk);
@@ -897,10 +902,10 @@ template <typename T> constexpr int march_waves() { return sizeof(T) == 4 ? 4 : 
 // where 3 made the ensemble step 12% slower)
 template <typename T> constexpr int fluid_march_waves() { return sizeof(T) == 4 ? 3 : 2; }
 
-template <typename T, int D, bool W32>
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
 __global__ void __launch_bounds__(256, fluid_march_waves<T>()) fluid_march_kernel(SweepParams<T> P, int chunk)
 {
-    fluid_march_lane<T, D, W32>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+    fluid_march_lane<T, D, W32, LIM>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
 
 // Inputs of the magnetic window at one position: v_n of the 5 pencils, the
@@ -963,7 +968,7 @@ struct MagLoads {
 };
 
 // One lane of a grid: magnetic operator M_d.
-template <typename T, int D, bool W32>
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
 __device__ __forceinline__ void mag_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
@@ -987,7 +992,7 @@ __device__ __forceinline__ void mag_march_lane(const SweepParams<T>& P, long gid
     const unsigned step = G.sd * A::scale;
     const unsigned gb = G.base * A::scale;
 
-    MagWindow<T> W;
+    MagWindow<T, LIM> W;
     W.init();
     const MagLoads<T, D, W32> in(P, G);
     constexpr int U = march_unroll<T>();
@@ -1026,10 +1031,10 @@ __device__ __forceinline__ void mag_march_lane(const SweepParams<T>& P, long gid
     }
 }
 
-template <typename T, int D, bool W32>
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
 __global__ void __launch_bounds__(256, march_waves<T>()) mag_march_kernel(SweepParams<T> P, int chunk)
 {
-    mag_march_lane<T, D, W32>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+    mag_march_lane<T, D, W32, LIM>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
 
 // positions unrolled per group, as in the single-operator marches
@@ -1186,8 +1191,8 @@ inline bool offsets32(const SweepParams<T>& P, const LaunchTuning& tune)
     return !tune.wide && (unsigned long long)P.nx * P.ny * P.nz * sizeof(T) <= (1ull << 32);
 }
 
-template <typename T>
-hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+template <typename T, int LIM>
+hipError_t launch_fluid_lim(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
     if (d == 0) {
         int tpr, rpw, threads;
@@ -1197,9 +1202,9 @@ hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune
         const size_t lds = sizeof(T) * 25 * threads;
         if (P.cfl_acc) {
             if (threads % 64) return hipErrorInvalidValue;      // fused CFL needs full waves
-            hipLaunchKernelGGL((fluid_x_kernel<T, true>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((fluid_x_kernel<T, true, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
         } else {
-            hipLaunchKernelGGL((fluid_x_kernel<T, false>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((fluid_x_kernel<T, false, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
         }
     } else {
         const int nd = d == 1 ? P.ny : P.nz;
@@ -1209,18 +1214,18 @@ hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune
         const long lanes = (long)npencil * (nd / chunk);
         const int grid = (int)((lanes + 255) / 256);
         if (offsets32<T>(P, tune)) {
-            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, true>), dim3(grid), dim3(256), 0, s, P, chunk);
-            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, true, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, true, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
         } else {
-            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, false>), dim3(grid), dim3(256), 0, s, P, chunk);
-            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, false, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, false, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
         }
     }
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+template <typename T, int LIM>
+hipError_t launch_magnetic_lim(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
     if (d == 0) {
         int tpr, rpw, threads;
@@ -1228,7 +1233,7 @@ hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& t
         const int nrows = P.ny * P.nz;
         const int grid = (nrows + rpw - 1) / rpw;
         const size_t lds = sizeof(T) * 16 * threads;
-        hipLaunchKernelGGL(mag_x_kernel<T>, dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+        hipLaunchKernelGGL((mag_x_kernel<T, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
     } else {
         const int nd = d == 1 ? P.ny : P.nz;
         const int npencil = P.nx * (d == 1 ? P.nz : P.ny);
@@ -1237,14 +1242,40 @@ hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& t
         const long lanes = (long)npencil * (nd / chunk);
         const int grid = (int)((lanes + 255) / 256);
         if (offsets32<T>(P, tune)) {
-            if (d == 1) hipLaunchKernelGGL((mag_march_kernel<T, 1, true>), dim3(grid), dim3(256), 0, s, P, chunk);
-            else hipLaunchKernelGGL((mag_march_kernel<T, 2, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+            if (d == 1) hipLaunchKernelGGL((mag_march_kernel<T, 1, true, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((mag_march_kernel<T, 2, true, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
         } else {
-            if (d == 1) hipLaunchKernelGGL((mag_march_kernel<T, 1, false>), dim3(grid), dim3(256), 0, s, P, chunk);
-            else hipLaunchKernelGGL((mag_march_kernel<T, 2, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+            if (d == 1) hipLaunchKernelGGL((mag_march_kernel<T, 1, false, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((mag_march_kernel<T, 2, false, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
         }
     }
     return hipGetLastError();
+}
+
+// the single operators with the limiter P.limiter (the fused pairs and the
+// ensemble kernels use van Leer's only)
+template <typename T>
+hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+{
+    switch (P.limiter) {
+    case LIM_VANLEER: return launch_fluid_lim<T, LIM_VANLEER>(P, d, tune, s);
+    case LIM_MINMOD: return launch_fluid_lim<T, LIM_MINMOD>(P, d, tune, s);
+    case LIM_MC: return launch_fluid_lim<T, LIM_MC>(P, d, tune, s);
+    case LIM_SUPERBEE: return launch_fluid_lim<T, LIM_SUPERBEE>(P, d, tune, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+{
+    switch (P.limiter) {
+    case LIM_VANLEER: return launch_magnetic_lim<T, LIM_VANLEER>(P, d, tune, s);
+    case LIM_MINMOD: return launch_magnetic_lim<T, LIM_MINMOD>(P, d, tune, s);
+    case LIM_MC: return launch_magnetic_lim<T, LIM_MC>(P, d, tune, s);
+    case LIM_SUPERBEE: return launch_magnetic_lim<T, LIM_SUPERBEE>(P, d, tune, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // the reverse-half pair M_d then F_d in one launch; P.cfl_acc (x only)
@@ -1308,6 +1339,7 @@ __device__ __forceinline__ SweepParams<T> box_params(const BatchParams<T>& B, in
     P.flag = B.flag ? B.flag + (size_t)box * FLAG_COUNT : nullptr;
     P.cfl_acc = nullptr;
     P.gamma64 = 0.0;
+    P.limiter = 0;
     return P;
 }
 

@@ -22,6 +22,7 @@ MHD_TUNE_CHUNK_Y, MHD_TUNE_CHUNK_Z, MHD_TUNE_REVERSE = 1, 2, 3
 MHD_TUNE_PAIR_CHUNK_Y, MHD_TUNE_PAIR_CHUNK_Z, MHD_TUNE_WIDE_OFFSETS = 4, 5, 6
 MHD_BATCH_GRID_X, MHD_BATCH_GRID_Y, MHD_BATCH_GRID_Z, MHD_BATCH_CHUNK = 10, 11, 12, 13
 MHD_BATCH_REVERSE, MHD_BATCH_WIDE_OFFSETS, MHD_BATCH_PAIR_CHUNK = 14, 15, 16
+MHD_LIMITER_VANLEER, MHD_LIMITER_MINMOD, MHD_LIMITER_MC, MHD_LIMITER_SUPERBEE = 0, 1, 2, 3
 
 _lib = None
 
@@ -78,6 +79,8 @@ def load():
         "mhd_restrict": (i, [vp, vp]),
         "mhd_set_launch": (i, [vp, i, i]),
         "mhd_get_launch": (i, [vp, i, ip]),
+        "mhd_set_limiter": (i, [vp, i]),
+        "mhd_get_limiter": (i, [vp, ip]),
         "mhd_batch_create": (vp, [i, ip, d, i, vp]),
         "mhd_batch_destroy": (None, [vp]),
         "mhd_batch_info": (i, [vp, ip, ctypes.POINTER(ctypes.c_longlong)]),
@@ -123,7 +126,7 @@ def exported_symbols():
                         "mhd_cfl_dt", "mhd_set_relaxation_speed", "mhd_get_relaxation_speed",
                         "mhd_fluid", "mhd_magnetic", "mhd_sweep", "mhd_step", "mhd_step_auto",
                         "mhd_status", "mhd_time", "mhd_diag", "mhd_restrict", "mhd_set_launch",
-                        "mhd_get_launch", "mhd_batch_create", "mhd_batch_destroy",
+                        "mhd_get_launch", "mhd_set_limiter", "mhd_get_limiter", "mhd_batch_create", "mhd_batch_destroy",
                         "mhd_batch_info", "mhd_batch_set_state", "mhd_batch_get_state",
                         "mhd_batch_step_auto", "mhd_batch_run", "mhd_batch_status",
                         "mhd_batch_time", "mhd_batch_set_launch", "mhd_batch_get_launch",
@@ -380,6 +383,17 @@ class Solver:
     def reverse(self):
         v = ctypes.c_int(0)
         check(self.lib.mhd_get_launch(self.h, MHD_TUNE_REVERSE, ctypes.byref(v)))
+        return v.value
+
+    def set_limiter(self, kind):
+        """slope limiter of the operators: MHD_LIMITER_VANLEER (the paper's,
+        default), _MINMOD, _MC or _SUPERBEE; other than van Leer's, the
+        reverse pairs run as two launches each"""
+        check(self.lib.mhd_set_limiter(self.h, kind))
+
+    def limiter(self):
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_get_limiter(self.h, ctypes.byref(v)))
         return v.value
 
     def restrict_to(self, coarse):

@@ -80,3 +80,12 @@ def test_library_shares_torchs_hip_runtime():
     with open("/proc/self/maps") as f:
         libs = {line.split()[-1] for line in f if "libamdhip64" in line}
     assert len(libs) == 1, libs
+
+
+def test_limiter_calls_on_a_null_handle_fail_cleanly():
+    import ctypes
+    from paper_1004_1680_amd import mhd
+    lib = mhd.load()
+    assert lib.mhd_set_limiter(None, 1) == mhd.MHD_EINVAL
+    v = ctypes.c_int(7)
+    assert lib.mhd_get_limiter(None, ctypes.byref(v)) == mhd.MHD_EINVAL

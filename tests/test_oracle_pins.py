@@ -388,3 +388,94 @@ def test_field_loop_returns_and_keeps_div_b(orc):
     assert errs[1] < errs[0] / 1.8
     # the scheme only dissipates magnetic energy, less at higher resolution
     assert 0.0 < ratios[0] < ratios[1] < 1.0
+
+
+# ---------------------------------------------------------------------------
+# slope limiter variants (minmod, MC, superbee; the paper's is van Leer's)
+# ---------------------------------------------------------------------------
+
+KINDS = {"vanleer": 0, "minmod": 1, "mc": 2, "superbee": 3}
+
+
+def test_limiter_closed_forms(orc):
+    # (a, b) -> value of each limiter, from its definition by hand
+    cases = {(1.0, 3.0): (1.5, 1.0, 2.0, 2.0), (2.0, 0.5): (0.8, 0.5, 1.0, 1.0),
+             (1.0, 1.5): (1.2, 1.0, 1.25, 1.5), (3.0, 1.0): (1.5, 1.0, 2.0, 2.0)}
+    for (a, b), want in cases.items():
+        for kind, w in zip(range(4), want):
+            assert orc.limiter_value(kind, a, b) == pytest.approx(w, rel=1e-15), (kind, a, b)
+            assert orc.limiter_value(kind, -a, -b) == pytest.approx(-w, rel=1e-15)
+    for kind in range(4):
+        for a, b in ((1.0, -2.0), (0.0, 1.0), (-3.0, 0.0), (0.0, 0.0)):
+            assert orc.limiter_value(kind, a, b) == 0.0
+
+
+def test_limiter_ordering_and_tvd_region(orc):
+    rng = np.random.default_rng(7)
+    for a, b in rng.uniform(1e-3, 10.0, size=(400, 2)):
+        v = [orc.limiter_value(k, a, b) for k in range(4)]
+        # all lie in [min, 2 min] (Sweby's second-order TVD region in slope
+        # form); minmod <= van Leer <= MC <= superbee
+        lo, hi = min(a, b), 2 * min(a, b)
+        assert all(lo * (1 - 1e-15) <= x <= hi * (1 + 1e-15) for x in v)
+        assert v[1] <= v[0] * (1 + 1e-15) and v[0] <= v[2] * (1 + 1e-15) and v[2] <= v[3] * (1 + 1e-15)
+        for k in range(4):
+            assert orc.limiter_value(k, b, a) == pytest.approx(v[k], rel=1e-15)   # symmetric
+        # equal slopes are reproduced (consistency on linear data)
+        for k in range(4):
+            assert orc.limiter_value(k, a, a) == pytest.approx(a, rel=1e-15)
+
+
+@pytest.mark.parametrize("name", ["minmod", "mc", "superbee"])
+def test_limiter_variant_invariants(orc, name):
+    kind = KINDS[name]
+    u = I.uniform((16, 12, 8), rho=1.3, v=(0.3, -0.7, 0.2), p=0.9, b=(0.4, -1.1, 0.6))
+    dt, vmax = orc.cfl(u)
+    assert np.array_equal(orc.step(u, dt, vmax, limiter=kind), u)
+    # (superbee at CFL 0.7 takes the stronger-field state amp_b = 0.25 out
+    # of the physical range within 4 steps; at CFL 0.5 it does not)
+    s = I.random_smooth((16, 12, 8), seed=3)
+    out, _, _ = orc.run(s, 4, limiter=kind)
+    before, after = orc.diag(s), orc.diag(out)
+    scale = np.array([np.abs(s[f]).sum() for f in range(8)]) / (16 ** 3)
+    assert np.all(np.abs(after[:8] - before[:8]) / scale < 1e-13)
+    assert after[8] < 1e-13
+    # the limiter really changes the result
+    ref, _, _ = orc.run(s, 4)
+    assert l1(out[6], ref[6]) > 1e-9
+
+
+@pytest.mark.parametrize("name", ["minmod", "mc", "superbee"])
+@pytest.mark.parametrize("vx", [0.5, -0.5])
+def test_limiter_variant_advection_is_tvd(orc, name, vx):
+    kind = KINDS[name]
+    N, steps = 64, 12
+    sq = lambda x: np.where((x > 0.35) & (x < 0.65), 1.0, 0.0)
+    s = advect_state(N, vx, sq)
+    dt = 0.8 / (abs(vx) * N)
+    tv = np.abs(np.diff(s[6, 0, 0], append=s[6, 0, 0, :1])).sum()
+    for _ in range(steps):
+        s = orc.mag_sweep(s, 0, dt, limiter=kind)
+        by = s[6, 0, 0]
+        tvn = np.abs(np.diff(by, append=by[:1])).sum()
+        assert tvn <= tv + 1e-12
+        assert by.min() >= -1e-12 and by.max() <= 1 + 1e-12
+        tv = tvn
+    assert s[6, 0, 0].sum() == pytest.approx(sq((np.arange(N) + 0.5) / N).sum(), rel=1e-13)
+
+
+@pytest.mark.parametrize("name,min_order", [("minmod", 1.7), ("mc", 1.9), ("superbee", 1.6)])
+def test_limiter_variant_self_convergence(orc, name, min_order):
+    """a fast wave over one crossing at 32, 64, 128 cells: observed orders
+    1.4/1.8 (minmod), 2.0/2.0 (MC), 1.0/1.8 (superbee, which steepens smooth
+    profiles)"""
+    kind = KINDS[name]
+    B, amp = (1.0, 0.0, 0.0), 1e-6
+    lam, _ = I.wave_mode("fast", 1.0, 1.0, B)
+    errs = []
+    for N in (32, 64, 128):
+        s0 = I.linear_wave((N, 8, 8), "fast", amp, B)
+        out, _, _ = orc.run(s0, 0, t_end=1.0 / abs(lam), limiter=kind)
+        errs.append(sum(l1(out[f], s0[f]) for f in range(8)) / amp)
+    order = np.log2(errs[-2] / errs[-1])
+    assert order > min_order, (errs, order)
