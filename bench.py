@@ -55,6 +55,8 @@ CLOSURE_FLOP_PER_CELL = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 8)
 ALG_WORDS = {"fluid": 8 + 5, "magnetic": 5 + 3, "pair": 8 + 8, "cfl": 8}
 STEP_WORDS = 6 * (8 + 8) + 8   # fused-sweep lower bound: 8r + 8w per sweep, + CFL
 
+LIMITERS = {"vanleer": 0, "minmod": 1, "mc": 2, "superbee": 3}
+
 WORKLOADS = {
     "turb256": dict(n=256, prec="f32", ic="turbulence",
                     desc="random-phase solenoidal turbulence 256^3, P(k)~k^-4 (1<=k<=8), "
@@ -222,9 +224,10 @@ def time_components(S, n, prec, stream, reps, torch, mhd):
     return out
 
 
-def step_launches(S, n, esize, fused, w32):
+def step_launches(S, n, esize, fused, w32, lim=0):
     """(kernel name, grid threads) of every sweep launch of one step of an
-    n^3 grid, in the profiler's naming"""
+    n^3 grid, in the profiler's naming (the single operators carry the
+    slope limiter as their last template argument)"""
     t = "double" if esize == 8 else "float"
     tpr = n // 4
     rpw = max(1, 256 // tpr)
@@ -234,18 +237,18 @@ def step_launches(S, n, esize, fused, w32):
         lanes = n * n * (n // chunk)
         return -(-lanes // 256) * 256
 
-    fx = (f"fluid_x_kernel<{t}, false>", xgrid)
-    mx = (f"mag_x_kernel<{t}>", xgrid)
-    fy = (f"fluid_march_kernel<{t}, 1, {w32}>", march(S.chunk(1)))
-    my = (f"mag_march_kernel<{t}, 1, {w32}>", march(S.chunk(1)))
-    fz = (f"fluid_march_kernel<{t}, 2, {w32}>", march(S.chunk(2)))
-    mz = (f"mag_march_kernel<{t}, 2, {w32}>", march(S.chunk(2)))
+    fx = (f"fluid_x_kernel<{t}, false, {lim}>", xgrid)
+    mx = (f"mag_x_kernel<{t}, {lim}>", xgrid)
+    fy = (f"fluid_march_kernel<{t}, 1, {w32}, {lim}>", march(S.chunk(1)))
+    my = (f"mag_march_kernel<{t}, 1, {w32}, {lim}>", march(S.chunk(1)))
+    fz = (f"fluid_march_kernel<{t}, 2, {w32}, {lim}>", march(S.chunk(2)))
+    mz = (f"mag_march_kernel<{t}, 2, {w32}, {lim}>", march(S.chunk(2)))
     if fused:
         return [fx, mx, fy, my, fz, mz,
                 (f"magfluid_march_kernel<{t}, 2, {w32}>", march(S.pair_chunk(2))),
                 (f"magfluid_march_kernel<{t}, 1, {w32}>", march(S.pair_chunk(1))),
                 (f"magfluid_x_kernel<{t}, true>", xgrid)]
-    return [fx, mx, fy, my, fz, mz, mz, fz, my, fy, mx, (f"fluid_x_kernel<{t}, true>", xgrid)]
+    return [fx, mx, fy, my, fz, mz, mz, fz, my, fy, mx, (f"fluid_x_kernel<{t}, true, {lim}>", xgrid)]
 
 
 def cpu_baseline(wl):
@@ -619,6 +622,8 @@ def main():
                     help="closure128: also evaluate learned vs plain against the 1024^3 solution")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--limiter", default="vanleer", choices=sorted(LIMITERS),
+                    help="slope limiter of the operators (the paper's: vanleer)")
     ap.add_argument("--size-sweep", default=None, metavar="SIZES",
                     help="time a full step at each n^3 (comma list, or 'default': "
                          + ",".join(map(str, SWEEP_SIZES)) + ") with the paper's four criteria")
@@ -649,6 +654,8 @@ def main():
     stream = torch.cuda.current_stream()
     log(f"[bench] workload {args.workload}: {wl['desc']}")
     S = mhd.Solver((n, n, n), prec=wl["prec"], stream=stream)
+    lim = LIMITERS[args.limiter]
+    S.set_limiter(lim)
     st = make_state_device(wl, torch)
     S.set_state_tensor(st)
     del st
@@ -682,7 +689,7 @@ def main():
     log("[bench] per-kernel timing")
     saved = S.get_state_tensor()
     kern = {}
-    fused = S.reverse() == 1
+    fused = S.reverse() == 1 and lim == 0
     ops = ("fluid", "magnetic", "pair") if fused else ("fluid", "magnetic")
     for op in ops:
         for d in range(3):
@@ -734,9 +741,12 @@ def main():
     w32 = "true" if ncell * esize <= 2 ** 32 else "false"
     axis = dom.split("_")[1][0]
     cfl_x = dom.endswith("+cfl")
-    tname = {"x": "{op}_x_kernel<{t}, " + ("true>" if cfl_x else "false>") if op != "magnetic" else "mag_x_kernel<{t}>",
-             "y": "{op}_march_kernel<{t}, 1, {w}>", "z": "{op}_march_kernel<{t}, 2, {w}>"}[axis].format(
-        op=kname, t="double" if esize == 8 else "float", w=w32)
+    # the single operators carry the slope limiter as a last template argument
+    lt = "" if op == "pair" else f", {lim}"
+    tname = {"x": ("{op}_x_kernel<{t}, " + ("true" if cfl_x else "false") + "{lt}>") if op != "magnetic"
+             else "mag_x_kernel<{t}{lt}>",
+             "y": "{op}_march_kernel<{t}, 1, {w}{lt}>", "z": "{op}_march_kernel<{t}, 2, {w}{lt}>"}[axis].format(
+        op=kname, t="double" if esize == 8 else "float", w=w32, lt=lt)
     if tname in tmap:
         traffic = tmap[tname]
     step_alg = STEP_WORDS * esize * ncell / (ms_per_step * 1e-3) / 1e9
@@ -745,7 +755,7 @@ def main():
     step_traffic = None
     if tmap:
         tot = 0
-        for name, grid in step_launches(S, n, esize, fused, w32):
+        for name, grid in step_launches(S, n, esize, fused, w32, lim):
             b = tmap.get(f"{name} @ {grid}", tmap.get(name))
             if b is None:
                 tot = None
@@ -770,6 +780,7 @@ def main():
                    "step": ("CFL (FP64) + F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x; "
                             + ("9 launches: each reverse pair M_d F_d fused, CFL in the last"
                                if fused else "12 launches")),
+                   "limiter": args.limiter,
                    "march_chunks": [S.chunk(1), S.chunk(2)],
                    "pair_chunks": [S.pair_chunk(1), S.pair_chunk(2)] if fused else None,
                    "parallelism": "single GPU"},
