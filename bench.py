@@ -226,8 +226,8 @@ def time_components(S, n, prec, stream, reps, torch, mhd):
 
 def step_launches(S, n, esize, fused, w32, lim=0):
     """(kernel name, grid threads) of every sweep launch of one step of an
-    n^3 grid, in the profiler's naming (the single operators carry the
-    slope limiter as their last template argument)"""
+    n^3 grid, in the profiler's naming (the sweep kernels carry the slope
+    limiter as their last template argument)"""
     t = "double" if esize == 8 else "float"
     tpr = n // 4
     rpw = max(1, 256 // tpr)
@@ -245,9 +245,9 @@ def step_launches(S, n, esize, fused, w32, lim=0):
     mz = (f"mag_march_kernel<{t}, 2, {w32}, {lim}>", march(S.chunk(2)))
     if fused:
         return [fx, mx, fy, my, fz, mz,
-                (f"magfluid_march_kernel<{t}, 2, {w32}>", march(S.pair_chunk(2))),
-                (f"magfluid_march_kernel<{t}, 1, {w32}>", march(S.pair_chunk(1))),
-                (f"magfluid_x_kernel<{t}, true>", xgrid)]
+                (f"magfluid_march_kernel<{t}, 2, {w32}, {lim}>", march(S.pair_chunk(2))),
+                (f"magfluid_march_kernel<{t}, 1, {w32}, {lim}>", march(S.pair_chunk(1))),
+                (f"magfluid_x_kernel<{t}, true, {lim}>", xgrid)]
     return [fx, mx, fy, my, fz, mz, mz, fz, my, fy, mx, (f"fluid_x_kernel<{t}, true, {lim}>", xgrid)]
 
 
@@ -689,7 +689,7 @@ def main():
     log("[bench] per-kernel timing")
     saved = S.get_state_tensor()
     kern = {}
-    fused = S.reverse() == 1 and lim == 0
+    fused = S.reverse() == 1
     ops = ("fluid", "magnetic", "pair") if fused else ("fluid", "magnetic")
     for op in ops:
         for d in range(3):
@@ -741,8 +741,8 @@ def main():
     w32 = "true" if ncell * esize <= 2 ** 32 else "false"
     axis = dom.split("_")[1][0]
     cfl_x = dom.endswith("+cfl")
-    # the single operators carry the slope limiter as a last template argument
-    lt = "" if op == "pair" else f", {lim}"
+    # the sweep kernels carry the slope limiter as a last template argument
+    lt = f", {lim}"
     tname = {"x": ("{op}_x_kernel<{t}, " + ("true" if cfl_x else "false") + "{lt}>") if op != "magnetic"
              else "mag_x_kernel<{t}{lt}>",
              "y": "{op}_march_kernel<{t}, 1, {w}{lt}>", "z": "{op}_march_kernel<{t}, 2, {w}{lt}>"}[axis].format(

@@ -147,9 +147,8 @@ int mhd_sweep(mhd_ctx *h, int dim, double dt);
  *   MHD_LIMITER_MC        sign(a) min(2|a|, 2|b|, |a+b|/2)
  *   MHD_LIMITER_SUPERBEE  sign(a) max(min(2|a|, |b|), min(|a|, 2|b|))
  * and 0 when a b <= 0.  Applies to the handle's operators, sweeps and steps
- * from the next call on; with a limiter other than van Leer's the reverse
- * pairs run as two launches each.  MHD_EINVAL for another value.  Ensembles
- * always use van Leer's. */
+ * (fused reverse pairs included) from the next call on.  MHD_EINVAL for
+ * another value.  Ensembles always use van Leer's. */
 enum { MHD_LIMITER_VANLEER = 0, MHD_LIMITER_MINMOD = 1, MHD_LIMITER_MC = 2, MHD_LIMITER_SUPERBEE = 3 };
 int mhd_set_limiter(mhd_ctx *h, int limiter);
 int mhd_get_limiter(const mhd_ctx *h, int *limiter);
@@ -197,7 +196,9 @@ int mhd_restrict(mhd_ctx *fine, mhd_ctx *coarse);
  * key MHD_TUNE_REVERSE: how the reverse-half pairs M_d F_d of a step and of
  * mhd_sweep(3..5) run: 1 = one fused launch per pair (the new faces stay
  * in registers; 9 launches per step), 2 = the two operators in turn (12
- * launches), 0 = the built-in choice (1 in FP32, 2 in FP64).
+ * launches), 0 = the built-in choice (1 in FP32 with the van Leer or
+ * minmod limiter, 2 otherwise: the fused MC and superbee kernels spill
+ * registers); mhd_get_launch reports the resolved 1 or 2.
  * key MHD_TUNE_WIDE_OFFSETS: 1 makes the y and z sweeps address memory with
  * 64-bit arithmetic per access, as they must for fields over 4 GiB; 0 (the
  * default) uses 32-bit byte offsets wherever they fit.

@@ -69,7 +69,7 @@ struct mhd_ctx {
     bool fuse_ok;           // grid shape allows the fused epilogue
     // reverse-half pairs M_d F_d: one fused launch each (true) or the two
     // operators in turn; same result bit for bit
-    bool rev_fused;
+    int rev_mode;           // 0 built-in choice, 1 fused, 2 the two operators
     int limiter;            // slope limiter of the operators (MHD_LIMITER_*)
     double scal_dt, scal_c;
     bool failed;
@@ -128,9 +128,13 @@ static void default_tuning(mhd_ctx* h)
     }
 }
 
-static bool default_rev_fused(int prec)
+// built-in choice of fused reverse pairs: FP32 with van Leer's or minmod
+// (measured faster at 256^3); not with MC or superbee, whose fused march
+// kernels spill registers (2-3% and 34% slower than the two operators), nor
+// in FP64 (the fused FP64 march runs 1 wave per SIMD)
+static bool default_rev_fused(int prec, int limiter)
 {
-    return prec == MHD_F32;
+    return prec == MHD_F32 && (limiter == MHD_LIMITER_VANLEER || limiter == MHD_LIMITER_MINMOD);
 }
 
 static int sync_stream(mhd_ctx* h)
@@ -261,7 +265,7 @@ extern "C" mhd_ctx* mhd_create_ex(int nx, int ny, int nz, double gamma, int prec
         return nullptr;
     }
     default_tuning(h);
-    h->rev_fused = default_rev_fused(prec);
+    h->rev_mode = 0;
     h->fuse_ok = prec == MHD_F64 ? fused_cfl_possible<double>(nx) : fused_cfl_possible<float>(nx);
     h->acc_valid = false;
     return h;
@@ -585,9 +589,11 @@ extern "C" int mhd_magnetic(mhd_ctx* h, int dim, double dt)
     return MHD_OK;
 }
 
-// the reverse pairs run as one fused launch: when asked for and with van
-// Leer's limiter (the fused kernels have no other)
-static bool pairs_fused(const mhd_ctx* h) { return h->rev_fused && h->limiter == MHD_LIMITER_VANLEER; }
+// the reverse pairs run as one fused launch each
+static bool pairs_fused(const mhd_ctx* h)
+{
+    return h->rev_mode == 1 || (h->rev_mode == 0 && default_rev_fused(h->prec, h->limiter));
+}
 
 extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
 {
@@ -623,7 +629,7 @@ extern "C" int mhd_sweep(mhd_ctx* h, int dim, double dt)
 
 // the 12 operators of a full step: x, y, z forward (fluid, magnetic), then
 // z, y, x reverse (magnetic, fluid), each reverse pair in one launch when
-// rev_fused (9 launches).  acc (nullable): the last operator (F_x) also
+// pairs_fused (9 launches).  acc (nullable): the last operator (F_x) also
 // accumulates the CFL maximum of the state it leaves.
 static int enqueue_step_ops(mhd_ctx* h, const int* flag, unsigned long long* acc)
 {
@@ -801,7 +807,7 @@ extern "C" int mhd_set_launch(mhd_ctx* h, int key, int value)
     if (key == MHD_TUNE_REVERSE) {
         if (value < 0 || value > 2)
             return fail(MHD_EINVAL, "reverse-half choice must be 0, 1 or 2 (got %d)", value);
-        h->rev_fused = value == 0 ? default_rev_fused(h->prec) : value == 1;
+        h->rev_mode = value;
         return MHD_OK;
     }
     if (key == MHD_TUNE_WIDE_OFFSETS) {
@@ -832,7 +838,7 @@ extern "C" int mhd_get_launch(const mhd_ctx* h, int key, int* value)
 {
     if (!h || !value) return fail(MHD_EINVAL, "null argument");
     if (key == MHD_TUNE_REVERSE) {
-        *value = h->rev_fused ? 1 : 2;
+        *value = pairs_fused(h) ? 1 : 2;
         return MHD_OK;
     }
     if (key == MHD_TUNE_WIDE_OFFSETS) {

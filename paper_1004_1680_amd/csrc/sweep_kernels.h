@@ -530,7 +530,7 @@ __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, i
 // of 25 values per thread (the magnetic part uses the first 16; the b_x
 // exchange uses values 20..21, which the fluid part first writes after a
 // barrier that follows its last read).
-template <typename T, bool CFL = false>
+template <typename T, bool CFL = false, int LIM = LIM_VANLEER>
 __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
                                                 int rows_per_wg, T* const A)
 {
@@ -549,7 +549,7 @@ __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int til
         return;
     }
     T nb[5][4];
-    mag_x_core(P, R, nb, A);
+    mag_x_core<T, LIM>(P, R, nb, A);
     // new b_x of the first cell -> previous thread
     T* const X = A + 20 * blockDim.x;
     X[R.t] = nb[4][0];
@@ -575,14 +575,14 @@ __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int til
         }
     }
     load_u4(P, R, base, u);
-    fluid_x_core<T, CFL>(P, R, base, u, bb, fb, A);
+    fluid_x_core<T, CFL, LIM>(P, R, base, u, bb, fb, A);
 }
 
-template <typename T, bool CFL>
+template <typename T, bool CFL, int LIM = LIM_VANLEER>
 __global__ void __launch_bounds__(256) magfluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    magfluid_x_tile<T, CFL>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    magfluid_x_tile<T, CFL, LIM>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -1052,7 +1052,7 @@ template <typename T> constexpr int magfluid_unroll() { return march_unroll<T>()
 //   at s-7.
 // Fluid outputs j0 .. j0+chunk-1 need new faces at j0-3 .. j0+chunk+3, which
 // need magnetic inputs from j0-6: chunk + 13 positions.
-template <typename T, int D, bool W32>
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
 __device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
@@ -1077,9 +1077,9 @@ __device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, lon
     const unsigned step = G.sd * A::scale;
     const unsigned gb = G.base * A::scale;
 
-    MagWindow<T> WM;
+    MagWindow<T, LIM> WM;
     WM.init();
-    FluidWindow<T> WF;
+    FluidWindow<T, LIM> WF;
     WF.init();
     const MagLoads<T, D, W32> in(P, G);
     constexpr int U = magfluid_unroll<T>();
@@ -1156,10 +1156,10 @@ __device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, lon
 // per SIMD without spills (3 waves spill ~100 VGPRs); FP64 takes 1
 template <typename T> constexpr int magfluid_waves() { return sizeof(T) == 4 ? 2 : 1; }
 
-template <typename T, int D, bool W32>
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
 __global__ void __launch_bounds__(256, magfluid_waves<T>()) magfluid_march_kernel(SweepParams<T> P, int chunk)
 {
-    magfluid_march_lane<T, D, W32>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+    magfluid_march_lane<T, D, W32, LIM>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1252,8 +1252,8 @@ hipError_t launch_magnetic_lim(const SweepParams<T>& P, int d, const LaunchTunin
     return hipGetLastError();
 }
 
-// the single operators with the limiter P.limiter (the fused pairs and the
-// ensemble kernels use van Leer's only)
+// the single operators with the limiter P.limiter (the ensemble kernels use
+// van Leer's only)
 template <typename T>
 hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
@@ -1280,8 +1280,8 @@ hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& t
 
 // the reverse-half pair M_d then F_d in one launch; P.cfl_acc (x only)
 // adds the fused CFL epilogue
-template <typename T>
-hipError_t launch_magfluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+template <typename T, int LIM>
+hipError_t launch_magfluid_lim(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
     if (d == 0) {
         int tpr, rpw, threads;
@@ -1291,9 +1291,9 @@ hipError_t launch_magfluid(const SweepParams<T>& P, int d, const LaunchTuning& t
         const size_t lds = sizeof(T) * 25 * threads;
         if (P.cfl_acc) {
             if (threads % 64) return hipErrorInvalidValue;      // fused CFL needs full waves
-            hipLaunchKernelGGL((magfluid_x_kernel<T, true>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((magfluid_x_kernel<T, true, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
         } else {
-            hipLaunchKernelGGL((magfluid_x_kernel<T, false>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((magfluid_x_kernel<T, false, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
         }
     } else {
         if (P.cfl_acc) return hipErrorInvalidValue;
@@ -1304,14 +1304,26 @@ hipError_t launch_magfluid(const SweepParams<T>& P, int d, const LaunchTuning& t
         const long lanes = (long)npencil * (nd / chunk);
         const int grid = (int)((lanes + 255) / 256);
         if (offsets32<T>(P, tune)) {
-            if (d == 1) hipLaunchKernelGGL((magfluid_march_kernel<T, 1, true>), dim3(grid), dim3(256), 0, s, P, chunk);
-            else hipLaunchKernelGGL((magfluid_march_kernel<T, 2, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+            if (d == 1) hipLaunchKernelGGL((magfluid_march_kernel<T, 1, true, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((magfluid_march_kernel<T, 2, true, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
         } else {
-            if (d == 1) hipLaunchKernelGGL((magfluid_march_kernel<T, 1, false>), dim3(grid), dim3(256), 0, s, P, chunk);
-            else hipLaunchKernelGGL((magfluid_march_kernel<T, 2, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+            if (d == 1) hipLaunchKernelGGL((magfluid_march_kernel<T, 1, false, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((magfluid_march_kernel<T, 2, false, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
         }
     }
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_magfluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+{
+    switch (P.limiter) {
+    case LIM_VANLEER: return launch_magfluid_lim<T, LIM_VANLEER>(P, d, tune, s);
+    case LIM_MINMOD: return launch_magfluid_lim<T, LIM_MINMOD>(P, d, tune, s);
+    case LIM_MC: return launch_magfluid_lim<T, LIM_MC>(P, d, tune, s);
+    case LIM_SUPERBEE: return launch_magfluid_lim<T, LIM_SUPERBEE>(P, d, tune, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------------------------

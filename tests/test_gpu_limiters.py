@@ -2,7 +2,8 @@
 on the GPU against the oracle run with the same limiter: every operator
 along every axis and full steps, in both tiers, with the tolerances of
 test_gpu_parity.py; device-dt steps; switching back to van Leer's restores
-the fused path bit for bit; argument checks."""
+the fused path bit for bit; the fused reverse pairs with each variant equal
+the two operators bit for bit; argument checks."""
 import sys
 
 import numpy as np
@@ -88,10 +89,39 @@ def test_limiter_steps_parity(M, prec, kind):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("d", [0, 1, 2])
+def test_limiter_fused_pair_is_the_two_operators(M, prec, kind, d):
+    """the fused reverse pair M_d F_d with a variant limiter equals the two
+    operators bit for bit, and the oracle's M_d then F_d"""
+    n = (40, 24, 16)
+    say(f"case: limiter {kind} fused pair d={d} {prec}")
+    s = I.random_smooth(n, seed=31 + d)
+    if prec == "f32":
+        s = f32_round(s)
+    dt, c = 0.35 / n[0] / 2.5, 3.1
+    outs = []
+    for mode in (1, 2):
+        S = M.Solver(n, prec=prec)
+        S.set_reverse(mode)
+        S.set_limiter(kind)
+        S.set_state(s)
+        S.set_relaxation_speed(c)
+        S.sweep(3 + d, dt)
+        outs.append(S.get_state())
+        S.close()
+    assert np.array_equal(outs[0], outs[1])
+    o = oracle.fluid_sweep(oracle.mag_sweep(s, d, dt, limiter=kind), d, dt, c, limiter=kind)
+    err = max_family_err(outs[0], o)
+    say("err", err)
+    assert err <= (2e-5 if prec == "f32" else 1e-12)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_limiter_device_steps_and_switch_back(M, prec):
-    """device-dt steps with a variant equal those of a handle that runs the
-    reverse pairs separately anyway; back on van Leer's, the (fused, in
-    FP32) steps equal a fresh handle's from the same state"""
+    """device-dt steps with a variant are the same with fused and with
+    separate reverse pairs; back on van Leer's, the steps equal a fresh
+    handle's from the same state"""
     n = (32, 32, 32)
     say(f"case: limiter device steps, switch back {prec}")
     s = I.random_smooth(n, seed=12)
@@ -132,4 +162,13 @@ def test_limiter_key_checks(M):
     assert S.limiter() == M.MHD_LIMITER_VANLEER
     S.set_limiter(M.MHD_LIMITER_SUPERBEE)
     assert S.limiter() == M.MHD_LIMITER_SUPERBEE
+    # the built-in reverse-pair choice follows the limiter (FP32: fused for
+    # van Leer's and minmod, the two operators for MC and superbee); an
+    # explicit choice stays
+    for kind, want in ((0, 1), (1, 1), (2, 2), (3, 2)):
+        S.set_limiter(kind)
+        assert S.reverse() == want, kind
+    S.set_reverse(1)
+    S.set_limiter(M.MHD_LIMITER_SUPERBEE)
+    assert S.reverse() == 1
     S.close()
