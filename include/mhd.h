@@ -148,7 +148,7 @@ int mhd_sweep(mhd_ctx *h, int dim, double dt);
  *   MHD_LIMITER_SUPERBEE  sign(a) max(min(2|a|, |b|), min(|a|, 2|b|))
  * and 0 when a b <= 0.  Applies to the handle's operators, sweeps and steps
  * (fused reverse pairs included) from the next call on.  MHD_EINVAL for
- * another value.  Ensembles always use van Leer's. */
+ * another value.  Ensembles have their own setting (mhd_batch_set_limiter). */
 enum { MHD_LIMITER_VANLEER = 0, MHD_LIMITER_MINMOD = 1, MHD_LIMITER_MC = 2, MHD_LIMITER_SUPERBEE = 3 };
 int mhd_set_limiter(mhd_ctx *h, int limiter);
 int mhd_get_limiter(const mhd_ctx *h, int *limiter);
@@ -254,7 +254,8 @@ int mhd_batch_time(mhd_batch *b, double *times);
  * box takes the largest divisor of its axis length <= target, >= 8), and
  * MHD_BATCH_REVERSE as MHD_TUNE_REVERSE of a single grid (1: each
  * reverse-half pair M_d F_d in one launch, 2: the two operators in turn,
- * 0: built-in, 1 in FP32 and 2 in FP64), the target march chunk of the
+ * 0: built-in, 1 in FP32 with the van Leer or minmod limiter, 2 otherwise),
+ * the target march chunk of the
  * fused pairs (MHD_BATCH_PAIR_CHUNK, default 128), and MHD_BATCH_WIDE_OFFSETS
  * as MHD_TUNE_WIDE_OFFSETS.
  * Launch-shape parameters, not part of the method. */
@@ -263,6 +264,13 @@ enum { MHD_BATCH_GRID_X = 10, MHD_BATCH_GRID_Y = 11, MHD_BATCH_GRID_Z = 12,
        MHD_BATCH_PAIR_CHUNK = 16 };
 int mhd_batch_set_launch(mhd_batch *b, int key, int value);
 int mhd_batch_get_launch(const mhd_batch *b, int key, int *value);
+
+/* Slope limiter of every box's operators (MHD_LIMITER_*, as mhd_set_limiter;
+ * van Leer's by default).  Synchronises the ensemble's stream and drops a
+ * captured step graph (the next graph run captures again).  MHD_EINVAL for
+ * another value. */
+int mhd_batch_set_limiter(mhd_batch *b, int limiter);
+int mhd_batch_get_limiter(const mhd_batch *b, int *limiter);
 
 /* ------------------------------------------------------------------------
  * Learned closure of a coarse grid (an addition to the paper's method).

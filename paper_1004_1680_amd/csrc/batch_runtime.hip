@@ -50,7 +50,8 @@ struct mhd_batch {
     int grid[3];
     int chunk_target;
     int pair_chunk_target;
-    bool rev_fused;         // reverse-half pairs M_d F_d in one launch each
+    int rev_mode;           // reverse-half pairs M_d F_d: 0 built-in, 1 one launch each, 2 two
+    int limiter;            // slope limiter of the operators (MHD_LIMITER_*)
     bool wide;              // 64-bit addressing in the marches even where 32-bit offsets fit
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -183,7 +184,8 @@ extern "C" mhd_batch* mhd_batch_create(int nbox, const int* dims, double gamma, 
     b->esize = prec == MHD_F64 ? sizeof(double) : sizeof(float);
     b->chunk_target = 64;
     b->pair_chunk_target = 128;
-    b->rev_fused = prec == MHD_F32;
+    b->rev_mode = 0;
+    b->limiter = MHD_LIMITER_VANLEER;
     b->wide = false;
     b->d_boxes = nullptr;
     for (int d = 0; d < 3; ++d) {
@@ -351,6 +353,15 @@ extern "C" int mhd_batch_get_state(mhd_batch* b, int box, double* host, size_t n
     return MHD_OK;
 }
 
+// reverse-half pairs in one launch each: asked for, or the built-in choice
+// (FP32 with van Leer's or minmod, as for a single grid)
+static bool batch_pairs_fused(const mhd_batch* b)
+{
+    return b->rev_mode == 1 ||
+           (b->rev_mode == 0 && b->prec == MHD_F32 &&
+            (b->limiter == MHD_LIMITER_VANLEER || b->limiter == MHD_LIMITER_MINMOD));
+}
+
 template <typename T>
 static int enqueue_batch_step(mhd_batch* b, double cfl)
 {
@@ -364,10 +375,11 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
                                          { 1, 2 }, { 0, 2 }, { 1, 1 }, { 0, 1 }, { 1, 0 }, { 0, 0 } };
     static const int fused[9][2] = { { 0, 0 }, { 1, 0 }, { 0, 1 }, { 1, 1 }, { 0, 2 }, { 1, 2 },
                                      { 2, 2 }, { 2, 1 }, { 2, 0 } };
-    const int nops = b->rev_fused ? 9 : 12;
+    const bool fz = batch_pairs_fused(b);
+    const int nops = fz ? 9 : 12;
     for (int k = 0; k < nops; ++k) {
-        const int op = b->rev_fused ? fused[k][0] : separate[k][0];
-        const int d = b->rev_fused ? fused[k][1] : separate[k][1];
+        const int op = fz ? fused[k][0] : separate[k][0];
+        const int d = fz ? fused[k][1] : separate[k][1];
         BatchParams<T> P;
         for (int q = 0; q < 8; ++q) {
             P.in_base[q] = reinterpret_cast<const T*>(b->buf[b->cur[q]]);
@@ -382,6 +394,7 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
         P.scal = b->scal;
         P.flag = b->flag;
         P.offsets32 = !b->wide;
+        P.limiter = b->limiter;
         for (const BoxDesc& bd : b->boxes)
             if ((unsigned long long)bd.ncell * (b->prec == MHD_F64 ? 8 : 4) > (1ull << 32)) P.offsets32 = false;
         const int grid = std::max(8, std::min(b->grid[d], (P.nitems + 7) / 8 * 8));
@@ -506,11 +519,31 @@ extern "C" int mhd_batch_set_launch(mhd_batch* b, int key, int value)
     if (key == MHD_BATCH_REVERSE) {
         if (value < 0 || value > 2)
             return mhd_fail(MHD_EINVAL, "reverse-half choice must be 0, 1 or 2 (got %d)", value);
-        b->rev_fused = value == 0 ? b->prec == MHD_F32 : value == 1;
+        b->rev_mode = value;
         drop_graph(b);
         return MHD_OK;
     }
     return mhd_fail(MHD_EINVAL, "unknown launch key %d", key);
+}
+
+extern "C" int mhd_batch_set_limiter(mhd_batch* b, int limiter)
+{
+    int r = check_batch(b);
+    if (r) return r;
+    if (limiter < MHD_LIMITER_VANLEER || limiter > MHD_LIMITER_SUPERBEE)
+        return mhd_fail(MHD_EINVAL, "limiter must be 0..3 (got %d)", limiter);
+    HIP_TRY(b, hipSetDevice(b->device));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    b->limiter = limiter;
+    drop_graph(b);          // a captured step holds the kernels of the old limiter
+    return MHD_OK;
+}
+
+extern "C" int mhd_batch_get_limiter(const mhd_batch* b, int* limiter)
+{
+    if (!b || !limiter) return mhd_fail(MHD_EINVAL, "null argument");
+    *limiter = b->limiter;
+    return MHD_OK;
 }
 
 extern "C" int mhd_batch_get_launch(const mhd_batch* b, int key, int* value)
@@ -523,7 +556,7 @@ extern "C" int mhd_batch_get_launch(const mhd_batch* b, int key, int* value)
     else if (key == MHD_BATCH_PAIR_CHUNK)
         *value = b->pair_chunk_target;
     else if (key == MHD_BATCH_REVERSE)
-        *value = b->rev_fused ? 1 : 2;
+        *value = batch_pairs_fused(b) ? 1 : 2;
     else if (key == MHD_BATCH_WIDE_OFFSETS)
         *value = b->wide ? 1 : 0;
     else

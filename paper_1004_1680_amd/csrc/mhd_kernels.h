@@ -68,6 +68,7 @@ struct BatchParams {
     const double* scal;           // per box: SCAL_COUNT doubles
     const int* flag;              // per box: FLAG_COUNT ints (null: never skip)
     bool offsets32;               // every box's fields have 32-bit byte offsets
+    int limiter;                  // slope limiter (LIM_*; 0: van Leer)
 };
 
 // op 0 fluid, 1 magnetic, 2 magnetic then fluid in one pass (the reverse-half

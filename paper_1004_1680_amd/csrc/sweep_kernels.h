@@ -1252,8 +1252,7 @@ hipError_t launch_magnetic_lim(const SweepParams<T>& P, int d, const LaunchTunin
     return hipGetLastError();
 }
 
-// the single operators with the limiter P.limiter (the ensemble kernels use
-// van Leer's only)
+// the single operators with the limiter P.limiter
 template <typename T>
 hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
@@ -1363,7 +1362,7 @@ constexpr int batch_waves(int d)
 }
 
 // W32: every box's fields have 32-bit byte offsets (see Addr)
-template <typename T, int OP, int D, bool W32>
+template <typename T, int OP, int D, bool W32, int LIM = LIM_VANLEER>
 __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kernel(BatchParams<T> B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1378,44 +1377,56 @@ __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kern
         const SweepParams<T> P = box_params(B, it.x, bd);
         if constexpr (D == 0) {
             if constexpr (OP == 0)
-                fluid_x_tile(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
+                fluid_x_tile<T, false, LIM>(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
             else if constexpr (OP == 1)
-                mag_x_tile(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
+                mag_x_tile<T, LIM>(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
             else
-                magfluid_x_tile(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
+                magfluid_x_tile<T, false, LIM>(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
         } else {
             const long gid = (long)it.y * blockDim.x + threadIdx.x;
             if constexpr (OP == 0)
-                fluid_march_lane<T, D, W32>(P, gid, bd.chunk[D]);
+                fluid_march_lane<T, D, W32, LIM>(P, gid, bd.chunk[D]);
             else if constexpr (OP == 1)
-                mag_march_lane<T, D, W32>(P, gid, bd.chunk[D]);
+                mag_march_lane<T, D, W32, LIM>(P, gid, bd.chunk[D]);
             else
-                magfluid_march_lane<T, D, W32>(P, gid, bd.pchunk[D]);
+                magfluid_march_lane<T, D, W32, LIM>(P, gid, bd.pchunk[D]);
         }
     }
 }
 
-template <typename T, int OP>
+template <typename T, int OP, int LIM>
 static void launch_batch_op_dir(const BatchParams<T>& B, int d, int grid, size_t lds, hipStream_t s)
 {
     // x tiles have no march addressing: one instantiation
-    if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 0, true>), dim3(grid), dim3(256), lds, s, B);
+    if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 0, true, LIM>), dim3(grid), dim3(256), lds, s, B);
     else if (B.offsets32) {
-        if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 1, true>), dim3(grid), dim3(256), lds, s, B);
-        else hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 2, true>), dim3(grid), dim3(256), lds, s, B);
+        if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 1, true, LIM>), dim3(grid), dim3(256), lds, s, B);
+        else hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 2, true, LIM>), dim3(grid), dim3(256), lds, s, B);
     } else {
-        if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 1, false>), dim3(grid), dim3(256), lds, s, B);
-        else hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 2, false>), dim3(grid), dim3(256), lds, s, B);
+        if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 1, false, LIM>), dim3(grid), dim3(256), lds, s, B);
+        else hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 2, false, LIM>), dim3(grid), dim3(256), lds, s, B);
     }
+}
+
+template <typename T, int LIM>
+static void launch_batch_op_lim(const BatchParams<T>& B, int op, int d, int grid, size_t lds, hipStream_t s)
+{
+    if (op == 0) launch_batch_op_dir<T, 0, LIM>(B, d, grid, lds, s);
+    else if (op == 1) launch_batch_op_dir<T, 1, LIM>(B, d, grid, lds, s);
+    else launch_batch_op_dir<T, 2, LIM>(B, d, grid, lds, s);
 }
 
 template <typename T>
 hipError_t launch_batch_op(const BatchParams<T>& B, int op, int d, int grid, hipStream_t s)
 {
     const size_t lds = d == 0 ? sizeof(T) * (op == 1 ? 16 : 25) * 256 : 0;
-    if (op == 0) launch_batch_op_dir<T, 0>(B, d, grid, lds, s);
-    else if (op == 1) launch_batch_op_dir<T, 1>(B, d, grid, lds, s);
-    else launch_batch_op_dir<T, 2>(B, d, grid, lds, s);
+    switch (B.limiter) {
+    case LIM_VANLEER: launch_batch_op_lim<T, LIM_VANLEER>(B, op, d, grid, lds, s); break;
+    case LIM_MINMOD: launch_batch_op_lim<T, LIM_MINMOD>(B, op, d, grid, lds, s); break;
+    case LIM_MC: launch_batch_op_lim<T, LIM_MC>(B, op, d, grid, lds, s); break;
+    case LIM_SUPERBEE: launch_batch_op_lim<T, LIM_SUPERBEE>(B, op, d, grid, lds, s); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

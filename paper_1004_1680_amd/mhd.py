@@ -92,6 +92,8 @@ def load():
         "mhd_batch_time": (i, [vp, dp]),
         "mhd_batch_set_launch": (i, [vp, i, i]),
         "mhd_batch_get_launch": (i, [vp, i, ip]),
+        "mhd_batch_set_limiter": (i, [vp, i]),
+        "mhd_batch_get_limiter": (i, [vp, ip]),
         "mhd_closure_create": (vp, [i, i, i, vp]),
         "mhd_closure_destroy": (None, [vp]),
         "mhd_closure_set_params": (i, [vp, fp, sz]),
@@ -130,6 +132,7 @@ def exported_symbols():
                         "mhd_batch_info", "mhd_batch_set_state", "mhd_batch_get_state",
                         "mhd_batch_step_auto", "mhd_batch_run", "mhd_batch_status",
                         "mhd_batch_time", "mhd_batch_set_launch", "mhd_batch_get_launch",
+                        "mhd_batch_set_limiter", "mhd_batch_get_limiter",
                         "mhd_closure_create", "mhd_closure_destroy", "mhd_closure_set_params",
                         "mhd_closure_get_params", "mhd_closure_set_scales", "mhd_closure_forward",
                         "mhd_closure_grad", "mhd_closure_train_step", "mhd_closure_step",
@@ -490,6 +493,15 @@ class Batch:
     def launch(self, key):
         v = ctypes.c_int(0)
         check(self.lib.mhd_batch_get_launch(self.h, key, ctypes.byref(v)))
+        return v.value
+
+    def set_limiter(self, kind):
+        """slope limiter of every box (MHD_LIMITER_*; van Leer's by default)"""
+        check(self.lib.mhd_batch_set_limiter(self.h, kind))
+
+    def limiter(self):
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_batch_get_limiter(self.h, ctypes.byref(v)))
         return v.value
 
 

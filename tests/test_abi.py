@@ -89,3 +89,5 @@ def test_limiter_calls_on_a_null_handle_fail_cleanly():
     assert lib.mhd_set_limiter(None, 1) == mhd.MHD_EINVAL
     v = ctypes.c_int(7)
     assert lib.mhd_get_limiter(None, ctypes.byref(v)) == mhd.MHD_EINVAL
+    assert lib.mhd_batch_set_limiter(None, 1) == mhd.MHD_EINVAL
+    assert lib.mhd_batch_get_limiter(None, ctypes.byref(v)) == mhd.MHD_EINVAL

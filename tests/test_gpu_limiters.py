@@ -172,3 +172,64 @@ def test_limiter_key_checks(M):
     S.set_limiter(M.MHD_LIMITER_SUPERBEE)
     assert S.reverse() == 1
     S.close()
+
+
+BDIMS = [(16, 16, 16), (24, 16, 32), (8, 12, 16)]
+
+
+def single_box_steps(M, n, s, kinds_steps):
+    S = M.Solver(n, prec="f32")
+    S.set_state(s)
+    total = 0
+    for kind, k in kinds_steps:
+        S.set_limiter(kind)
+        for _ in range(k):
+            S.step_auto(0.7)
+        total += k
+    assert S.status() == total
+    out = S.get_state()
+    S.close()
+    return out
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_limiter_equals_single_boxes(M, kind, graph):
+    """an ensemble with a variant limiter evolves every box bit for bit as
+    a single-grid handle with that limiter, eagerly or from a graph"""
+    say(f"case: batch limiter {kind} graph={graph}")
+    ss = [I.random_smooth(n, seed=70 + i) for i, n in enumerate(BDIMS)]
+    ref = [single_box_steps(M, n, s, [(kind, 3)]) for n, s in zip(BDIMS, ss)]
+    B = M.Batch(BDIMS, prec="f32")
+    B.set_limiter(kind)
+    assert B.limiter() == kind
+    for i, s in enumerate(ss):
+        B.set_state(i, s)
+    B.run(3, graph=graph)
+    steps, nonphys = B.status()
+    assert list(steps) == [3] * len(BDIMS) and not nonphys.any()
+    for i in range(len(BDIMS)):
+        assert np.array_equal(B.get_state(i), ref[i]), i
+    B.close()
+
+
+def test_batch_limiter_change_recaptures_the_graph(M):
+    """graph steps with van Leer's, then with MC: the captured step of the
+    first limiter is not replayed for the second"""
+    say("case: batch limiter change between graph runs")
+    ss = [I.random_smooth(n, seed=80 + i) for i, n in enumerate(BDIMS)]
+    ref = [single_box_steps(M, n, s, [(0, 2), (2, 2)]) for n, s in zip(BDIMS, ss)]
+    B = M.Batch(BDIMS, prec="f32")
+    for i, s in enumerate(ss):
+        B.set_state(i, s)
+    B.run(2, graph=True)
+    B.set_limiter(M.MHD_LIMITER_MC)
+    B.run(2, graph=True)
+    steps, nonphys = B.status()
+    assert list(steps) == [4] * len(BDIMS) and not nonphys.any()
+    for i in range(len(BDIMS)):
+        assert np.array_equal(B.get_state(i), ref[i]), i
+    with pytest.raises(M.MHDError):
+        B.set_limiter(5)
+    assert B.limiter() == M.MHD_LIMITER_MC
+    B.close()
