@@ -308,6 +308,7 @@ def run_ensemble(args, wl, torch, mhd):
     spec = I.ensemble_spec(nbox=64, seed=4)
     dims = [(n, n, n) for n, _, _, _ in spec]
     B = mhd.Batch(dims, prec=wl["prec"])
+    B.set_limiter(LIMITERS[args.limiter])
     ncell = B.ncell
     for i, (n, m, b, sd) in enumerate(spec):
         B.set_state(i, I.turbulence((n, n, n), seed=sd, mach=m, beta=b))
@@ -340,7 +341,7 @@ def run_ensemble(args, wl, torch, mhd):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "boxes": len(dims), "cells": ncell, "cfl": args.cfl,
-                   "launch": shape, "parallelism": "single GPU"},
+                   "limiter": args.limiter, "launch": shape, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm",
                      "kernel": "whole step (" + ("3 split pairs, 3 fused reverse pairs" if fused
                                                  else "12 split operators") + ", per-box CFL)",
