@@ -635,8 +635,8 @@ def main():
                     help="size sweep: smallest n of the large-box slope fit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(a multi-GPU decomposition is designed, not built)", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(a multi-GPU decomposition is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
