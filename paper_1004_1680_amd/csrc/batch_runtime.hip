@@ -52,6 +52,11 @@ struct mhd_batch {
     int pair_chunk_target;
     int rev_mode;           // reverse-half pairs M_d F_d: 0 built-in, 1 one launch each, 2 two
     int limiter;            // slope limiter of the operators (MHD_LIMITER_*)
+    // fused CFL: the last launch of a step leaves each box's FP64 maximum
+    // signal speed in cfl_acc (CFL_ACC_SLOTS + 1 words per box); acc_valid
+    // while the state is the one those maxima describe
+    unsigned long long* cfl_acc;
+    bool acc_valid;
     bool wide;              // 64-bit addressing in the marches even where 32-bit offsets fit
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -142,7 +147,7 @@ extern "C" void mhd_batch_destroy(mhd_batch* b)
     drop_graph(b);
     free_lists(b);
     void* ptrs[] = { b->buf[0], b->buf[1], b->scal, b->flag, b->d_cfl_items, b->d_item_first,
-                     b->partial, b->partial_bad };
+                     b->partial, b->partial_bad, b->cfl_acc };
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
@@ -242,7 +247,8 @@ extern "C" mhd_batch* mhd_batch_create(int nbox, const int* dims, double gamma, 
               hipMalloc(&b->d_cfl_items, sizeof(int2) * cfl_items.size()) == hipSuccess &&
               hipMalloc(&b->d_item_first, sizeof(int) * (nbox + 1)) == hipSuccess &&
               hipMalloc(&b->partial, sizeof(double) * cfl_items.size()) == hipSuccess &&
-              hipMalloc(&b->partial_bad, sizeof(int) * cfl_items.size()) == hipSuccess;
+              hipMalloc(&b->partial_bad, sizeof(int) * cfl_items.size()) == hipSuccess &&
+              hipMalloc(&b->cfl_acc, sizeof(unsigned long long) * (CFL_ACC_SLOTS + 1) * nbox) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         mhd_fail(MHD_ENOMEM, "device allocation of 2 x %zu bytes failed", bytes);
@@ -255,7 +261,9 @@ extern "C" mhd_batch* mhd_batch_create(int nbox, const int* dims, double gamma, 
                    hipMemcpyHostToDevice) == hipSuccess &&
          hipMemset(b->buf[0], 0, bytes) == hipSuccess && hipMemset(b->buf[1], 0, bytes) == hipSuccess &&
          hipMemset(b->scal, 0, sizeof(double) * SCAL_COUNT * nbox) == hipSuccess &&
-         hipMemset(b->flag, 0, sizeof(int) * FLAG_COUNT * nbox) == hipSuccess;
+         hipMemset(b->flag, 0, sizeof(int) * FLAG_COUNT * nbox) == hipSuccess &&
+         hipMemset(b->cfl_acc, 0, sizeof(unsigned long long) * (CFL_ACC_SLOTS + 1) * nbox) == hipSuccess;
+    b->acc_valid = false;
     if (!ok || build_lists(b) != MHD_OK) {
         mhd_fail(MHD_EDEVICE, "batch initialisation failed");
         mhd_batch_destroy(b);
@@ -297,6 +305,7 @@ extern "C" int mhd_batch_set_state(mhd_batch* b, int box, const double* host, si
     const BoxDesc& bd = b->boxes[box];
     if (n != 8 * (size_t)bd.ncell) return mhd_fail(MHD_EINVAL, "state size %zu != 8 * cells of box", n);
     HIP_TRY(b, hipSetDevice(b->device));
+    b->acc_valid = false;         // the fused CFL maxima describe the old state
     const size_t N = bd.ncell;
     if (b->prec == MHD_F64) {
         HIP_TRY(b, hipMemcpyAsync(box_field<double>(b, box, 0, 0), host, 8 * N * sizeof(double),
@@ -367,9 +376,17 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
 {
     const T* base[8];
     for (int q = 0; q < 8; ++q) base[q] = reinterpret_cast<const T*>(b->buf[b->cur[q]]);
-    HIP_TRY(b, launch_batch_cfl<T>(base, b->d_boxes, b->d_cfl_items, b->n_cfl_items,
-                                   b->d_item_first, b->nbox, b->gamma, cfl, b->partial,
-                                   b->partial_bad, b->scal, b->flag, b->stream));
+    if (b->acc_valid) {
+        // the previous step's last launch found every box's maximum already
+        HIP_TRY(b, launch_batch_cfl_from_acc(b->cfl_acc, b->d_boxes, b->nbox, cfl, b->scal, b->flag,
+                                             b->stream));
+    } else {
+        HIP_TRY(b, launch_batch_cfl<T>(base, b->d_boxes, b->d_cfl_items, b->n_cfl_items,
+                                       b->d_item_first, b->nbox, b->gamma, cfl, b->partial,
+                                       b->partial_bad, b->scal, b->flag, b->stream));
+        HIP_TRY(b, launch_batch_clear_acc(b->cfl_acc, b->nbox, b->stream));
+    }
+    b->acc_valid = false;
     // (op, d): op 0 fluid, 1 magnetic, 2 the reverse-half pair in one launch
     static const int separate[12][2] = { { 0, 0 }, { 1, 0 }, { 0, 1 }, { 1, 1 }, { 0, 2 }, { 1, 2 },
                                          { 1, 2 }, { 0, 2 }, { 1, 1 }, { 0, 1 }, { 1, 0 }, { 0, 0 } };
@@ -395,6 +412,9 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
         P.flag = b->flag;
         P.offsets32 = !b->wide;
         P.limiter = b->limiter;
+        // the last launch (F_x or the x pair) also finds the next step's CFL
+        P.cfl_acc = k == nops - 1 ? b->cfl_acc : nullptr;
+        P.gamma64 = b->gamma;
         for (const BoxDesc& bd : b->boxes)
             if ((unsigned long long)bd.ncell * (b->prec == MHD_F64 ? 8 : 4) > (1ull << 32)) P.offsets32 = false;
         const int grid = std::max(8, std::min(b->grid[d], (P.nitems + 7) / 8 * 8));
@@ -405,6 +425,7 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
             for (int q = 5; q < 8; ++q) b->cur[q] = 1 - b->cur[q];
     }
     HIP_TRY(b, launch_batch_advance(b->scal, b->flag, b->nbox, b->stream));
+    b->acc_valid = true;
     return MHD_OK;
 }
 
@@ -434,6 +455,13 @@ extern "C" int mhd_batch_run(mhd_batch* b, double cfl, int nsteps, int use_graph
             if ((r = enqueue_step(b, cfl))) return r;
         return MHD_OK;
     }
+    // the captured step takes its CFL from the maxima the previous step left:
+    // a step without them (after a new state) runs eagerly first
+    if (!b->acc_valid && nsteps > 0) {
+        if ((r = enqueue_step(b, cfl))) return r;
+        --nsteps;
+    }
+    if (nsteps == 0) return MHD_OK;
     if (!b->graph_valid || b->graph_cfl != cfl) {
         drop_graph(b);
         HIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));

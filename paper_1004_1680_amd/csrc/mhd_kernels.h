@@ -69,6 +69,11 @@ struct BatchParams {
     const int* flag;              // per box: FLAG_COUNT ints (null: never skip)
     bool offsets32;               // every box's fields have 32-bit byte offsets
     int limiter;                  // slope limiter (LIM_*; 0: van Leer)
+    // fused CFL of the x operator that ends a step (null: off): box b's FP64
+    // maximum signal speed accumulates in cfl_acc[b * (CFL_ACC_SLOTS + 1) ..],
+    // as for a single grid
+    unsigned long long* cfl_acc;
+    double gamma64;
 };
 
 // op 0 fluid, 1 magnetic, 2 magnetic then fluid in one pass (the reverse-half
@@ -86,6 +91,12 @@ struct BatchCflArgs {
 // per-box CFL: items (box, block of CFL_CELLS cells); item_first[b] ..
 // item_first[b+1]-1 are box b's items
 constexpr int CFL_CELLS = 2048;
+// per box, dt / relaxation speed / non-physical flag from the maxima the
+// fused CFL accumulated (the rules of batch_cfl_final), then clears them
+hipError_t launch_batch_cfl_from_acc(unsigned long long* acc, const BoxDesc* boxes, int nbox, double cfl,
+                                     double* scal, int* flag, hipStream_t s);
+hipError_t launch_batch_clear_acc(unsigned long long* acc, int nbox, hipStream_t s);
+
 template <typename T>
 hipError_t launch_batch_cfl(const T* const base[8], const BoxDesc* boxes, const int2* items,
                             int nitems, const int* item_first, int nbox, double gamma,

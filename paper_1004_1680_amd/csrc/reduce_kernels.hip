@@ -294,6 +294,58 @@ template hipError_t launch_batch_cfl<double>(const double* const[8], const BoxDe
                                              int, const int*, int, double, double, double*, int*,
                                              double*, int*, hipStream_t);
 
+// box b (one block of CFL_ACC_SLOTS threads per box): the rules of
+// batch_cfl_final_kernel on the maxima the fused CFL accumulated; clears them
+__global__ void __launch_bounds__(CFL_ACC_SLOTS) batch_cfl_from_acc_kernel(unsigned long long* acc,
+                                                                           const BoxDesc* boxes, double cfl,
+                                                                           double* scal, int* flag)
+{
+    const int b = blockIdx.x;
+    unsigned long long* a = acc + (size_t)b * (CFL_ACC_SLOTS + 1);
+    double m = __longlong_as_double((long long)a[threadIdx.x]);
+    m = wave_max(m);
+    __shared__ double smax[CFL_ACC_SLOTS / 64];
+    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double vmax = smax[0];
+        for (int q = 1; q < CFL_ACC_SLOTS / 64; ++q) vmax = fmax(vmax, smax[q]);
+        const int bb = (int)a[CFL_ACC_SLOTS];
+        double* sc = scal + (size_t)b * SCAL_COUNT;
+        if (bb || !(vmax > 0.0)) {
+            sc[SCAL_DT] = 0.0;
+            sc[SCAL_VMAX] = 0.0;
+            flag[(size_t)b * FLAG_COUNT + FLAG_NONPHYS] = bb ? 1 : 2;
+        } else {
+            sc[SCAL_DT] = cfl * (1.0 / (double)boxes[b].n[0]) / vmax;
+            sc[SCAL_VMAX] = vmax;
+            sc[SCAL_C] = vmax;
+        }
+        a[CFL_ACC_SLOTS] = 0;
+    }
+    a[threadIdx.x] = 0;
+}
+
+hipError_t launch_batch_cfl_from_acc(unsigned long long* acc, const BoxDesc* boxes, int nbox, double cfl,
+                                     double* scal, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_cfl_from_acc_kernel, dim3(nbox), dim3(CFL_ACC_SLOTS), 0, s, acc, boxes, cfl, scal, flag);
+    return hipGetLastError();
+}
+
+__global__ void batch_clear_acc_kernel(unsigned long long* acc)
+{
+    unsigned long long* a = acc + (size_t)blockIdx.x * (CFL_ACC_SLOTS + 1);
+    a[threadIdx.x] = 0;
+    if (threadIdx.x == 0) a[CFL_ACC_SLOTS] = 0;
+}
+
+hipError_t launch_batch_clear_acc(unsigned long long* acc, int nbox, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_clear_acc_kernel, dim3(nbox), dim3(CFL_ACC_SLOTS), 0, s, acc);
+    return hipGetLastError();
+}
+
 // per-box time advance (skipped for a box with a non-physical record)
 __global__ void batch_advance_kernel(double* scal, int* flag, int nbox)
 {

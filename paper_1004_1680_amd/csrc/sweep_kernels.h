@@ -1348,8 +1348,8 @@ __device__ __forceinline__ SweepParams<T> box_params(const BatchParams<T>& B, in
     P.gamma = B.gamma;
     P.scal = B.scal + (size_t)box * SCAL_COUNT;
     P.flag = B.flag ? B.flag + (size_t)box * FLAG_COUNT : nullptr;
-    P.cfl_acc = nullptr;
-    P.gamma64 = 0.0;
+    P.cfl_acc = B.cfl_acc ? B.cfl_acc + (size_t)box * (CFL_ACC_SLOTS + 1) : nullptr;
+    P.gamma64 = B.gamma64;
     P.limiter = 0;
     return P;
 }
@@ -1362,7 +1362,9 @@ constexpr int batch_waves(int d)
 }
 
 // W32: every box's fields have 32-bit byte offsets (see Addr)
-template <typename T, int OP, int D, bool W32, int LIM = LIM_VANLEER>
+// CFL (x fluid operator or x pair only): also accumulate each box's CFL
+// maximum of the result (B.cfl_acc)
+template <typename T, int OP, int D, bool W32, int LIM = LIM_VANLEER, bool CFL = false>
 __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kernel(BatchParams<T> B)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1377,11 +1379,11 @@ __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kern
         const SweepParams<T> P = box_params(B, it.x, bd);
         if constexpr (D == 0) {
             if constexpr (OP == 0)
-                fluid_x_tile<T, false, LIM>(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
+                fluid_x_tile<T, CFL, LIM>(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
             else if constexpr (OP == 1)
                 mag_x_tile<T, LIM>(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
             else
-                magfluid_x_tile<T, false, LIM>(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
+                magfluid_x_tile<T, CFL, LIM>(P, it.y, bd.tpr, bd.rpw, reinterpret_cast<T*>(smem_raw));
         } else {
             const long gid = (long)it.y * blockDim.x + threadIdx.x;
             if constexpr (OP == 0)
@@ -1397,9 +1399,17 @@ __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kern
 template <typename T, int OP, int LIM>
 static void launch_batch_op_dir(const BatchParams<T>& B, int d, int grid, size_t lds, hipStream_t s)
 {
-    // x tiles have no march addressing: one instantiation
-    if (d == 0) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 0, true, LIM>), dim3(grid), dim3(256), lds, s, B);
-    else if (B.offsets32) {
+    // x tiles have no march addressing: one instantiation (two for the
+    // operators that can end a step: with and without the fused CFL)
+    if (d == 0) {
+        if constexpr (OP != 1) {
+            if (B.cfl_acc) {
+                hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 0, true, LIM, true>), dim3(grid), dim3(256), lds, s, B);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 0, true, LIM>), dim3(grid), dim3(256), lds, s, B);
+    } else if (B.offsets32) {
         if (d == 1) hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 1, true, LIM>), dim3(grid), dim3(256), lds, s, B);
         else hipLaunchKernelGGL((batch_sweep_kernel<T, OP, 2, true, LIM>), dim3(grid), dim3(256), lds, s, B);
     } else {
@@ -1419,6 +1429,7 @@ static void launch_batch_op_lim(const BatchParams<T>& B, int op, int d, int grid
 template <typename T>
 hipError_t launch_batch_op(const BatchParams<T>& B, int op, int d, int grid, hipStream_t s)
 {
+    if (B.cfl_acc && (d != 0 || op == 1)) return hipErrorInvalidValue;   // only x fluid / x pair
     const size_t lds = d == 0 ? sizeof(T) * (op == 1 ? 16 : 25) * 256 : 0;
     switch (B.limiter) {
     case LIM_VANLEER: launch_batch_op_lim<T, LIM_VANLEER>(B, op, d, grid, lds, s); break;
