@@ -137,3 +137,17 @@ def loss_and_grad(x, ps, scale, target, tscale, n, g=None):
     g1 = conv3d_dgrad(g2, w2, n) * (a1 > 0)
     dw1, db1 = conv3d_wgrad(x0, g1, n, 8, 32)
     return L, [dw1, db1, dw2, db2, dw3, db3]
+
+
+def adam_step(p, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, Algorithm 1) of parameters p with
+    gradient g at step t >= 1, from the first- and second-moment estimates
+    m, v of the previous step (zeros before the first).  Returns (p, m, v):
+        m <- beta1 m + (1 - beta1) g,     v <- beta2 v + (1 - beta2) g^2,
+        p <- p - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps)."""
+    p, g, m, v = (np.asarray(a, dtype=np.float64) for a in (p, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m, v

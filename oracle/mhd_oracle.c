@@ -26,7 +26,9 @@
  *   - the relaxation (freezing) speed c of the fluid sweeps is one number
  *     per full step: the largest signal speed max_d |v_d| + c_fast found by
  *     the CFL function at the start of the step (a constant relaxation speed
- *     as in Jin & Xin; no square root is taken inside the sweeps);
+ *     as in Jin & Xin; no square root is taken inside the sweeps); per-cell
+ *     and per-pencil speeds are selectable method variants
+ *     (oracle_set_freeze);
  *   - two-stage step: first-order upwind half step, then a van-Leer-limited
  *     full step from the old state with fluxes of the half-step state;
  *   - every operator of a full step uses the same dt; a step advances 2 dt;
@@ -116,6 +118,26 @@ int oracle_set_limiter(int kind)
     return 0;
 }
 
+/* Relaxation (freezing) speed of the fluid sweeps.  The reading taken for
+ * the paper's method is one number per step, the CFL speed passed in as c
+ * (FREEZE_GRID).  The paper does not fix this choice (section II.B only
+ * asks the speed to exceed the flux's characteristic speeds); two method
+ * variants take it from the state of each stage instead:
+ *   FREEZE_CELL:   c_i = |v_n| + c_fast of cell i (local Lax-Friedrichs-like);
+ *   FREEZE_PENCIL: c = the largest |v_n| + c_fast along the pencil,
+ * with c_fast = sqrt((gamma p + |Bbar|^2)/rho), stage 1 from the old state
+ * and stage 2 from the half-step state.  Process-wide, FREEZE_GRID by
+ * default (oracle_set_freeze). */
+enum { FREEZE_GRID = 0, FREEZE_CELL = 1, FREEZE_PENCIL = 2 };
+static int g_freeze = FREEZE_GRID;
+
+int oracle_set_freeze(int mode)
+{
+    if (mode < FREEZE_GRID || mode > FREEZE_PENCIL) return -1;
+    g_freeze = mode;
+    return 0;
+}
+
 /* phi(a, b) with limiter `kind` (for tests of the formulas themselves) */
 double oracle_limiter_value(int kind, double a, double b)
 {
@@ -153,6 +175,39 @@ static void fluid_flux(const double u[5], const double bb[3], double gamma,
     f[4] = (e + ptot) * vn - bb[0] * bv;             /* eq. (3) */
 }
 
+/* |v_n| + c_fast of one cell (the variants' freezing speed), with the same
+ * pressure as fluid_flux: c_fast = sqrt((gamma p + |Bbar|^2)/rho). */
+static double normal_speed(const double u[5], const double bb[3], double gamma)
+{
+    double rho = u[0], mn = u[1], mt1 = u[2], mt2 = u[3], e = u[4];
+    double vn = mn / rho;
+    double b2 = bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
+    double mm = mn * mn + mt1 * mt1 + mt2 * mt2;
+    double p = (gamma - 1.0) * (e - 0.5 * mm / rho - 0.5 * b2);
+    return fabs(vn) + sqrt((gamma * p + b2) / rho);
+}
+
+/* freezing speed of every cell of a pencil for one stage (state w) */
+static void stage_speeds(int n, const double *w, const double *bb, double gamma,
+                         double c, double *cc)
+{
+    int i, q;
+    double cmax = 0.0;
+    for (i = 0; i < n; i++) {
+        double uc[5], b[3];
+        if (g_freeze == FREEZE_GRID) {
+            cc[i] = c;
+            continue;
+        }
+        for (q = 0; q < 5; q++) uc[q] = w[q * n + i];
+        for (q = 0; q < 3; q++) b[q] = bb[q * n + i];
+        cc[i] = normal_speed(uc, b, gamma);
+        if (cc[i] > cmax) cmax = cc[i];
+    }
+    if (g_freeze == FREEZE_PENCIL)
+        for (i = 0; i < n; i++) cc[i] = cmax;
+}
+
 /* ------------------------------------------------------------------------- */
 /* One-dimensional relaxing-TVD update of one pencil (section II.B, eq. (6)) */
 /* ------------------------------------------------------------------------- */
@@ -167,20 +222,22 @@ static void fluid_pencil(int n, double *u, const double *bb, double gamma,
     double *fl = malloc(sizeof(double) * 5 * n);
     double *fi = malloc(sizeof(double) * 5 * n);   /* interface fluxes i+1/2 */
     double *uh = malloc(sizeof(double) * 5 * n);
+    double *cc = malloc(sizeof(double) * n);       /* freezing speed per cell */
     double halftau = 0.5 * tau;
     int i, q;
 
     /* stage 1: split each cell's flux into right- and left-moving parts,
      * F^R = (cU + F)/2, F^L = (cU - F)/2, and take first-order upwind
      * interface fluxes F_{i+1/2} = F^R_i - F^L_{i+1}. */
+    stage_speeds(n, u, bb, gamma, c, cc);
     for (i = 0; i < n; i++) {
         double uc[5], b[3], f[5];
         for (q = 0; q < 5; q++) uc[q] = u[q * n + i];
         for (q = 0; q < 3; q++) b[q] = bb[q * n + i];
         fluid_flux(uc, b, gamma, f);
         for (q = 0; q < 5; q++) {
-            fr[q * n + i] = 0.5 * (c * uc[q] + f[q]);
-            fl[q * n + i] = 0.5 * (c * uc[q] - f[q]);
+            fr[q * n + i] = 0.5 * (cc[i] * uc[q] + f[q]);
+            fl[q * n + i] = 0.5 * (cc[i] * uc[q] - f[q]);
         }
     }
     for (i = 0; i < n; i++)
@@ -194,14 +251,15 @@ static void fluid_pencil(int n, double *u, const double *bb, double gamma,
 
     /* stage 2: fluxes of the half-step state, second-order TVD correction
      * with the van Leer limiter on each moving part */
+    stage_speeds(n, uh, bb, gamma, c, cc);
     for (i = 0; i < n; i++) {
         double uc[5], b[3], f[5];
         for (q = 0; q < 5; q++) uc[q] = uh[q * n + i];
         for (q = 0; q < 3; q++) b[q] = bb[q * n + i];
         fluid_flux(uc, b, gamma, f);
         for (q = 0; q < 5; q++) {
-            fr[q * n + i] = 0.5 * (c * uc[q] + f[q]);
-            fl[q * n + i] = 0.5 * (c * uc[q] - f[q]);
+            fr[q * n + i] = 0.5 * (cc[i] * uc[q] + f[q]);
+            fl[q * n + i] = 0.5 * (cc[i] * uc[q] - f[q]);
         }
     }
     for (i = 0; i < n; i++) {
@@ -221,7 +279,7 @@ static void fluid_pencil(int n, double *u, const double *bb, double gamma,
             u[q * n + i] = u[q * n + i] -
                            tau * (fi[q * n + i] - fi[q * n + wrap(i - 1, n)]);
 
-    free(fr); free(fl); free(fi); free(uh);
+    free(fr); free(fl); free(fi); free(uh); free(cc);
 }
 
 int oracle_fluid_sweep(int nx, int ny, int nz, double gamma,

@@ -38,6 +38,10 @@ void oracle_diag(int nx, int ny, int nz, const double *s, double out[9]);
  * 3 superbee; -1 for another value */
 int oracle_set_limiter(int kind);
 double oracle_limiter_value(int kind, double a, double b);
+/* process-wide freezing speed of the fluid sweeps: 0 the c argument (one
+ * number per step, default), 1 |v_n| + c_fast per cell, 2 its largest value
+ * along the pencil; both variants per stage; -1 for another value */
+int oracle_set_freeze(int mode);
 int oracle_restrict(int nx, int ny, int nz, int r, const double *fine,
                     double *coarse);
 

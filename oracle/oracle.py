@@ -19,7 +19,8 @@ _lib = None
 
 __all__ = ["build", "load", "fluid_sweep", "mag_sweep", "sweep", "step",
            "cfl", "cfl_dt", "diag", "restrict", "run", "NonPhysical",
-           "limiter_value", "VANLEER", "MINMOD", "MC", "SUPERBEE"]
+           "limiter_value", "VANLEER", "MINMOD", "MC", "SUPERBEE",
+           "FREEZE_GRID", "FREEZE_CELL", "FREEZE_PENCIL"]
 
 
 class NonPhysical(RuntimeError):
@@ -63,10 +64,12 @@ def load():
                "oracle_closure_project", "oracle_closure_project_T", "oracle_closure_gate"):
         getattr(lib, fn).restype = None
     lib.oracle_set_limiter.argtypes = [i]
+    lib.oracle_set_freeze.argtypes = [i]
     lib.oracle_limiter_value.argtypes = [i, d, d]
     lib.oracle_limiter_value.restype = d
     for fn in ("oracle_fluid_sweep", "oracle_mag_sweep", "oracle_sweep",
-               "oracle_step", "oracle_cfl", "oracle_restrict", "oracle_set_limiter"):
+               "oracle_step", "oracle_cfl", "oracle_restrict", "oracle_set_limiter",
+               "oracle_set_freeze"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -90,18 +93,30 @@ def _dims(s):
 VANLEER, MINMOD, MC, SUPERBEE = 0, 1, 2, 3
 
 
-class _Limiter:
-    """the oracle's process-wide limiter for the duration of one call"""
+# freezing (relaxation) speed of the fluid sweeps: 0 one number per step
+# (the c argument; the reading taken for the paper's method), 1 |v_n| +
+# c_fast per cell, 2 its largest value along the pencil (method variants)
+FREEZE_GRID, FREEZE_CELL, FREEZE_PENCIL = 0, 1, 2
 
-    def __init__(self, kind):
+
+class _Limiter:
+    """the oracle's process-wide limiter and freezing-speed mode for the
+    duration of one call"""
+
+    def __init__(self, kind, freeze=FREEZE_GRID):
         self.kind = kind
+        self.freeze = freeze
 
     def __enter__(self):
         if load().oracle_set_limiter(self.kind) != 0:
             raise ValueError(f"unknown limiter {self.kind}")
+        if load().oracle_set_freeze(self.freeze) != 0:
+            load().oracle_set_limiter(VANLEER)
+            raise ValueError(f"unknown freezing-speed mode {self.freeze}")
 
     def __exit__(self, *exc):
         load().oracle_set_limiter(VANLEER)
+        load().oracle_set_freeze(FREEZE_GRID)
 
 
 def limiter_value(kind, a, b):
@@ -109,12 +124,13 @@ def limiter_value(kind, a, b):
     return load().oracle_limiter_value(kind, a, b)
 
 
-def fluid_sweep(s, d, dt, c, gamma=5.0 / 3.0, limiter=VANLEER):
-    """Fluid operator along axis d with relaxation speed c."""
+def fluid_sweep(s, d, dt, c, gamma=5.0 / 3.0, limiter=VANLEER, freeze=FREEZE_GRID):
+    """Fluid operator along axis d with relaxation speed c (freeze: see
+    FREEZE_*; c is unused by the per-cell and per-pencil variants)."""
     s = _check(s)
     out = np.empty_like(s)
     nx, ny, nz = _dims(s)
-    with _Limiter(limiter):
+    with _Limiter(limiter, freeze):
         r = load().oracle_fluid_sweep(nx, ny, nz, gamma, _ptr(s), _ptr(out), d, dt, c)
     assert r == 0
     return out
@@ -131,21 +147,21 @@ def mag_sweep(s, d, dt, gamma=5.0 / 3.0, limiter=VANLEER):
     return out
 
 
-def sweep(s, code, dt, c, gamma=5.0 / 3.0, limiter=VANLEER):
+def sweep(s, code, dt, c, gamma=5.0 / 3.0, limiter=VANLEER, freeze=FREEZE_GRID):
     """code 0..2: fluid then magnetic along code; 3..5: the reverse along
     code-3."""
     s = _check(s).copy()
     nx, ny, nz = _dims(s)
-    with _Limiter(limiter):
+    with _Limiter(limiter, freeze):
         assert load().oracle_sweep(nx, ny, nz, gamma, _ptr(s), code, dt, c) == 0
     return s
 
 
-def step(s, dt, c, gamma=5.0 / 3.0, limiter=VANLEER):
+def step(s, dt, c, gamma=5.0 / 3.0, limiter=VANLEER, freeze=FREEZE_GRID):
     """Full Strang step (x, y, z, z, y, x) of 2 dt with relaxation speed c."""
     s = _check(s).copy()
     nx, ny, nz = _dims(s)
-    with _Limiter(limiter):
+    with _Limiter(limiter, freeze):
         assert load().oracle_step(nx, ny, nz, gamma, _ptr(s), dt, c) == 0
     return s
 
@@ -184,7 +200,8 @@ def restrict(s, r):
     return out
 
 
-def run(s, nsteps, cfl_number=0.7, gamma=5.0 / 3.0, t_end=None, limiter=VANLEER):
+def run(s, nsteps, cfl_number=0.7, gamma=5.0 / 3.0, t_end=None, limiter=VANLEER,
+        freeze=FREEZE_GRID):
     """Advance nsteps full steps with dt from the CFL condition before each
     step.  If t_end is given, stop there, shortening the last step so that
     the run ends exactly at t_end.  Returns (state, time, list of dt)."""
@@ -197,7 +214,7 @@ def run(s, nsteps, cfl_number=0.7, gamma=5.0 / 3.0, t_end=None, limiter=VANLEER)
         dt, vmax = cfl(s, cfl_number, gamma)
         if t_end is not None:
             dt = min(dt, 0.5 * (t_end - t))
-        s = step(s, dt, vmax, gamma, limiter)
+        s = step(s, dt, vmax, gamma, limiter, freeze)
         t += 2.0 * dt
         dts.append(dt)
     return s, t, dts

@@ -168,3 +168,54 @@ def test_gated_gradient_matches_finite_differences():
     d = C.forward(x, ps, sc, n, g=g)
     _, (_, _, _, o) = C.forward(x, ps, sc, n, keep=True)
     assert np.allclose(d, C.project(o * g[:, None], sc, n), rtol=1e-13, atol=1e-15)
+
+
+# --- Adam (the optimizer of the training step) -------------------------------
+
+def test_adam_first_step_closed_form():
+    """at t = 1 the bias corrections give m_hat = g and v_hat = g^2, so every
+    parameter moves by -lr g / (|g| + eps), whatever the betas"""
+    rng = np.random.default_rng(11)
+    p = rng.normal(size=1000)
+    g = rng.normal(size=1000) * 10.0 ** rng.uniform(-9, 2, 1000)
+    z = np.zeros(1000)
+    for b1, b2 in ((0.9, 0.999), (0.5, 0.9)):
+        q, m, v = C.adam_step(p, g, z, z, 1, 1e-3, b1, b2)
+        assert np.allclose(q, p - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+        assert np.allclose(m, (1 - b1) * g, rtol=1e-15, atol=0)
+        assert np.allclose(v, (1 - b2) * g * g, rtol=1e-15, atol=0)
+
+
+def test_adam_constant_and_alternating_gradients():
+    """a constant gradient keeps m_hat = g and v_hat = g^2 at every step (the
+    bias corrections exactly undo the zero start); after g, a gradient -g
+    gives at t = 2 m = beta1 (1-beta1) g - (1-beta1) g = -(1-beta1)^2 g,
+    m_hat = -(1-beta1)^2 g / (1 - beta1^2) = -g (1-beta1)/(1+beta1) = -g/19
+    and v_hat = g^2, so the second move is +lr g / (19 (|g| + eps))"""
+    rng = np.random.default_rng(12)
+    p0 = rng.normal(size=200)
+    g = rng.normal(size=200)
+    lr = 2e-3
+    p, m, v = p0, np.zeros(200), np.zeros(200)
+    for t in range(1, 6):
+        p, m, v = C.adam_step(p, g, m, v, t, lr)
+        assert np.allclose(p, p0 - t * lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-14), t
+    p, m, v = C.adam_step(p0, g, np.zeros(200), np.zeros(200), 1, lr)
+    q, m, v = C.adam_step(p, -g, m, v, 2, lr)
+    assert np.allclose(q - p, lr * g / (19.0 * (np.abs(g) + 1e-8)), rtol=0, atol=1e-15)
+
+
+def test_adam_zero_gradient_and_scale_invariance():
+    """zero gradient: no move; without eps the move does not depend on the
+    gradient's scale (Adam divides by the root mean square)"""
+    rng = np.random.default_rng(13)
+    p = rng.normal(size=100)
+    z = np.zeros(100)
+    q, _, _ = C.adam_step(p, z, z, z, 1, 1e-3)
+    assert np.array_equal(q, p)
+    g1, g2 = rng.normal(size=100), rng.normal(size=100)
+    a, m, v = C.adam_step(p, g1, z, z, 1, 1e-3, eps=0.0)
+    a, _, _ = C.adam_step(a, g2, m, v, 2, 1e-3, eps=0.0)
+    b, m, v = C.adam_step(p, 37.0 * g1, z, z, 1, 1e-3, eps=0.0)
+    b, _, _ = C.adam_step(b, 37.0 * g2, m, v, 2, 1e-3, eps=0.0)
+    assert np.allclose(a, b, rtol=0, atol=1e-15)

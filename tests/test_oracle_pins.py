@@ -243,10 +243,10 @@ def test_exact_riemann_solver_matches_textbook():
     assert round(w[0, 1], 5) == g["rho_star_right"]
 
 
-def sod_error(orc, N, t_end=0.1, limiter=0):
+def sod_error(orc, N, t_end=0.1, limiter=0, freeze=0):
     g = 1.4
     s0 = I.sod((N, 8, 8), gamma=g)
-    out, t, _ = orc.run(s0, 0, t_end=t_end, gamma=g, limiter=limiter)
+    out, t, _ = orc.run(s0, 0, t_end=t_end, gamma=g, limiter=limiter, freeze=freeze)
     x = (np.arange(N) + 0.5) / N
     # the interface at 3/4 is a standard left->right Sod tube
     sel = (x > 0.5) & (x < 1.0)
@@ -494,3 +494,91 @@ def test_limiter_variant_sod_converges_to_exact_solution(orc, name):
     if name == "minmod":
         ev, uv, _ = sod_error(orc, 256)
         assert e1 > ev and u1 > uv
+
+
+# ---------------------------------------------------------------------------
+# freezing-speed variants of the fluid operator: per-cell |v_n| + c_fast and
+# its per-pencil maximum, each taken from the state of each stage (the
+# method's reading is one speed per step, the CFL speed)
+# ---------------------------------------------------------------------------
+
+FREEZES = {"cell": 1, "pencil": 2}
+
+
+@pytest.mark.parametrize("name", ["cell", "pencil"])
+def test_freeze_variant_invariants(orc, name):
+    fr = FREEZES[name]
+    u = I.uniform((16, 12, 8), rho=1.3, v=(0.3, -0.7, 0.2), p=0.9, b=(0.4, -1.1, 0.6))
+    dt, vmax = orc.cfl(u)
+    assert np.array_equal(orc.step(u, dt, vmax, freeze=fr), u)
+    s = I.random_smooth((16, 12, 8), seed=3)
+    out, _, _ = orc.run(s, 4, freeze=fr)
+    before, after = orc.diag(s), orc.diag(out)
+    scale = np.array([np.abs(s[f]).sum() for f in range(8)]) / (16 ** 3)
+    assert np.all(np.abs(after[:8] - before[:8]) / scale < 1e-13)
+    assert after[8] < 1e-13
+    ref, _, _ = orc.run(s, 4)
+    assert l1(out[1], ref[1]) > 1e-7          # the variant really acts
+    # no preferred axis (the speed is |v_n| of the sweep axis)
+    r = rotate(s)
+    for d in range(3):
+        a = rotate(orc.fluid_sweep(s, d, 0.25 / s.shape[3], 0.0, freeze=fr))
+        b = orc.fluid_sweep(r, (d + 1) % 3, 0.25 / r.shape[3], 0.0, freeze=fr)
+        assert np.array_equal(a, b), (name, d)
+
+
+def test_freeze_pencil_speed_is_the_pencil_maximum(orc):
+    """a state that varies along x only: every x pencil is the same, so the
+    per-pencil speed of stage 1 is one number, the largest |v_x| + c_fast;
+    with the grid mode given that number the first stage is identical, and
+    a fluid sweep with a speed too small for some cell (the pencil's
+    smallest) differs"""
+    N = 32
+    s = I.linear_wave((N, 8, 8), "fast", 1e-2, (1.0, 0.5, 0.2))
+    g = 5.0 / 3.0
+    rho, m, e = s[0], s[1:4], s[4]
+    b = [0.5 * (s[5] + np.roll(s[5], -1, 2)), s[6], s[7]]    # uniform b_y, b_z
+    b2 = b[0] ** 2 + b[1] ** 2 + b[2] ** 2
+    p = (g - 1) * (e - 0.5 * (m ** 2).sum(0) / rho - 0.5 * b2)
+    sp = np.abs(m[0] / rho) + np.sqrt((g * p + b2) / rho)
+    cmax, cmin = sp.max(), sp.min()
+    dt = 0.2 / N / cmax
+    pen = orc.fluid_sweep(s, 0, dt, 0.0, freeze=2)
+    grid = orc.fluid_sweep(s, 0, dt, cmax)
+    low = orc.fluid_sweep(s, 0, dt, cmin)
+    # stage 2 takes the maximum of the half-step state, a shade different
+    assert 0 < np.abs(pen - grid).max() < 1e-3 * np.abs(pen - s).max()
+    assert np.abs(low - grid).max() > 10 * np.abs(pen - grid).max()
+
+
+def test_freeze_variant_orders_on_linear_waves(orc):
+    """Order of accuracy over one crossing (32, 64, 128 cells): a speed that
+    is one number per pencil or per step keeps the scheme second order on a
+    fast wave; the per-cell speed |v_n| + c_fast has a kink where v_n changes
+    sign, which costs half an order (measured 1.47-1.53, errors about twice
+    the others); on an Alfven wave v_n = 0 and the three agree"""
+    def errs(mode, B, fr):
+        lam, _ = I.wave_mode(mode, 1.0, 1.0, B)
+        out = []
+        for N in (32, 64, 128):
+            s0 = I.linear_wave((N, 8, 8), mode, 1e-6, B)
+            o, _, _ = orc.run(s0, 0, t_end=1.0 / abs(lam), freeze=fr)
+            out.append(sum(l1(o[f], s0[f]) for f in range(8)) / 1e-6)
+        return np.array(out), np.log2(np.array(out[:-1]) / np.array(out[1:]))
+    B = (1.0, 0.8, 0.3)
+    eg, og = errs("fast", B, 0)
+    ep, op = errs("fast", B, 2)
+    ec, oc = errs("fast", B, 1)
+    assert og[-1] > 1.95 and op[-1] > 1.95, (og, op)
+    assert 1.3 < oc[-1] < 1.7 and 1.3 < oc[0] < 1.7, oc
+    assert ec[-1] > 2.5 * eg[-1]
+    ea, oa = errs("alfven", B, 1)
+    assert oa[-1] > 1.95, oa
+
+
+@pytest.mark.parametrize("name", ["cell", "pencil"])
+def test_freeze_variant_sod_converges_to_exact_solution(orc, name):
+    e1, u1, _ = sod_error(orc, 256, freeze=FREEZES[name])
+    e2, u2, _ = sod_error(orc, 512, freeze=FREEZES[name])
+    assert e1 < 0.012 and u1 < 0.02, (e1, u1)
+    assert e2 < 0.65 * e1 and u2 < 0.65 * u1, (e1, e2, u1, u2)
