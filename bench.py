@@ -5,16 +5,25 @@ device and the 12 operators F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x
 (dt kept on the device, as mhd_step_auto enqueues it).  In FP32 each
 reverse-half pair (M_d F_d) runs as one fused kernel, so a step is 9
 launches, and the CFL maximum of the next step is found by the last one.  The default
-workload is the 256^3 FP32 run of seeded random-phase solenoidal turbulence
-(P(k) ~ k^-4, 1 <= k <= 8, rms Mach 1, beta 1, B0 along z).  The state is
-resident in HBM before the timed region starts.
+workload is the 512^3 FP32 run of the 3D Orszag-Tang-type state (the size at
+which the HBM-roofline target is stated); ot1024, turb256 (seeded
+random-phase solenoidal turbulence, P(k) ~ k^-4, 1 <= k <= 8, rms Mach 1,
+beta 1, B0 along z) and the others are selectable.  The state is resident in
+HBM before the timed region starts.
 
 Also reported:
  * roofline of the dominant kernel: algorithmic bytes per launch divided by
    its average duration, timed with HIP events on the solver's stream;
  * every operator kernel's average duration and bandwidth;
- * cpu_baseline: the FP64 CPU oracle on one full step of the same workload
-   on the host cores (a bounded sample), scaled to Mcell-updates/s.
+ * cpu_baseline: the FP64 CPU oracle on full steps of the same initial
+   state on the host cores (median of 3 one-step runs; states above 512^3
+   are sampled at 512^3), scaled to Mcell-updates/s, with the CPU model and
+   the threads used;
+ * power: GPU board power sampled over a separate window of at least 2 s
+   of the same steps (energy per step);
+ * copy_ceiling: a plain streaming copy kernel of the library
+   (mhd_stream_copy) on 2 GiB buffers, the practical HBM bandwidth that
+   the sweep kernels are compared with.
 
 The closure128 workload times the learned coarse step on a 128^3 grid (plain
 step + BF16 MFMA network + gate + projection + guard) and a training step,
@@ -23,8 +32,11 @@ also rolls out trained weights against the restricted 1024^3 solution and
 plain 128^3 / 256^3 / 512^3 runs (learned vs plain at equal L1).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload turb256|ot512|ot1024|turb256-f64|ensemble64|closure128]
+                       [--workload ot512|ot1024|turb256|turb256-f64|ensemble64|closure128]
                        [--no-cpu] [--closure-weights W.npz [--closure-eval]]
+       python bench.py --precision-report all|2|3
+           (FP32 and FP64 on the GPU against the FP64 oracle: 256^3 turbulence
+            over 100 steps; 1024^3 FP32 against FP64 over 50 steps)
        python bench.py --size-sweep default|16,32,... [--sweep-prec f32|f64]
            (ms per step against n^3 with the paper's four criteria: code and
             fractional speed-up against the one-thread oracle, FLOPS and
@@ -137,14 +149,85 @@ class PowerSampler:
             self._stop.set()
             self._thread.join()
 
-    def result(self, seconds, steps, cells):
+    def result(self, seconds, steps, cells, what="GPU board power (hwmon), mean over the timed region"):
         if not self.samples:
             return None
         w = sum(self.samples) / len(self.samples)
         return {"avg_W": round(w, 1), "J_per_step": round(w * seconds / steps, 4),
                 "Mcell_updates_per_J": round(cells * steps / (w * seconds) / 1e6, 2),
-                "samples": len(self.samples), "source": self.path,
-                "what": "GPU board power (hwmon), mean over the timed region"}
+                "samples": len(self.samples), "window_s": round(seconds, 3), "steps": steps,
+                "min_W": round(min(self.samples), 1), "max_W": round(max(self.samples), 1),
+                "period_s": self.period, "source": self.path,
+                "reading": os.path.basename(self.path) if self.path else None,
+                "what": what}
+
+
+def energy_window(S, cfl, cells, torch, seconds=2.0):
+    """board power over a window of at least `seconds` of device-dt steps of
+    the solver's current state (energy per step; the timed region of the
+    throughput figure is too short for a stable power reading)"""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.step_auto(cfl)
+    torch.cuda.synchronize()
+    per = max(time.perf_counter() - t0, 1e-4)
+    steps = max(10, int(seconds / per) + 1)
+    with PowerSampler(torch) as power:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            S.step_auto(cfl)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    S.status()
+    return power.result(el, steps, cells, what=f"GPU board power (hwmon), mean over {steps} steps "
+                                             "run for this reading after the timed region")
+
+
+def copy_ceiling(torch, mhd, stream, gib=2, reps=10):
+    """bandwidth of the library's plain streaming copy (mhd_stream_copy) and
+    of torch's device copy on gib-GiB buffers: read + write bytes / time"""
+    n = (gib << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for name, fn in (("mhd_stream_copy", lambda: mhd.stream_copy(src, dst, stream)),
+                     ("torch_copy", lambda: dst.copy_(src))):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "GBs": round(2 * 4 * n / (ms * 1e-3) / 1e9, 1)}
+    assert torch.equal(src, dst)
+    del src, dst
+    torch.cuda.empty_cache()
+    best = out["mhd_stream_copy"]["GBs"]
+    return {"kernel": "mhd_stream_copy", "bytes_moved": 2 * 4 * n, "GBs": best,
+            "frac": round(best / HBM_PEAK_GBS, 4), "torch_copy_GBs": out["torch_copy"]["GBs"],
+            "what": f"{gib} GiB read + {gib} GiB written per copy, mean of {reps}"}
+
+
+def cpu_info():
+    """host CPU model string and the OpenMP threads the oracle uses"""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or avail
+    return model, threads, avail
 
 
 def make_state_device(wl, torch):
@@ -251,25 +334,32 @@ def step_launches(S, n, esize, fused, w32, lim=0):
     return [fx, mx, fy, my, fz, mz, mz, fz, my, fy, mx, (f"fluid_x_kernel<{t}, true, {lim}>", xgrid)]
 
 
-def cpu_baseline(wl):
+def cpu_baseline(wl, reps=3):
+    """the oracle on the workload's initial state (states above 512^3, whose
+    FP64 copies would not fit host memory, at 512^3 of the same family):
+    `reps` full steps (CFL + 12 operators), each from that state, on all
+    host threads; the median time"""
     import oracle
     from paper_1004_1680_amd import inputs as I
-    n = wl["n"]
+    n = min(wl["n"], 512)
     ncell = n ** 3
-    if ncell > 256 ** 3:             # keep the sample bounded: 256^3 of the family
-        n = 256
-        ncell = n ** 3
     s = I.turbulence((n, n, n), seed=2) if wl["ic"] == "turbulence" else I.orszag_tang((n, n, n))
     oracle.load()
-    t0 = time.perf_counter()
-    dt, vmax = oracle.cfl(s)
-    oracle.step(s, dt, vmax)
-    el = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    out = {"value": round(ncell / el / 1e6, 4), "unit": "Mcell-updates/s", "cores": cores,
-           "kind": "oracle",
-           "sample": f"1 full step (CFL + 12 operators) of the same initial state at {n}^3, "
-                     f"FP64, OpenMP over pencils; {el:.2f} s wall"}
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        dt, vmax = oracle.cfl(s)
+        oracle.step(s, dt, vmax)
+        times.append(time.perf_counter() - t0)
+    el = float(np.median(times))
+    model, threads, avail = cpu_info()
+    same = "the same" if n == wl["n"] else f"a {n}^3 sample of the same family as the"
+    out = {"value": round(ncell / el / 1e6, 4), "unit": "Mcell-updates/s", "cores": threads,
+           "kind": "oracle", "cpu_model": model, "host_threads_available": avail,
+           "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+           "sample": f"median of {reps} full steps (CFL + 12 operators), each from {same} "
+                     f"initial state at {n}^3, FP64, OpenMP over pencils; wall "
+                     + ", ".join(f"{t:.2f}" for t in times) + " s"}
     out["single_thread"] = cpu_baseline_single_thread(wl)
     return out
 
@@ -491,6 +581,134 @@ def cpu_baseline_closure():
                       f"projection); {el:.2f} s wall"}
 
 
+FAMILIES = {"rho": [0], "m": [1, 2, 3], "e": [4], "b": [5, 6, 7]}
+
+
+def family_errors(a, ref):
+    """per field family: max |a - ref| / max |ref| and the relative L1
+    (mean |a - ref| / mean |ref| averaged over the family's fields)"""
+    out = {}
+    for k, idx in FAMILIES.items():
+        den = np.abs(ref[idx]).max()
+        l1 = [float(np.mean(np.abs(a[f] - ref[f])) / max(np.mean(np.abs(ref[f])), 1e-300)) for f in idx]
+        out[k] = {"max_rel": float(np.abs(a[idx] - ref[idx]).max() / den), "l1": float(np.mean(l1))}
+    return out
+
+
+def precision_config2(args, torch, mhd, checkpoints=(1, 10, 50, 100)):
+    """256^3 random-phase solenoidal turbulence (rms Mach 1, beta 1, B0 || z,
+    seed 2): FP32 GPU, FP64 GPU and the FP64 oracle over 100 steps (each
+    with its own CFL time steps, device dt on the GPU), errors at the
+    checkpoints"""
+    import oracle
+    from paper_1004_1680_amd import inputs as I
+    n = (256, 256, 256)
+    s = I.turbulence(n, seed=2)
+    gpu = {}
+    for prec in ("f64", "f32"):
+        S = mhd.Solver(n, prec=prec)
+        S.set_state(s)
+        k, states = 0, {}
+        t0 = time.perf_counter()
+        for c in checkpoints:
+            while k < c:
+                S.step_auto(args.cfl)
+                k += 1
+            S.status()
+            states[c] = (S.get_state(), S.time())
+        log(f"[precision] config 2 {prec}: {k} steps in {time.perf_counter() - t0:.1f} s")
+        S.close()
+        gpu[prec] = states
+    oracle.load()
+    o, t, k = s, 0.0, 0
+    rows = []
+    t0 = time.perf_counter()
+    for c in checkpoints:
+        while k < c:
+            dt, vmax = oracle.cfl(o, args.cfl)
+            o = oracle.step(o, dt, vmax)
+            t += 2.0 * dt
+            k += 1
+        log(f"[precision] config 2 oracle at step {k} ({time.perf_counter() - t0:.0f} s)")
+        g64, t64 = gpu["f64"][c]
+        g32, t32 = gpu["f32"][c]
+        rows.append({"step": c, "time_oracle": t, "time_f64": t64, "time_f32": t32,
+                     "f64_vs_oracle": family_errors(g64, o), "f32_vs_oracle": family_errors(g32, o),
+                     "f32_vs_f64": family_errors(g32, g64)})
+    return {"workload": "random-phase solenoidal turbulence 256^3, P(k)~k^-4 (1<=k<=8), rms Mach 1, "
+                        "beta 1, B0 || z, seed 2", "cfl": args.cfl, "checkpoints": rows}
+
+
+def precision_config3(args, torch, mhd, checkpoints=(1, 10, 25, 50)):
+    """1024^3 Orszag-Tang-type state, FP32 against FP64 on the GPU over 50
+    steps (the oracle would need 137 GB of host memory per state).  The FP64
+    state is read back as float32 through host memory (its rounding, 6e-8,
+    is far below the differences measured), the FP32 state on the device;
+    errors per field family at the checkpoints"""
+    from paper_1004_1680_amd import inputs as I
+    n = (1024, 1024, 1024)
+    S64 = mhd.Solver(n, prec="f64")
+    t = I.orszag_tang_torch(n, seed=0, dtype=torch.float64)
+    S64.set_state_tensor(t)
+    torch.cuda.synchronize()
+    del t
+    torch.cuda.empty_cache()
+    S32 = mhd.Solver(n, prec="f32")
+    t = I.orszag_tang_torch(n, seed=0, dtype=torch.float32)
+    S32.set_state_tensor(t)
+    torch.cuda.synchronize()
+    del t
+    torch.cuda.empty_cache()
+    rows, k = [], 0
+    el = {"f64": 0.0, "f32": 0.0}
+    for c in checkpoints:
+        for name, S in (("f64", S64), ("f32", S32)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(c - k):
+                S.step_auto(args.cfl)
+            S.status()
+            torch.cuda.synchronize()
+            el[name] += time.perf_counter() - t0
+        k = c
+        ref = S64.get_state_tensor(dtype=torch.float32).cpu()
+        torch.cuda.empty_cache()
+        g = S32.get_state_tensor()
+        fams = {}
+        for fam, idx in FAMILIES.items():
+            mx, den, l1 = 0.0, 0.0, []
+            for f in idx:
+                r = ref[f].cuda()
+                d = (g[f] - r).abs_()
+                mx = max(mx, float(d.max()))
+                den = max(den, float(r.abs().max()))
+                l1.append(float(d.sum(dtype=torch.float64)) / max(float(r.abs().sum(dtype=torch.float64)), 1e-300))
+                del r, d
+            fams[fam] = {"max_rel": mx / den if den > 0 else mx, "l1": float(np.mean(l1))}
+        del g, ref
+        torch.cuda.empty_cache()
+        rows.append({"step": c, "time_f64": S64.time(), "time_f32": S32.time(), "f32_vs_f64": fams})
+        log(f"[precision] config 3 step {c}: {fams}")
+    S64.close()
+    S32.close()
+    return {"workload": "3D Orszag-Tang-type 1024^3", "cfl": args.cfl, "checkpoints": rows,
+            "ms_per_step": {p: round(1e3 * el[p] / checkpoints[-1], 2) for p in el}}
+
+
+def run_precision_report(args, torch, mhd):
+    """FP32 and FP64 on the GPU against the oracle over many steps: config 2
+    (256^3 turbulence, 100 steps, with the oracle) and config 3 (1024^3,
+    50 steps, FP32 against FP64)"""
+    rep = {"metric": "precision of the FP32 and FP64 GPU tiers over many steps", "unit": "relative error",
+           "higher_is_better": False, "n_gpus": 1, "data": "synthetic"}
+    which = args.precision_report
+    if which in ("all", "2"):
+        rep["config2_turb256_100_steps"] = precision_config2(args, torch, mhd)
+    if which in ("all", "3"):
+        rep["config3_ot1024_50_steps"] = precision_config3(args, torch, mhd)
+    print(json.dumps(rep), flush=True)
+
+
 SWEEP_SIZES = (16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
 ORACLE_1CORE_SIZES = (16, 32, 64, 128)   # the sizes of the paper's one-core x86 column
 
@@ -612,7 +830,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="turb256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ot512", choices=sorted(WORKLOADS))
     ap.add_argument("--cfl", type=float, default=0.7)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=20)
@@ -632,6 +850,9 @@ def main():
                     help="size sweep: timed seconds per size (10..500 steps)")
     ap.add_argument("--sweep-slope-from", type=int, default=128,
                     help="size sweep: smallest n of the large-box slope fit")
+    ap.add_argument("--precision-report", default=None, choices=("all", "2", "3"),
+                    help="FP32 / FP64 GPU against the oracle over many steps: 256^3 turbulence "
+                         "for 100 steps (2), 1024^3 FP32 against FP64 for 50 steps (3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
@@ -643,6 +864,8 @@ def main():
 
     if args.size_sweep:
         return run_size_sweep(args, torch, mhd)
+    if args.precision_report:
+        return run_precision_report(args, torch, mhd)
     wl = WORKLOADS[args.workload]
     if wl["ic"] == "ensemble":
         return run_ensemble(args, wl, torch, mhd)
@@ -720,6 +943,8 @@ def main():
     kern["cfl(sync)"] = {"ms": round(ms_cfl_sync, 5),
                          "alg_GBs": round(ALG_WORDS["cfl"] * esize * ncell / (ms_cfl_sync * 1e-3) / 1e9, 1)}
     components = time_components(S, n, wl["prec"], stream, min(args.kernel_reps, 10), torch, mhd)
+    log("[bench] energy window")
+    energy = energy_window(S, args.cfl, ncell, torch)
     # dominant kernel: largest time per step (with fused reverse pairs every
     # kernel runs once a step, otherwise each operator runs twice)
     dom = max((k for k in kern if k != "cfl(sync)" and (k != "pair_x" or not fused)),
@@ -795,10 +1020,14 @@ def main():
             "frac": round(step_traffic / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels": kern,
         "components": components,
-        "power": power.result(el, args.steps, ncell),
+        "power": energy,
+        "power_timed_region": power.result(el, args.steps, ncell),
         "steps_completed": nsteps_ok,
     }
     S.close()
+    log("[bench] copy ceiling")
+    out["copy_ceiling"] = copy_ceiling(torch, mhd, stream)
+    out["step_frac_of_copy"] = round(step_alg / out["copy_ceiling"]["GBs"], 4)
     if args.calibrate_copy:
         # a plain copy kernel of known size: 1 GiB read + 1 GiB written
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

@@ -153,6 +153,24 @@ enum { MHD_LIMITER_VANLEER = 0, MHD_LIMITER_MINMOD = 1, MHD_LIMITER_MC = 2, MHD_
 int mhd_set_limiter(mhd_ctx *h, int limiter);
 int mhd_get_limiter(const mhd_ctx *h, int *limiter);
 
+/* Freezing (relaxation) speed of the fluid operator, a method variant
+ * (section II.B requires only that it exceed the characteristic speeds of
+ * the flux; the reading taken here is one number per step):
+ *   MHD_FREEZE_STEP    the step's relaxation speed, the largest signal speed
+ *                      found by the CFL function (default; see above)
+ *   MHD_FREEZE_CELL    |v_n| + c_fast of each cell, c_fast = sqrt((gamma p +
+ *                      |Bbar|^2)/rho), from the state of each stage (the old
+ *                      state for the first, the half-step state for the
+ *                      second)
+ *   MHD_FREEZE_PENCIL  the largest of those along the pencil, per stage.
+ * The variants need no relaxation speed to be set, run the reverse-half
+ * pairs as two launches each, and come with van Leer's limiter only
+ * (MHD_EINVAL otherwise, here and in mhd_set_limiter).  Applies from the
+ * next call on.  Ensembles always use the step's speed. */
+enum { MHD_FREEZE_STEP = 0, MHD_FREEZE_CELL = 1, MHD_FREEZE_PENCIL = 2 };
+int mhd_set_freezing_speed(mhd_ctx *h, int mode);
+int mhd_get_freezing_speed(const mhd_ctx *h, int *mode);
+
 /* Full step of 2*dt (section II.B; section IV.A): sweeps x, y, z, then
  * z, y, x, i.e. F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x, every
  * operator over dt.  Advances the time by 2*dt.  Asynchronous. */
@@ -352,6 +370,14 @@ int mhd_conv3d_dgrad(const int *n, int cin, int cout, const void *dy, const floa
                      float *dx, void *stream);
 int mhd_conv3d_wgrad(const int *n, int cin, int cout, const void *xT, const void *dyT,
                      float *dw_host, float *dbias_host, void *stream);
+
+/* Plain device-to-device copy of `bytes` bytes with 16-byte vector loads and
+ * stores, enqueued on `stream` (hipStream_t as void*, NULL = default): the
+ * streaming-bandwidth reference the benchmark reports beside the sweep
+ * kernels (not part of the method).  bytes and both pointers must be
+ * multiples of 16 and the ranges must not overlap (MHD_EINVAL); a launch
+ * failure gives MHD_EDEVICE.  Both buffers stay the caller's. */
+int mhd_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Thread-local message describing the last error (never NULL). */
 const char *mhd_last_error(void);

@@ -115,6 +115,36 @@ __device__ __forceinline__ void relax_split(const T u[5], const T bb[3], T gamma
     }
 }
 
+// Freezing (relaxation) speed of the fluid operator.  The method's reading
+// is one number per step (the CFL speed, FRZ_STEP); two variants take it
+// from the state of each stage: FRZ_CELL uses |v_n| + c_fast of each cell,
+// FRZ_PENCIL the largest such value along the pencil (section II.B asks
+// only that it exceed the characteristic speeds of the flux).
+enum { FRZ_STEP = 0, FRZ_CELL = 1, FRZ_PENCIL = 2 };
+
+// |v_n| + sqrt((gamma p + |Bbar|^2)/rho) of one cell with the pressure of
+// fluid_flux (the variants' freezing speed).  FP64: every operation as
+// written, IEEE division and square root; FP32: one reciprocal of rho.
+template <typename T>
+__device__ __forceinline__ T normal_speed(const T u[5], const T bb[3], T gamma)
+{
+    const T rho = u[0], mn = u[1], mt1 = u[2], mt2 = u[3], e = u[4];
+    if constexpr (sizeof(T) == 4) {
+        const float inv = Arith<float>::rcp(rho);
+        const float vn = mn * inv, vt1 = mt1 * inv, vt2 = mt2 * inv;
+        const float b2 = __builtin_fmaf(bb[2], bb[2], __builtin_fmaf(bb[1], bb[1], bb[0] * bb[0]));
+        const float ke = 0.5f * __builtin_fmaf(mt2, vt2, __builtin_fmaf(mt1, vt1, mn * vn));
+        const float p = (gamma - 1.0f) * (e - ke - 0.5f * b2);
+        return fabsf(vn) + sqrtf(__builtin_fmaf(gamma, p, b2) * inv);
+    } else {
+        const T vn = mn / rho;
+        const T b2 = bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
+        const T mm = mn * mn + mt1 * mt1 + mt2 * mt2;
+        const T p = (gamma - T(1)) * (e - T(0.5) * mm / rho - T(0.5) * b2);
+        return fabs(vn) + sqrt((gamma * p + b2) / rho);
+    }
+}
+
 // van Leer limiter (section II.B): 2ab/(a+b) if ab > 0, else 0.
 template <typename T>
 __device__ __forceinline__ T van_leer(T a, T b)

@@ -25,11 +25,13 @@ struct SweepParams {
     // fused CFL (x fluid operator, alone or fused; null: off): the FP64 signal-speed
     // maximum of the operator's output is accumulated in cfl_acc[0 ..
     // CFL_ACC_SLOTS) (bits of the double, atomic max into the slot of the
-    // workgroup, spreading the atomics) and non-physical cells in
-    // cfl_acc[CFL_ACC_SLOTS]
+    // workgroup, spreading the atomics); cfl_acc[CFL_ACC_SLOTS] gets bit 0
+    // for a non-physical cell, and an operator skipped under a record ORs
+    // that record (1 non-physical, 2 zero signal speed) into it
     unsigned long long* cfl_acc;
     double gamma64;          // gamma in FP64 for that speed
     int limiter;             // slope limiter of the single operators (LIM_*; 0: van Leer)
+    int freeze;              // freezing speed of the fluid operator (FRZ_*; 0: the step's c)
 };
 
 // Launch shape choices of the march kernels: chunk length along y and z
@@ -143,6 +145,9 @@ template <typename T>
 hipError_t launch_convert_out(const T* src, double* dst, size_t n, hipStream_t s);
 template <typename S, typename T>
 hipError_t launch_cast(const S* src, T* dst, size_t n, hipStream_t s);
+
+// Plain device copy of `bytes` (a multiple of 16; 16-byte aligned pointers).
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 
 // Restriction by factor r of all 8 fields.
 template <typename T>

@@ -71,6 +71,7 @@ struct mhd_ctx {
     // operators in turn; same result bit for bit
     int rev_mode;           // 0 built-in choice, 1 fused, 2 the two operators
     int limiter;            // slope limiter of the operators (MHD_LIMITER_*)
+    int freeze;             // freezing speed of the fluid operator (MHD_FREEZE_*)
     double scal_dt, scal_c;
     bool failed;
     LaunchTuning tune;
@@ -527,6 +528,7 @@ static hipError_t enqueue_op(mhd_ctx* h, int op, int d, const int* flag, unsigne
     P.cfl_acc = acc;
     P.gamma64 = h->gamma;
     P.limiter = h->limiter;
+    P.freeze = h->freeze;
     hipError_t e = op == 0 ? launch_fluid<T>(P, d, h->tune, h->stream)
                  : op == 1 ? launch_magnetic<T>(P, d, h->tune, h->stream)
                            : launch_magfluid<T>(P, d, h->tune, h->stream);
@@ -556,6 +558,8 @@ static int prepare_host_dt(mhd_ctx* h, double dt, bool need_c)
     int r = check_handle(h);
     if (r) return r;
     if ((r = check_dt(dt))) return r;
+    // the per-cell and per-pencil freezing speeds come from the state
+    if (h->freeze != MHD_FREEZE_STEP) need_c = false;
     if (need_c && !h->have_c)
         return fail(MHD_ESTATE, "relaxation speed not set: call mhd_cfl_dt or mhd_set_relaxation_speed");
     HIP_TRY(h, hipSetDevice(h->device));
@@ -589,9 +593,11 @@ extern "C" int mhd_magnetic(mhd_ctx* h, int dim, double dt)
     return MHD_OK;
 }
 
-// the reverse pairs run as one fused launch each
+// the reverse pairs run as one fused launch each (the fused kernels take
+// the step's freezing speed only)
 static bool pairs_fused(const mhd_ctx* h)
 {
+    if (h->freeze != MHD_FREEZE_STEP) return false;
     return h->rev_mode == 1 || (h->rev_mode == 0 && default_rev_fused(h->prec, h->limiter));
 }
 
@@ -654,7 +660,30 @@ extern "C" int mhd_set_limiter(mhd_ctx* h, int limiter)
     if (r) return r;
     if (limiter < MHD_LIMITER_VANLEER || limiter > MHD_LIMITER_SUPERBEE)
         return fail(MHD_EINVAL, "limiter must be 0..3 (got %d)", limiter);
+    if (limiter != MHD_LIMITER_VANLEER && h->freeze != MHD_FREEZE_STEP)
+        return fail(MHD_EINVAL, "the freezing-speed variants come with van Leer's limiter only");
     h->limiter = limiter;
+    return MHD_OK;
+}
+
+extern "C" int mhd_set_freezing_speed(mhd_ctx* h, int mode)
+{
+    int r = check_handle(h);
+    if (r) return r;
+    if (mode < MHD_FREEZE_STEP || mode > MHD_FREEZE_PENCIL)
+        return fail(MHD_EINVAL, "freezing-speed mode must be 0..2 (got %d)", mode);
+    if (mode != MHD_FREEZE_STEP && h->limiter != MHD_LIMITER_VANLEER)
+        return fail(MHD_EINVAL, "the freezing-speed variants come with van Leer's limiter only");
+    h->freeze = mode;
+    return MHD_OK;
+}
+
+extern "C" int mhd_get_freezing_speed(const mhd_ctx* h, int* mode)
+{
+    int r = check_handle(h);
+    if (r) return r;
+    if (!mode) return fail(MHD_EINVAL, "null output");
+    *mode = h->freeze;
     return MHD_OK;
 }
 
@@ -871,6 +900,20 @@ void mhd_internal_state_changed(mhd_ctx* h)
 }
 
 double mhd_internal_gamma(const mhd_ctx* h) { return h->gamma; }
+
+extern "C" int mhd_stream_copy(const void* src, void* dst, size_t bytes, void* stream)
+{
+    if (!src || !dst) return fail(MHD_EINVAL, "null device pointer");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(MHD_EINVAL, "the copy moves 16-byte words: size and both pointers must be multiples of 16");
+    const char* a = static_cast<const char*>(src);
+    const char* b = static_cast<const char*>(dst);
+    if (a < b + bytes && b < a + bytes) return fail(MHD_EINVAL, "source and destination overlap");
+    if (bytes == 0) return MHD_OK;
+    const hipError_t e = launch_stream_copy(src, dst, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(MHD_EDEVICE, "stream copy: %s", hipGetErrorString(e));
+    return MHD_OK;
+}
 
 extern "C" const char* mhd_last_error(void)
 {

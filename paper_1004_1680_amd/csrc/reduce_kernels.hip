@@ -166,11 +166,13 @@ __global__ void __launch_bounds__(CFL_ACC_SLOTS) cfl_from_acc_kernel(unsigned lo
     if (threadIdx.x == 0) {
         double vmax = smax[0];
         for (int q = 1; q < CFL_ACC_SLOTS / 64; ++q) vmax = fmax(vmax, smax[q]);
+        // bit 0: a non-physical cell (or record); bit 1 alone: a step skipped
+        // under a zero-speed record, whose state still has no signal speed
         const int b = (int)acc[CFL_ACC_SLOTS];
         if (b || !(vmax > 0.0)) {
             scal[SCAL_DT] = 0.0;
             scal[SCAL_VMAX] = 0.0;
-            flag[0] = b ? 1 : 2;
+            flag[0] = (b & 1) ? 1 : 2;
         } else {
             scal[SCAL_DT] = cfl * (1.0 / (double)nx) / vmax;
             scal[SCAL_VMAX] = vmax;
@@ -315,7 +317,7 @@ __global__ void __launch_bounds__(CFL_ACC_SLOTS) batch_cfl_from_acc_kernel(unsig
         if (bb || !(vmax > 0.0)) {
             sc[SCAL_DT] = 0.0;
             sc[SCAL_VMAX] = 0.0;
-            flag[(size_t)b * FLAG_COUNT + FLAG_NONPHYS] = bb ? 1 : 2;
+            flag[(size_t)b * FLAG_COUNT + FLAG_NONPHYS] = (bb & 1) ? 1 : 2;
         } else {
             sc[SCAL_DT] = cfl * (1.0 / (double)boxes[b].n[0]) / vmax;
             sc[SCAL_VMAX] = vmax;
@@ -501,6 +503,36 @@ template hipError_t launch_cast<double, float>(const double*, float*, size_t, hi
 template hipError_t launch_cast<float, double>(const float*, double*, size_t, hipStream_t);
 template hipError_t launch_cast<float, float>(const float*, float*, size_t, hipStream_t);
 template hipError_t launch_cast<double, double>(const double*, double*, size_t, hipStream_t);
+
+// Plain streaming copy of 16-byte words, the bandwidth reference of the
+// sweep kernels: each thread moves 4 words per round (a wave's 64 lanes read
+// one contiguous KiB per word slot), all loads of a round before its stores;
+// grid-stride over the buffer.
+__global__ void __launch_bounds__(256) stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                          size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * 256 * 4;
+    for (size_t i = (size_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + (size_t)k * 256 < n) v[k] = src[i + (size_t)k * 256];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i + (size_t)k * 256 < n) dst[i + (size_t)k * 256] = v[k];
+    }
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    size_t grid = (n + 1023) / 1024;
+    if (grid > 4096) grid = 4096;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)grid), dim3(256), 0, s, static_cast<const uint4*>(src),
+                       static_cast<uint4*>(dst), n);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_convert_in(const double* src, T* dst, size_t n, hipStream_t s)

@@ -33,6 +33,8 @@ namespace mhd {
 static_assert(LIM_VANLEER == MHD_LIMITER_VANLEER && LIM_MINMOD == MHD_LIMITER_MINMOD && LIM_MC == MHD_LIMITER_MC &&
                   LIM_SUPERBEE == MHD_LIMITER_SUPERBEE,
               "device limiter codes are the C ABI's");
+static_assert(FRZ_STEP == MHD_FREEZE_STEP && FRZ_CELL == MHD_FREEZE_CELL && FRZ_PENCIL == MHD_FREEZE_PENCIL,
+              "device freezing-speed codes are the C ABI's");
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -96,21 +98,57 @@ __device__ __forceinline__ void step_scalars(const SweepParams<T>& P, T& tau, T&
 // exchange with themselves, so every LDS index stays below blockDim.x.
 struct RowThread {
     int t, tprev, tnext, i0, y, z;
-    bool active;
-    __device__ __forceinline__ RowThread(int tile, int tpr, int rows_per_wg, int ny, int nz)
+    int row0, tr, tpr;       // first thread of the row, position in it, threads per row
+    bool active, inrow;
+    __device__ __forceinline__ RowThread(int tile, int tpr_, int rows_per_wg, int ny, int nz)
     {
         t = threadIdx.x;
-        const int rloc = t / tpr, tr = t - rloc * tpr;
+        tpr = tpr_;
+        const int rloc = t / tpr;
+        tr = t - rloc * tpr;
         const int row = tile * rows_per_wg + rloc;
         active = rloc < rows_per_wg && row < ny * nz;
         y = active ? row % ny : 0;
         z = active ? row / ny : 0;
-        const bool inrow = rloc < rows_per_wg;
+        inrow = rloc < rows_per_wg;
+        row0 = rloc * tpr;
         tprev = inrow ? rloc * tpr + (tr == 0 ? tpr - 1 : tr - 1) : t;
         tnext = inrow ? rloc * tpr + (tr == tpr - 1 ? 0 : tr + 1) : t;
         i0 = 4 * tr;
     }
 };
+
+// Freezing speed of the 4 cells of a row thread for one stage (state w,
+// field bb): FRZ_STEP the step's c; FRZ_CELL |v_n| + c_fast of each cell;
+// FRZ_PENCIL the largest of those along the row, an all-reduce over the
+// row's threads by doubling windows in S (blockDim.x values of LDS, free
+// on entry; free again on return).  Every thread of the workgroup calls it.
+template <typename T, int FRZ>
+__device__ __forceinline__ void row_stage_speeds(const T (&w)[4][5], const T (&bb)[4][3], T gamma, T c,
+                                                 const RowThread& R, T* const S, T (&cs)[4])
+{
+    if constexpr (FRZ == FRZ_STEP) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cs[k] = c;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cs[k] = normal_speed(w[k], bb[k], gamma);
+        if constexpr (FRZ == FRZ_PENCIL) {
+            T v = fmax(fmax(cs[0], cs[1]), fmax(cs[2], cs[3]));
+            // after the round with offset s each thread holds the maximum of
+            // the 2s threads tr .. tr+2s-1 of its row (cyclically)
+            for (int s = 1; s < R.tpr; s <<= 1) {
+                S[R.t] = v;
+                __syncthreads();
+                const T o = S[R.inrow ? R.row0 + (R.tr + s) % R.tpr : R.t];
+                __syncthreads();
+                v = fmax(v, o);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cs[k] = v;
+        }
+    }
+}
 
 // x fluid operator from given inputs: U of the thread's 4 cells, the frozen
 // Bbar, and (CFL) the raw face values (own, next) of b_x, b_y, b_z for the
@@ -119,7 +157,7 @@ struct RowThread {
 // CFL = true: the FP64 signal speed of every output cell, maximum per wave,
 // atomic maximum into P.cfl_acc; needs full waves (blockDim.x a multiple of
 // 64).
-template <typename T, bool CFL, int LIM = LIM_VANLEER>
+template <typename T, bool CFL, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
 __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowThread& R, size_t base,
                                              const T (&u)[4][5], const T (&bb)[4][3],
                                              const T (&fb)[CFL ? 4 : 1][6], T* const A)
@@ -133,8 +171,10 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
 
     // stage 1: relaxed split and first-order upwind interface fluxes
     T fr[4][5], fl[4][5];
+    T cs[4];
+    row_stage_speeds<T, FRZ>(u, bb, gamma, c, R, A, cs);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) relax_split(u[k], bb[k], gamma, c, fr[k], fl[k]);
+    for (int k = 0; k < 4; ++k) relax_split(u[k], bb[k], gamma, cs[k], fr[k], fl[k]);
     // LDS regions alternate A, B, A, B between the four exchanges: a region
     // is rewritten only after the barrier that follows its last read.
     // exchange 1: F^L of the first cell goes to the previous thread
@@ -161,9 +201,11 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
             uh[k][q] = sub_scaled(u[k][q], halftau, f1[k][q] - (k > 0 ? f1[k - 1][q] : f1prev));
     }
 
-    // stage 2: fluxes of the half-step state, van Leer limited
+    // stage 2: fluxes of the half-step state, van Leer limited (region A
+    // was last read before the previous barrier)
+    row_stage_speeds<T, FRZ>(uh, bb, gamma, c, R, A, cs);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) relax_split(uh[k], bb[k], gamma, c, fr[k], fl[k]);
+    for (int k = 0; k < 4; ++k) relax_split(uh[k], bb[k], gamma, cs[k], fr[k], fl[k]);
     // exchange 3: edge values of the stage-2 parts
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -280,7 +322,7 @@ __device__ __forceinline__ void load_u4(const SweepParams<T>& P, const RowThread
 }
 
 // One tile of rows_per_wg rows of one grid: fluid operator F_x.
-template <typename T, bool CFL = false, int LIM = LIM_VANLEER>
+template <typename T, bool CFL = false, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
 __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
                                              int rows_per_wg, T* const A)
 {
@@ -299,8 +341,10 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
                 vec4<T>::load(P.in[f] + base + i0, v);
                 vec4<T>::store(P.out[f] + base + i0, v);
             }
+        // the record (1 non-physical, 2 zero signal speed) carries over to
+        // the CFL that follows, as the separate reduction would find it
         if constexpr (CFL)
-            if (threadIdx.x == 0) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, 1ull);
+            if (threadIdx.x == 0) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, (unsigned long long)*P.flag);
         return;
     }
 
@@ -336,14 +380,14 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
 #pragma unroll
             for (int k = 0; k < 4; ++k) { fb[k][4] = tmp[k]; fb[k][5] = tmp2[k]; }
     }
-    fluid_x_core<T, CFL, LIM>(P, R, base, u, bb, fb, A);
+    fluid_x_core<T, CFL, LIM, FRZ>(P, R, base, u, bb, fb, A);
 }
 
-template <typename T, bool CFL, int LIM = LIM_VANLEER>
+template <typename T, bool CFL, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
 __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fluid_x_tile<T, CFL, LIM>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    fluid_x_tile<T, CFL, LIM, FRZ>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // Magnetic operator along x (e = y then z) of the thread's 4 cells.  For
@@ -544,8 +588,10 @@ __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int til
                 vec4<T>::load(P.in[f] + base + R.i0, v);
                 vec4<T>::store(P.out[f] + base + R.i0, v);
             }
+        // the record (1 non-physical, 2 zero signal speed) carries over to
+        // the CFL that follows, as the separate reduction would find it
         if constexpr (CFL)
-            if (threadIdx.x == 0) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, 1ull);
+            if (threadIdx.x == 0) atomicOr(P.cfl_acc + CFL_ACC_SLOTS, (unsigned long long)*P.flag);
         return;
     }
     T nb[5][4];
@@ -640,7 +686,7 @@ __device__ __forceinline__ int march_start(int j0, int chunk)
 // and gives the new U of cell L-3; it needs U and Bbar at L-3 .. L+3, so
 // pushes 6 positions before a chunk warm the window up (their results are
 // not used).
-template <typename T, int LIM = LIM_VANLEER>
+template <typename T, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
 struct FluidWindow {
     T u3[5], u2[5], u1[5];            // U at L-3, L-2, L-1
     T bbm[3];                         // Bbar at L-1
@@ -660,12 +706,14 @@ struct FluidWindow {
         bbm[0] = bbm[1] = bbm[2] = T(0);
     }
 
-    __device__ __forceinline__ void push(const T u0[5], const T bb0[3], T gamma, T c, T tau,
+    // c, c2: freezing speeds of stages 1 and 2 (the step's speed twice, or
+    // the pencil's two maxima); FRZ_CELL takes each cell's own instead
+    __device__ __forceinline__ void push(const T u0[5], const T bb0[3], T gamma, T c, T c2, T tau,
                                          T halftau, T unew[5])
     {
         // stage 1 at L: split, interface flux at L-1/2, half step at L-1
         T fr0[5], fl0[5], f1[5], uh[5];
-        relax_split(u0, bb0, gamma, c, fr0, fl0);
+        relax_split(u0, bb0, gamma, FRZ == FRZ_CELL ? normal_speed(u0, bb0, gamma) : c, fr0, fl0);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             f1[q] = frm[q] - fl0[q];
@@ -673,7 +721,7 @@ struct FluidWindow {
         }
         // stage 2 at L-1
         T r1[5], l1[5];
-        relax_split(uh, bbm, gamma, c, r1, l1);
+        relax_split(uh, bbm, gamma, FRZ == FRZ_CELL ? normal_speed(uh, bbm, gamma) : c2, r1, l1);
         // net flux at interface (L-3)+1/2 and the update of cell L-3
         T phi[5];
 #pragma unroll
@@ -812,8 +860,63 @@ __device__ __forceinline__ int wrap_pos(int j, int nd)
     return m < 0 ? m + nd : m;
 }
 
+// The two freezing speeds of the FRZ_PENCIL variant for one pencil: the
+// largest |v_n| + c_fast of the old state (stage 1) and of the half-step
+// state that stage 1 makes with it (stage 2), in two passes over the whole
+// pencil with the march's own expressions (the same values as the row
+// kernels find for an x pencil).  o_u: the five fluid fields of the pencil;
+// bn, bt1, bt2 with bases gb (this pencil), gt1, gt2 (pencils P+t1, P+t2).
+template <typename T, bool W32, typename UPtrs>
+__device__ __forceinline__ void pencil_speeds(const UPtrs& in_u, const T* __restrict__ bn,
+                                              const T* __restrict__ bt1, const T* __restrict__ bt2,
+                                              unsigned gb, unsigned gt1, unsigned gt2, unsigned step, int nd,
+                                              T gamma, T halftau, T& c1, T& c2)
+{
+    using A = Addr<T, W32>;
+    auto load = [&](int j, T (&u)[5], T (&bb)[3]) {
+        const int jn = j + 1 == nd ? 0 : j + 1;
+        const unsigned o = (unsigned)j * step, on = (unsigned)jn * step;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) u[q] = A::ld(in_u[q], gb + o);
+        bb[0] = T(0.5) * (A::ld(bn, gb + o) + A::ld(bn, gb + on));
+        bb[1] = T(0.5) * (A::ld(bt1, gb + o) + A::ld(bt1, gt1 + o));
+        bb[2] = T(0.5) * (A::ld(bt2, gb + o) + A::ld(bt2, gt2 + o));
+    };
+    c1 = T(0);
+    for (int j = 0; j < nd; ++j) {
+        T u[5], bb[3];
+        load(j, u, bb);
+        c1 = fmax(c1, normal_speed(u, bb, gamma));
+    }
+    // stage 1 with c1 (as FluidWindow::push): at position L the split of L,
+    // the interface flux at L-1/2 and the half-step state of cell L-1
+    c2 = T(0);
+    T frm[5] = {}, f1m[5] = {}, um[5] = {}, bbm[3] = {};
+    for (int L = -1; L <= nd; ++L) {
+        T u[5], bb[3], fr[5], fl[5];
+        load(wrap_pos(L, nd), u, bb);
+        relax_split(u, bb, gamma, c1, fr, fl);
+        T f1[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) f1[q] = frm[q] - fl[q];
+        if (L >= 1) {
+            T uh[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) uh[q] = sub_scaled(um[q], halftau, f1[q] - f1m[q]);
+            c2 = fmax(c2, normal_speed(uh, bbm, gamma));
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            frm[q] = fr[q];
+            f1m[q] = f1[q];
+            um[q] = u[q];
+        }
+        bbm[0] = bb[0]; bbm[1] = bb[1]; bbm[2] = bb[2];
+    }
+}
+
 // One lane (pencil chunk gid) of a grid: fluid operator F_d.
-template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
 __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long gid, int chunk)
 {
     constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
@@ -840,8 +943,10 @@ __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long g
     const T gamma = P.gamma;
     const unsigned step = G.sd * A::scale;
     const unsigned gb = G.base * A::scale, gt1 = G.b_t1p * A::scale, gt2 = G.b_t2p * A::scale;
+    T c2 = c;
+    if constexpr (FRZ == FRZ_PENCIL) pencil_speeds<T, W32>(in_u, bn, bt1, bt2, gb, gt1, gt2, step, nd, gamma, halftau, c, c2);
 
-    FluidWindow<T, LIM> W;
+    FluidWindow<T, LIM, FRZ> W;
     W.init();
     constexpr int U = march_unroll<T>();
     const int Lstart = march_start<U>(j0, chunk);
@@ -883,7 +988,7 @@ __device__ __forceinline__ void fluid_march_lane(const SweepParams<T>& P, long g
             pn.next(nd, step);
             prefetch();
             T unew[5];
-            W.push(u0, bb0, gamma, c, tau, halftau, unew);
+            W.push(u0, bb0, gamma, c, c2, tau, halftau, unew);
             if (L - 3 >= j0) {
 #pragma unroll
                 for (int q = 0; q < 5; ++q) A::st(out_u[q], po, unew[q]);
@@ -902,10 +1007,10 @@ template <typename T> constexpr int march_waves() { return sizeof(T) == 4 ? 4 : 
 // where 3 made the ensemble step 12% slower)
 template <typename T> constexpr int fluid_march_waves() { return sizeof(T) == 4 ? 3 : 2; }
 
-template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
 __global__ void __launch_bounds__(256, fluid_march_waves<T>()) fluid_march_kernel(SweepParams<T> P, int chunk)
 {
-    fluid_march_lane<T, D, W32, LIM>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+    fluid_march_lane<T, D, W32, LIM, FRZ>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
 
 // Inputs of the magnetic window at one position: v_n of the 5 pencils, the
@@ -1142,7 +1247,7 @@ __device__ __forceinline__ void magfluid_march_lane(const SweepParams<T>& P, lon
             bb0[2] = T(0.5) * (pb_t2o + pb_t2p);
             pb_t1o = nb[0]; pb_t1p = nb[1]; pb_t2o = nb[2]; pb_t2p = nb[3]; pb_n = nb[4];
             T unew[5];
-            WF.push(u0, bb0, gamma, c, tau, halftau, unew);
+            WF.push(u0, bb0, gamma, c, c, tau, halftau, unew);
             if (s - 7 >= j0) {
 #pragma unroll
                 for (int q = 0; q < 5; ++q) A::st(out_u[q], pfo, unew[q]);
@@ -1191,7 +1296,7 @@ inline bool offsets32(const SweepParams<T>& P, const LaunchTuning& tune)
     return !tune.wide && (unsigned long long)P.nx * P.ny * P.nz * sizeof(T) <= (1ull << 32);
 }
 
-template <typename T, int LIM>
+template <typename T, int LIM, int FRZ = FRZ_STEP>
 hipError_t launch_fluid_lim(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
     if (d == 0) {
@@ -1202,23 +1307,25 @@ hipError_t launch_fluid_lim(const SweepParams<T>& P, int d, const LaunchTuning& 
         const size_t lds = sizeof(T) * 25 * threads;
         if (P.cfl_acc) {
             if (threads % 64) return hipErrorInvalidValue;      // fused CFL needs full waves
-            hipLaunchKernelGGL((fluid_x_kernel<T, true, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((fluid_x_kernel<T, true, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
         } else {
-            hipLaunchKernelGGL((fluid_x_kernel<T, false, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((fluid_x_kernel<T, false, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
         }
     } else {
         const int nd = d == 1 ? P.ny : P.nz;
         const int npencil = P.nx * (d == 1 ? P.nz : P.ny);
         int chunk = tune.chunk[d];
-        if (chunk <= 0 || nd % chunk) chunk = nd;
+        // the pencil variant reads its whole pencil twice before marching:
+        // one chunk per pencil
+        if (chunk <= 0 || nd % chunk || FRZ == FRZ_PENCIL) chunk = nd;
         const long lanes = (long)npencil * (nd / chunk);
         const int grid = (int)((lanes + 255) / 256);
         if (offsets32<T>(P, tune)) {
-            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, true, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
-            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, true, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
+            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, true, LIM, FRZ>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, true, LIM, FRZ>), dim3(grid), dim3(256), 0, s, P, chunk);
         } else {
-            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, false, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
-            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, false, LIM>), dim3(grid), dim3(256), 0, s, P, chunk);
+            if (d == 1) hipLaunchKernelGGL((fluid_march_kernel<T, 1, false, LIM, FRZ>), dim3(grid), dim3(256), 0, s, P, chunk);
+            else hipLaunchKernelGGL((fluid_march_kernel<T, 2, false, LIM, FRZ>), dim3(grid), dim3(256), 0, s, P, chunk);
         }
     }
     return hipGetLastError();
@@ -1252,10 +1359,17 @@ hipError_t launch_magnetic_lim(const SweepParams<T>& P, int d, const LaunchTunin
     return hipGetLastError();
 }
 
-// the single operators with the limiter P.limiter
+// the single operators with the limiter P.limiter; the fluid operator's
+// freezing-speed variants (P.freeze) come with van Leer's limiter only
 template <typename T>
 hipError_t launch_fluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
+    if (P.freeze != FRZ_STEP) {
+        if (P.limiter != LIM_VANLEER) return hipErrorInvalidValue;
+        if (P.freeze == FRZ_CELL) return launch_fluid_lim<T, LIM_VANLEER, FRZ_CELL>(P, d, tune, s);
+        if (P.freeze == FRZ_PENCIL) return launch_fluid_lim<T, LIM_VANLEER, FRZ_PENCIL>(P, d, tune, s);
+        return hipErrorInvalidValue;
+    }
     switch (P.limiter) {
     case LIM_VANLEER: return launch_fluid_lim<T, LIM_VANLEER>(P, d, tune, s);
     case LIM_MINMOD: return launch_fluid_lim<T, LIM_MINMOD>(P, d, tune, s);
@@ -1351,6 +1465,7 @@ __device__ __forceinline__ SweepParams<T> box_params(const BatchParams<T>& B, in
     P.cfl_acc = B.cfl_acc ? B.cfl_acc + (size_t)box * (CFL_ACC_SLOTS + 1) : nullptr;
     P.gamma64 = B.gamma64;
     P.limiter = 0;
+    P.freeze = FRZ_STEP;
     return P;
 }
 

@@ -23,6 +23,7 @@ MHD_TUNE_PAIR_CHUNK_Y, MHD_TUNE_PAIR_CHUNK_Z, MHD_TUNE_WIDE_OFFSETS = 4, 5, 6
 MHD_BATCH_GRID_X, MHD_BATCH_GRID_Y, MHD_BATCH_GRID_Z, MHD_BATCH_CHUNK = 10, 11, 12, 13
 MHD_BATCH_REVERSE, MHD_BATCH_WIDE_OFFSETS, MHD_BATCH_PAIR_CHUNK = 14, 15, 16
 MHD_LIMITER_VANLEER, MHD_LIMITER_MINMOD, MHD_LIMITER_MC, MHD_LIMITER_SUPERBEE = 0, 1, 2, 3
+MHD_FREEZE_STEP, MHD_FREEZE_CELL, MHD_FREEZE_PENCIL = 0, 1, 2
 
 _lib = None
 
@@ -81,6 +82,8 @@ def load():
         "mhd_get_launch": (i, [vp, i, ip]),
         "mhd_set_limiter": (i, [vp, i]),
         "mhd_get_limiter": (i, [vp, ip]),
+        "mhd_set_freezing_speed": (i, [vp, i]),
+        "mhd_get_freezing_speed": (i, [vp, ip]),
         "mhd_batch_create": (vp, [i, ip, d, i, vp]),
         "mhd_batch_destroy": (None, [vp]),
         "mhd_batch_info": (i, [vp, ip, ctypes.POINTER(ctypes.c_longlong)]),
@@ -112,6 +115,7 @@ def load():
         "mhd_conv3d_forward": (i, [ip, i, i, vp, fp, fp, vp, vp]),
         "mhd_conv3d_dgrad": (i, [ip, i, i, vp, fp, vp, vp]),
         "mhd_conv3d_wgrad": (i, [ip, i, i, vp, vp, fp, fp, vp]),
+        "mhd_stream_copy": (i, [vp, vp, sz, vp]),
         "mhd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -128,7 +132,8 @@ def exported_symbols():
                         "mhd_cfl_dt", "mhd_set_relaxation_speed", "mhd_get_relaxation_speed",
                         "mhd_fluid", "mhd_magnetic", "mhd_sweep", "mhd_step", "mhd_step_auto",
                         "mhd_status", "mhd_time", "mhd_diag", "mhd_restrict", "mhd_set_launch",
-                        "mhd_get_launch", "mhd_set_limiter", "mhd_get_limiter", "mhd_batch_create", "mhd_batch_destroy",
+                        "mhd_get_launch", "mhd_set_limiter", "mhd_get_limiter", "mhd_set_freezing_speed",
+                        "mhd_get_freezing_speed", "mhd_batch_create", "mhd_batch_destroy",
                         "mhd_batch_info", "mhd_batch_set_state", "mhd_batch_get_state",
                         "mhd_batch_step_auto", "mhd_batch_run", "mhd_batch_status",
                         "mhd_batch_time", "mhd_batch_set_launch", "mhd_batch_get_launch",
@@ -139,7 +144,7 @@ def exported_symbols():
                         "mhd_closure_fallbacks", "mhd_closure_reduced", "mhd_closure_residual", "mhd_closure_stats",
                         "mhd_closure_set_gate", "mhd_closure_get_gate",
                         "mhd_conv3d_forward", "mhd_conv3d_dgrad",
-                        "mhd_conv3d_wgrad", "mhd_last_error")]
+                        "mhd_conv3d_wgrad", "mhd_stream_copy", "mhd_last_error")]
 
 
 def last_error():
@@ -399,6 +404,17 @@ class Solver:
         check(self.lib.mhd_get_limiter(self.h, ctypes.byref(v)))
         return v.value
 
+    def set_freezing(self, mode):
+        """freezing speed of the fluid operator: MHD_FREEZE_STEP (one number
+        per step, default), MHD_FREEZE_CELL or MHD_FREEZE_PENCIL (method
+        variants, van Leer's limiter only)"""
+        check(self.lib.mhd_set_freezing_speed(self.h, mode))
+
+    def freezing(self):
+        v = ctypes.c_int(0)
+        check(self.lib.mhd_get_freezing_speed(self.h, ctypes.byref(v)))
+        return v.value
+
     def restrict_to(self, coarse):
         check(self.lib.mhd_restrict(self.h, coarse.h))
 
@@ -641,3 +657,13 @@ def conv3d_wgrad(n, cin, cout, xT, dyT, stream=None):
     check(load().mhd_conv3d_wgrad(nn, cin, cout, _dptr(xT), _dptr(dyT), _fptr(dw), _fptr(db),
                                   _torch_stream(stream)))
     return dw, db
+
+
+def stream_copy(src, dst, stream=None):
+    """plain device copy of a tensor's bytes into another of the same size
+    (the streaming-bandwidth reference); asynchronous on `stream`"""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("source and destination sizes differ")
+    check(load().mhd_stream_copy(_dptr(src), _dptr(dst), nbytes, _torch_stream(stream)))
+

@@ -30,3 +30,14 @@ def test_power_sampler_reads_microwatts(tmp_path):
     assert r["samples"] >= 1 and r["avg_W"] == 250.0
     assert r["J_per_step"] == 125.0                  # 250 W x 2 s / 4 steps
     assert r["Mcell_updates_per_J"] == 8.0           # 4e9 cell-updates / 500 J
+
+
+def test_cpu_baseline_reports_median_model_and_threads():
+    sys.path.insert(0, ROOT)
+    import bench
+    out = bench.cpu_baseline({"n": 16, "ic": "orszag_tang"})
+    assert out["kind"] == "oracle" and out["value"] > 0
+    assert "median of 3 full steps" in out["sample"] and "the same initial state at 16^3" in out["sample"]
+    model, threads, avail = bench.cpu_info()
+    assert out["cores"] == threads >= 1 and out["cpu_model"] == model
+    assert out["single_thread"]["cores"] == 1

@@ -247,3 +247,27 @@ def test_sweep_with_fused_cfl(M, prec, mode):
         S.close()
     assert np.array_equal(outs[0][0], outs[1][0])
     assert outs[0][1] == outs[1][1]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_zero_speed_record_survives_the_fused_cfl(M, prec):
+    """a static, cold, unmagnetised state (rho = 1, m = e = b = 0) is
+    physical (p = 0) but has no signal speed: the device CFL records a zero
+    speed (MHD_EINVAL from status, not MHD_ENONPHYS), the steps keep the
+    state, and the record stays the same through the CFL that the skipped
+    last launch of a step hands to the next step"""
+    n = (16, 16, 16)
+    say(f"case: zero-speed record {prec}")
+    cold = np.zeros((8,) + n)
+    cold[0] = 1.0
+    S = M.Solver(n, prec=prec)
+    S.set_state(cold)
+    for rounds in range(2):
+        for _ in range(3):
+            S.step_auto(0.7)
+        with pytest.raises(M.MHDError) as e:
+            S.status()
+        assert not isinstance(e.value, M.NonPhysicalState), rounds
+        assert e.value.code == M.MHD_EINVAL, rounds
+    assert np.array_equal(S.get_state(), cold)
+    S.close()
