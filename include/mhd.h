@@ -371,6 +371,25 @@ int mhd_conv3d_dgrad(const int *n, int cin, int cout, const void *dy, const floa
 int mhd_conv3d_wgrad(const int *n, int cin, int cout, const void *xT, const void *dyT,
                      float *dw_host, float *dbias_host, void *stream);
 
+/* CFL time step of a state in the caller's device memory, allocating
+ * nothing: for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The same kernels
+ * and result as mhd_cfl_dt, with the reduction's block partials, scalars and
+ * flag in a fixed array of 49,200 bytes of each device's global memory, held
+ * until the process ends, instead of a handle's buffers.
+ * state_dev: 8*nx*ny*nz values of type float (prec MHD_F32) or double
+ * (MHD_F64) in the state layout above; out_dev: 3 doubles of device memory
+ * that receive dt = cfl h / vmax, vmax, and the record (0 none, 1 a cell
+ * with rho <= 0, p < 0 or a non-finite value, 2 zero signal speed; dt =
+ * vmax = 0 with a record).  Grid limits of mhd_create_ex (MHD_EINVAL beyond
+ * them, and for gamma <= 1, cfl <= 0 or a null pointer).  Enqueued on
+ * `stream` (hipStream_t as void*, NULL = default); read out_dev after the
+ * stream.  All calls on one device share the array: calls that overlap in
+ * time on one device (other streams, other threads) race, so serialise
+ * them.  Both buffers stay the caller's. */
+int mhd_cfl_dt_noalloc(const void *state_dev, int nx, int ny, int nz, int prec, double gamma,
+                       double cfl, double *out_dev, void *stream);
+
 /* Plain device-to-device copy of `bytes` bytes with 16-byte vector loads and
  * stores, enqueued on `stream` (hipStream_t as void*, NULL = default): the
  * streaming-bandwidth reference the benchmark reports beside the sweep

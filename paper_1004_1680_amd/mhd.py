@@ -116,6 +116,7 @@ def load():
         "mhd_conv3d_dgrad": (i, [ip, i, i, vp, fp, vp, vp]),
         "mhd_conv3d_wgrad": (i, [ip, i, i, vp, vp, fp, fp, vp]),
         "mhd_stream_copy": (i, [vp, vp, sz, vp]),
+        "mhd_cfl_dt_noalloc": (i, [vp, i, i, i, i, d, d, vp, vp]),
         "mhd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -144,7 +145,8 @@ def exported_symbols():
                         "mhd_closure_fallbacks", "mhd_closure_reduced", "mhd_closure_residual", "mhd_closure_stats",
                         "mhd_closure_set_gate", "mhd_closure_get_gate",
                         "mhd_conv3d_forward", "mhd_conv3d_dgrad",
-                        "mhd_conv3d_wgrad", "mhd_stream_copy", "mhd_last_error")]
+                        "mhd_conv3d_wgrad", "mhd_stream_copy", "mhd_cfl_dt_noalloc",
+                        "mhd_last_error")]
 
 
 def last_error():
@@ -667,3 +669,23 @@ def stream_copy(src, dst, stream=None):
         raise ValueError("source and destination sizes differ")
     check(load().mhd_stream_copy(_dptr(src), _dptr(dst), nbytes, _torch_stream(stream)))
 
+
+def cfl_dt_noalloc(state, n, gamma=5.0 / 3.0, cfl=0.7, out=None, stream=None):
+    """mhd_cfl_dt_noalloc on a device tensor `state` (8 * nx*ny*nz float32 or
+    float64 values, state layout) of grid n = (nx, ny, nz): enqueues the CFL
+    reduction (no allocation) writing (dt, vmax, record) into the float64
+    device tensor `out` (3 values; created if None) and returns it"""
+    import torch
+    if state.dtype == torch.float32:
+        prec = MHD_F32
+    elif state.dtype == torch.float64:
+        prec = MHD_F64
+    else:
+        raise ValueError("state must be float32 or float64")
+    if state.numel() != 8 * n[0] * n[1] * n[2] or not state.is_contiguous():
+        raise ValueError("state must be a contiguous tensor of 8 * nx * ny * nz values")
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=state.device)
+    check(load().mhd_cfl_dt_noalloc(_dptr(state), int(n[0]), int(n[1]), int(n[2]), prec, float(gamma),
+                                    float(cfl), _dptr(out), _torch_stream(stream)))
+    return out
