@@ -64,7 +64,7 @@ CLOSURE_FLOP_PER_CELL = 2 * 27 * (8 * 32 + 32 * 32 + 32 * 8)
 # cell-centred field, writes rho, m, e; magnetic reads rho, m_d and b (3),
 # writes b (3); the fused reverse pair (magnetic then fluid) reads and writes
 # the 8 fields; the CFL reads the 8 fields.
-ALG_WORDS = {"fluid": 8 + 5, "magnetic": 5 + 3, "pair": 8 + 8, "cfl": 8}
+ALG_WORDS = {"fluid": 8 + 5, "magnetic": 5 + 3, "pair": 8 + 8, "middle": 8 + 8, "cfl": 8}
 STEP_WORDS = 6 * (8 + 8) + 8   # fused-sweep lower bound: 8r + 8w per sweep, + CFL
 
 LIMITERS = {"vanleer": 0, "minmod": 1, "mc": 2, "superbee": 3}
@@ -256,6 +256,9 @@ def time_operator(S, op, d, dt, reps, stream, torch):
     elif op == "pair+cfl":
         def f(d, dt):
             S.sweep(6, dt)
+    elif op == "middle":
+        def f(d, dt):
+            S.sweep(7, dt)
     else:
         f = S.fluid if op == "fluid" else S.magnetic
     f(d, dt)                          # scalars already on the device
@@ -307,7 +310,7 @@ def time_components(S, n, prec, stream, reps, torch, mhd):
     return out
 
 
-def step_launches(S, n, esize, fused, w32, lim=0):
+def step_launches(S, n, esize, fused, w32, lim=0, middle=False):
     """(kernel name, grid threads) of every sweep launch of one step of an
     n^3 grid, in the profiler's naming (the sweep kernels carry the slope
     limiter as their last template argument)"""
@@ -326,6 +329,12 @@ def step_launches(S, n, esize, fused, w32, lim=0):
     my = (f"mag_march_kernel<{t}, 1, {w32}, {lim}>", march(S.chunk(1)))
     fz = (f"fluid_march_kernel<{t}, 2, {w32}, {lim}>", march(S.chunk(2)))
     mz = (f"mag_march_kernel<{t}, 2, {w32}, {lim}>", march(S.chunk(2)))
+    if middle:
+        from paper_1004_1680_amd import mhd
+        return [fx, mx, fy, my, fz,
+                (f"magmagfluid_march_kernel<{t}, 2, {w32}, {lim}>", march(S.launch(mhd.MHD_TUNE_MIDDLE_CHUNK))),
+                (f"magfluid_march_kernel<{t}, 1, {w32}, {lim}>", march(S.pair_chunk(1))),
+                (f"magfluid_x_kernel<{t}, true, {lim}>", xgrid)]
     if fused:
         return [fx, mx, fy, my, fz, mz,
                 (f"magfluid_march_kernel<{t}, 2, {w32}, {lim}>", march(S.pair_chunk(2))),
@@ -584,14 +593,21 @@ def cpu_baseline_closure():
 FAMILIES = {"rho": [0], "m": [1, 2, 3], "e": [4], "b": [5, 6, 7]}
 
 
+def family_l1(diff_sums, ref_sums):
+    """relative L1 of a field family, pooled over its fields: sum |a - ref|
+    / sum |ref| (a small member, such as b_z of the Orszag-Tang state, which
+    starts at zero and grows from roundoff-sized values, does not dominate)"""
+    return float(sum(diff_sums) / sum(ref_sums))
+
+
 def family_errors(a, ref):
-    """per field family: max |a - ref| / max |ref| and the relative L1
-    (mean |a - ref| / mean |ref| averaged over the family's fields)"""
+    """per field family: max |a - ref| / max |ref| and the relative L1"""
     out = {}
     for k, idx in FAMILIES.items():
         den = np.abs(ref[idx]).max()
-        l1 = [float(np.mean(np.abs(a[f] - ref[f])) / max(np.mean(np.abs(ref[f])), 1e-300)) for f in idx]
-        out[k] = {"max_rel": float(np.abs(a[idx] - ref[idx]).max() / den), "l1": float(np.mean(l1))}
+        l1 = family_l1([float(np.abs(a[f] - ref[f]).sum()) for f in idx],
+                       [float(np.abs(ref[f]).sum()) for f in idx])
+        out[k] = {"max_rel": float(np.abs(a[idx] - ref[idx]).max() / den), "l1": l1}
     return out
 
 
@@ -629,7 +645,8 @@ def precision_config2(args, torch, mhd, checkpoints=(1, 10, 50, 100)):
             o = oracle.step(o, dt, vmax)
             t += 2.0 * dt
             k += 1
-        log(f"[precision] config 2 oracle at step {k} ({time.perf_counter() - t0:.0f} s)")
+            if k % 5 == 0:
+                log(f"[precision] config 2 oracle step {k} ({time.perf_counter() - t0:.0f} s)")
         g64, t64 = gpu["f64"][c]
         g32, t32 = gpu["f32"][c]
         rows.append({"step": c, "time_oracle": t, "time_f64": t64, "time_f32": t32,
@@ -676,15 +693,16 @@ def precision_config3(args, torch, mhd, checkpoints=(1, 10, 25, 50)):
         g = S32.get_state_tensor()
         fams = {}
         for fam, idx in FAMILIES.items():
-            mx, den, l1 = 0.0, 0.0, []
+            mx, den, dsum, rsum = 0.0, 0.0, [], []
             for f in idx:
                 r = ref[f].cuda()
                 d = (g[f] - r).abs_()
                 mx = max(mx, float(d.max()))
                 den = max(den, float(r.abs().max()))
-                l1.append(float(d.sum(dtype=torch.float64)) / max(float(r.abs().sum(dtype=torch.float64)), 1e-300))
+                dsum.append(float(d.sum(dtype=torch.float64)))
+                rsum.append(float(r.abs().sum(dtype=torch.float64)))
                 del r, d
-            fams[fam] = {"max_rel": mx / den if den > 0 else mx, "l1": float(np.mean(l1))}
+            fams[fam] = {"max_rel": mx / den if den > 0 else mx, "l1": family_l1(dsum, rsum)}
         del g, ref
         torch.cuda.empty_cache()
         rows.append({"step": c, "time_f64": S64.time(), "time_f32": S32.time(), "f32_vs_f64": fams})
@@ -763,6 +781,8 @@ def run_size_sweep(args, torch, mhd):
         ncell = n ** 3
         log(f"[sweep] n={n} {prec}")
         S = mhd.Solver((n, n, n), prec=prec, stream=stream)
+        if args.middle:
+            S.set_launch(mhd.MHD_TUNE_MIDDLE, args.middle)
         st = make_state_device(dict(n=n, prec=prec, ic="orszag_tang"), torch)
         S.set_state_tensor(st)
         torch.cuda.synchronize()
@@ -842,6 +862,10 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--limiter", default="vanleer", choices=sorted(LIMITERS),
                     help="slope limiter of the operators (the paper's: vanleer)")
+    ap.add_argument("--middle", type=int, default=0, choices=(0, 1, 2),
+                    help="M_z M_z F_z of a step: 1 one launch, 2 M_z and the z pair, 0 built-in")
+    ap.add_argument("--row-group", type=int, default=None, metavar="ROWS",
+                    help="x sweeps: most rows along y in one group of the tile order (0 built-in, ny linear)")
     ap.add_argument("--size-sweep", default=None, metavar="SIZES",
                     help="time a full step at each n^3 (comma list, or 'default': "
                          + ",".join(map(str, SWEEP_SIZES)) + ") with the paper's four criteria")
@@ -879,6 +903,10 @@ def main():
     S = mhd.Solver((n, n, n), prec=wl["prec"], stream=stream)
     lim = LIMITERS[args.limiter]
     S.set_limiter(lim)
+    if args.middle:
+        S.set_launch(mhd.MHD_TUNE_MIDDLE, args.middle)
+    if args.row_group is not None:
+        S.set_launch(mhd.MHD_TUNE_ROW_GROUP, args.row_group)
     st = make_state_device(wl, torch)
     S.set_state_tensor(st)
     del st
@@ -913,6 +941,7 @@ def main():
     saved = S.get_state_tensor()
     kern = {}
     fused = S.reverse() == 1
+    middle = S.launch(mhd.MHD_TUNE_MIDDLE) == 1
     ops = ("fluid", "magnetic", "pair") if fused else ("fluid", "magnetic")
     for op in ops:
         for d in range(3):
@@ -929,6 +958,14 @@ def main():
             ms = time_operator(S, op, d, dt, args.kernel_reps, stream, torch)
             gbs = ALG_WORDS[op] * esize * ncell / (ms * 1e-3) / 1e9
             kern[f"{op}_{'xyz'[d]}"] = {"ms": round(ms, 5), "alg_GBs": round(gbs, 1)}
+    if middle:
+        # M_z M_z F_z in one launch (sweep code 7), run once a step in place of
+        # M_z and the z pair
+        S.set_state_tensor(saved)
+        dt = S.cfl_dt(args.cfl) * 0.25
+        ms = time_operator(S, "middle", 2, dt, args.kernel_reps, stream, torch)
+        kern["middle_z"] = {"ms": round(ms, 5),
+                            "alg_GBs": round(ALG_WORDS["middle"] * esize * ncell / (ms * 1e-3) / 1e9, 1)}
     # CFL (partial + final reduction)
     S.set_state_tensor(saved)
     del saved
@@ -947,8 +984,8 @@ def main():
     energy = energy_window(S, args.cfl, ncell, torch)
     # dominant kernel: largest time per step (with fused reverse pairs every
     # kernel runs once a step, otherwise each operator runs twice)
-    dom = max((k for k in kern if k != "cfl(sync)" and (k != "pair_x" or not fused)),
-              key=lambda k: kern[k]["ms"])
+    skip = {"cfl(sync)"} | ({"pair_x"} if fused else set()) | ({"magnetic_z", "pair_z"} if middle else set())
+    dom = max((k for k in kern if k not in skip), key=lambda k: kern[k]["ms"])
     op = dom.split("_")[0]
     bytes_per_launch = ALG_WORDS[op] * esize * ncell
     achieved = bytes_per_launch / (kern[dom]["ms"] * 1e-3) / 1e9
@@ -960,7 +997,7 @@ def main():
         tpath = os.path.join(ROOT, "profiles", f"sweeps_{args.workload}_hbm_traffic.md")
     from paper_1004_1680_amd.profile_summary import read_traffic
     tmap = read_traffic(tpath)
-    kname = {"fluid": "fluid", "magnetic": "mag", "pair": "magfluid"}[op]
+    kname = {"fluid": "fluid", "magnetic": "mag", "pair": "magfluid", "middle": "magmagfluid"}[op]
     # march kernels carry their addressing (32-bit byte offsets when a field
     # is under 4 GiB) as a third template argument
     w32 = "true" if ncell * esize <= 2 ** 32 else "false"
@@ -980,7 +1017,7 @@ def main():
     step_traffic = None
     if tmap:
         tot = 0
-        for name, grid in step_launches(S, n, esize, fused, w32, lim):
+        for name, grid in step_launches(S, n, esize, fused, w32, lim, middle):
             b = tmap.get(f"{name} @ {grid}", tmap.get(name))
             if b is None:
                 tot = None
@@ -1003,11 +1040,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "grid": [n, n, n], "cfl": args.cfl,
                    "step": ("CFL (FP64) + F_x M_x F_y M_y F_z M_z M_z F_z M_y F_y M_x F_x; "
-                            + ("9 launches: each reverse pair M_d F_d fused, CFL in the last"
+                            + ("8 launches: M_z M_z F_z in one, the reverse pairs M_y F_y, M_x F_x "
+                               "fused, CFL in the last" if middle else
+                               "9 launches: each reverse pair M_d F_d fused, CFL in the last"
                                if fused else "12 launches")),
                    "limiter": args.limiter,
                    "march_chunks": [S.chunk(1), S.chunk(2)],
                    "pair_chunks": [S.pair_chunk(1), S.pair_chunk(2)] if fused else None,
+                   "middle_chunk": S.launch(mhd.MHD_TUNE_MIDDLE_CHUNK) if middle else None,
+                   "x_row_group": S.launch(mhd.MHD_TUNE_ROW_GROUP),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -136,7 +136,9 @@ int mhd_magnetic(mhd_ctx *h, int dim, double dt);
  * dim 3,4,5 = magnetic then fluid along x, y, z.  dim 6 = dim 3 with the
  * CFL maximum of the resulting state found on the way (what the last
  * launch of a step does); the next mhd_step_auto then takes its dt from it
- * instead of a separate reduction.  Asynchronous. */
+ * instead of a separate reduction.  dim 7 = the middle of a step, M_z then
+ * dim 5 (M_z M_z F_z; one launch where MHD_TUNE_MIDDLE chooses it).
+ * Asynchronous. */
 int mhd_sweep(mhd_ctx *h, int dim, double dt);
 
 /* Slope limiter of the second-order parts of both operators, a method
@@ -217,13 +219,29 @@ int mhd_restrict(mhd_ctx *fine, mhd_ctx *coarse);
  * launches), 0 = the built-in choice (1 in FP32 with the van Leer or
  * minmod limiter, 2 otherwise: the fused MC and superbee kernels spill
  * registers); mhd_get_launch reports the resolved 1 or 2.
+ * key MHD_TUNE_MIDDLE: how the middle of a step, M_z M_z F_z (the last
+ * forward operator and the first reverse pair), runs: 1 = one launch (the
+ * second magnetic window takes the first one's new faces and edge
+ * velocities from registers; 8 launches per step), 2 = M_z and the reverse
+ * pair (9), 0 = the built-in choice (1 for grids of 128^3 cells and more,
+ * 2 below); mhd_get_launch reports 1 or 2.  It takes effect in FP32 with
+ * fused reverse pairs and van Leer's limiter only.
+ * MHD_TUNE_MIDDLE_CHUNK: its march chunk along z (rules of the chunks above).
+ * key MHD_TUNE_ROW_GROUP: the x sweeps visit their row tiles in groups of
+ * consecutive rows along y, one group per z in turn, so that the rows z +- 1
+ * a tile reads were read by tiles a few positions earlier on the same XCD;
+ * the value is the most rows in a group (0 = built-in, 64; a value of ny or
+ * more gives the linear y-then-z order).  mhd_get_launch reports the rows of
+ * a group as resolved (ny: linear order, also where the rows of a
+ * workgroup do not divide ny).
  * key MHD_TUNE_WIDE_OFFSETS: 1 makes the y and z sweeps address memory with
  * 64-bit arithmetic per access, as they must for fields over 4 GiB; 0 (the
  * default) uses 32-bit byte offsets wherever they fit.
  * Results do not depend on any of these (the fused pair is bitwise the two
  * operators).  Launch-shape parameters, not part of the method. */
 enum { MHD_TUNE_CHUNK_Y = 1, MHD_TUNE_CHUNK_Z = 2, MHD_TUNE_REVERSE = 3,
-       MHD_TUNE_PAIR_CHUNK_Y = 4, MHD_TUNE_PAIR_CHUNK_Z = 5, MHD_TUNE_WIDE_OFFSETS = 6 };
+       MHD_TUNE_PAIR_CHUNK_Y = 4, MHD_TUNE_PAIR_CHUNK_Z = 5, MHD_TUNE_WIDE_OFFSETS = 6,
+       MHD_TUNE_MIDDLE = 7, MHD_TUNE_MIDDLE_CHUNK = 8, MHD_TUNE_ROW_GROUP = 9 };
 int mhd_set_launch(mhd_ctx *h, int key, int value);
 int mhd_get_launch(const mhd_ctx *h, int key, int *value);
 

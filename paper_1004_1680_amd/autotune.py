@@ -7,7 +7,8 @@ the live state and keeps the fastest; choices are cached in a JSON file
 device, problem and precision.
 
 * single grid: the march chunk length along y and z of the single
-  operators and of the fused reverse-half pairs (the x sweeps hold whole
+  operators and of the fused reverse-half pairs, and along z of the fused
+  middle of a step (M_z M_z F_z) when it is on (the x sweeps hold whole
   rows and have no shape to choose);
 * batched ensemble: the persistent grid of the operator launches, the
   target march chunk and whether the reverse-half pairs run fused (fused
@@ -75,10 +76,15 @@ def tune_solver(S, cfl=0.7, steps=4, repeats=2, use_cache=True):
     timed over `steps` steps, best of `repeats`.  Returns {key: chunk} with
     keys (kind, axis), kind "op" or "pair"."""
     fused = S.reverse() == 1
+    middle = S.launch(mhd.MHD_TUNE_MIDDLE) == 1
     kinds = ("op", "pair") if fused else ("op",)
+    if middle:
+        kinds += ("mid",)
     key = (f"{_device_tag()}:single:{S.n[0]}x{S.n[1]}x{S.n[2]}:"
-           f"{'f64' if S.prec == mhd.MHD_F64 else 'f32'}:{'fused' if fused else 'separate'}")
-    setter = {"op": S.set_chunk, "pair": S.set_pair_chunk}
+           f"{'f64' if S.prec == mhd.MHD_F64 else 'f32'}:{'fused' if fused else 'separate'}"
+           f"{':middle' if middle else ''}")
+    setter = {"op": S.set_chunk, "pair": S.set_pair_chunk,
+              "mid": lambda axis, ch: S.set_launch(mhd.MHD_TUNE_MIDDLE_CHUNK, ch)}
     db = _load()
     if use_cache and key in db:
         best = {(k, int(a)): v for k, av in db[key].items() for a, v in av.items()}
@@ -102,7 +108,7 @@ def tune_solver(S, cfl=0.7, steps=4, repeats=2, use_cache=True):
 
     best = {}
     for kind in kinds:
-        for axis in (1, 2):
+        for axis in ((2,) if kind == "mid" else (1, 2)):
             timings = {}
             for ch in chunk_candidates(S.n[axis]):
                 setter[kind](axis, ch)

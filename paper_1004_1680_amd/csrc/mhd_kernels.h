@@ -40,8 +40,31 @@ struct SweepParams {
 struct LaunchTuning {
     int chunk[3];
     int pair_chunk[3];
+    int triple_chunk[3];     // the same for M_d M_d F_d in one launch
     int wide;                // 1: 64-bit addressing in the marches even where 32-bit offsets fit
+    int row_group;           // x sweeps: most rows (along y) in one group of the tile order (0: built-in)
 };
+
+// rows of one x-sweep workgroup: 4 cells per thread, up to 256 threads
+inline int x_rows_per_wg(int nx)
+{
+    const int r = 256 / (nx / 4);
+    return r < 1 ? 1 : r;
+}
+
+// tiles per group of the x sweeps' visit order (row_tile): the largest
+// divisor st of ny / rows_per_wg with st * rows_per_wg <= max_rows (64 rows
+// when max_rows is 0); 0 (linear order) when rows_per_wg does not divide ny
+inline int row_group_tiles(int ny, int rows_per_wg, int max_rows)
+{
+    if (max_rows <= 0) max_rows = 64;
+    if (ny % rows_per_wg) return 0;
+    const int ty = ny / rows_per_wg;
+    int st = 0;
+    for (int c = 1; c <= ty && c * rows_per_wg <= max_rows; ++c)
+        if (ty % c == 0) st = c;
+    return st;
+}
 
 // ---------------------------------------------------------------------------
 // Batched ensembles: boxes of different sizes in one pair of buffers.  Box b
@@ -116,6 +139,10 @@ hipError_t launch_magnetic(const SweepParams<T>& P, int d, const LaunchTuning& t
 // (d = 0 only) adds the fused CFL epilogue of launch_fluid
 template <typename T>
 hipError_t launch_magfluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s);
+// M_d M_d F_d in one pass along a march axis (the middle of a step, d = 2),
+// bitwise the three operators in turn; van Leer's limiter
+template <typename T>
+hipError_t launch_magmagfluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s);
 
 // CFL: per-block maxima of the signal speed into partial[], then a final
 // reduction writes scal[SCAL_VMAX], scal[SCAL_C] = vmax, scal[SCAL_DT] =

@@ -50,6 +50,26 @@ __device__ __forceinline__ int xcd_tile(int nblocks)
     return (b & 7) * per + (b >> 3);
 }
 
+// Visit order of the row tiles of an x sweep.  A tile holds rows_per_wg
+// consecutive rows along y at one z; tile L covers rows L * rows_per_wg ..
+// of the flattened (z, y) index, ty = ny / rows_per_wg tiles per y line.
+// Visit o goes to groups of st tiles along y, one group per z in turn, so
+// the rows z - 1 and z + 1 that a tile reads belong to tiles st positions
+// before and after it, which the same XCD (consecutive visits share one,
+// see xcd_tile) holds in its L2; in the linear order they are a whole y
+// line of tiles away.  Rows y +- 1 at a group's edge are read twice.  A
+// bijection of [0, ty * nz) when st divides ty; st <= 0 or st >= ty keeps
+// the linear order.
+__device__ __forceinline__ int row_tile(int o, int st, int ty, int nz)
+{
+    if (st <= 0 || st >= ty) return o;
+    const int per_col = st * nz;
+    const int c = o / per_col;
+    const int rem = o - c * per_col;
+    const int z = rem / st;
+    return z * ty + c * st + (rem - z * st);
+}
+
 template <typename T> struct vec4;
 template <> struct vec4<float> {
     static __device__ __forceinline__ void load(const float* p, float o[4])
@@ -384,10 +404,11 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
 }
 
 template <typename T, bool CFL, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
-__global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+__global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg, int st)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    fluid_x_tile<T, CFL, LIM, FRZ>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    const int tile = row_tile(xcd_tile(gridDim.x), st, P.ny / rows_per_wg, P.nz);
+    fluid_x_tile<T, CFL, LIM, FRZ>(P, tile, tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // Magnetic operator along x (e = y then z) of the thread's 4 cells.  For
@@ -560,10 +581,11 @@ __device__ __forceinline__ void mag_x_tile(const SweepParams<T>& P, int tile, in
 }
 
 template <typename T, int LIM = LIM_VANLEER>
-__global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+__global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg, int st)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    mag_x_tile<T, LIM>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    const int tile = row_tile(xcd_tile(gridDim.x), st, P.ny / rows_per_wg, P.nz);
+    mag_x_tile<T, LIM>(P, tile, tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // One tile of rows: the reverse-half pair M_x then F_x in one pass.  The new
@@ -625,10 +647,11 @@ __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int til
 }
 
 template <typename T, bool CFL, int LIM = LIM_VANLEER>
-__global__ void __launch_bounds__(256) magfluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg)
+__global__ void __launch_bounds__(256) magfluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg, int st)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    magfluid_x_tile<T, CFL, LIM>(P, xcd_tile(gridDim.x), tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    const int tile = row_tile(xcd_tile(gridDim.x), st, P.ny / rows_per_wg, P.nz);
+    magfluid_x_tile<T, CFL, LIM>(P, tile, tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -776,17 +799,28 @@ struct MagWindow {
         // velocity pencils of each chain: (chain pencil, chain pencil - e)
         constexpr int vr0[4] = { 0, 2, 0, 4 };
         constexpr int vr1[4] = { 1, 0, 3, 0 };
-        T f[4];
+        T a1[4];
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) {
             const T w0 = face_avg(v[vr0[ch]], v[vr1[ch]]);       // w at L
-            const T a1 = edge_avg(wm[ch], w0);                   // a at L-1
-            const T g1 = upwind_flux1(a1, q1[ch], q0[ch]);      // G1 at L-1
+            a1[ch] = edge_avg(wm[ch], w0);                       // a at L-1
+            wm[ch] = w0;
+        }
+        push_edge(a1, q0, bn0, tau, halftau, nb);
+    }
+
+    // the same with the edge velocity a(L-1) of every chain given (a second
+    // magnetic operator over the same velocity field reuses the first one's)
+    __device__ __forceinline__ void push_edge(const T a1[4], const T q0[4], T bn0, T tau, T halftau, T nb[5])
+    {
+        T f[4];
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const T g1 = upwind_flux1(a1[ch], q1[ch], q0[ch]);  // G1 at L-1
             const T hq1 = sub_scaled(q1[ch], halftau, g1 - gm[ch]);   // qh at L-1
             // edge flux at L-3 from a(L-3) and qh at L-4..L-1
             f[ch] = upwind_flux2<T, LIM>(a3[ch], h4[ch], h3[ch], h2[ch], hq1);
-            wm[ch] = w0;
-            a3[ch] = a2[ch]; a2[ch] = a1;
+            a3[ch] = a2[ch]; a2[ch] = a1[ch];
             gm[ch] = g1;
             h4[ch] = h3[ch]; h3[ch] = h2[ch]; h2[ch] = hq1;
         }
@@ -1267,6 +1301,138 @@ __global__ void __launch_bounds__(256, magfluid_waves<T>()) magfluid_march_kerne
     magfluid_march_lane<T, D, W32, LIM>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
 }
 
+// One lane of a grid: the middle of a step, M_d M_d F_d (the last forward
+// magnetic operator and the first reverse pair), in one pass.  The second
+// magnetic window runs 3 positions behind the first and takes its new faces
+// as inputs (b_t1, b_t2 of pencils P, P+t1, P+t2 and b_n of P: all of what
+// the second operator reads of b, since the plus chains are the neighbour
+// pencils' own chains) and its edge velocities (the velocity field is the
+// same for both); the fluid window runs behind the second as in the reverse
+// pair.  Same device functions in the same order as mag_march_lane twice
+// and fluid_march_lane, so the result is bitwise that of the three
+// operators, with the state read and written once.
+//   first magnetic look-ahead s: its new faces at s-3;
+//   second magnetic look-ahead s-3 (edge velocity a(s-4)): new faces at s-6;
+//   fluid look-ahead s-7: new U at s-10.
+// Fluid outputs j0 .. j0+chunk-1 need second-operator faces at j0-3 ..
+// j0+chunk+3, first-operator faces at j0-6 .. j0+chunk+6 and inputs from
+// j0-9: chunk + 19 positions.
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
+__device__ __forceinline__ void magmagfluid_march_lane(const SweepParams<T>& P, long gid, int chunk)
+{
+    constexpr int N_ = D, T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+    using A = Addr<T, W32>;
+    int p, j0;
+    if (!march_lane_of<D>(P.nx, P.ny, P.nz, gid, chunk, p, j0)) return;
+    const MarchGeom<D> G(P.nx, P.ny, P.nz, p);
+    const int nd = G.nd;
+    const T* __restrict__ in_u[5] = { P.in[RHO], P.in[MX + N_], P.in[MX + T1], P.in[MX + T2], P.in[EN] };
+    T* out_u[5] = { P.out[RHO], P.out[MX + N_], P.out[MX + T1], P.out[MX + T2], P.out[EN] };
+
+    if (P.flag && *P.flag) {
+        for (int j = j0; j < j0 + chunk; ++j) {
+            const unsigned o = G.base + G.sd * j;
+            for (int q = 0; q < NFIELD; ++q) P.out[q][o] = P.in[q][o];
+        }
+        return;
+    }
+    T tau, halftau, c;
+    step_scalars(P, tau, halftau, c);
+    const T gamma = P.gamma;
+    const unsigned step = G.sd * A::scale;
+    const unsigned gb = G.base * A::scale;
+
+    MagWindow<T, LIM> WM1, WM2;
+    WM1.init();
+    WM2.init();
+    FluidWindow<T, LIM> WF;
+    WF.init();
+    const MagLoads<T, D, W32> in(P, G);
+    constexpr int U = magfluid_unroll<T>();
+    constexpr int PF = MARCH_PF;
+    static_assert(U % PF == 0, "the unrolled group cycles through the prefetch buffers");
+    const int total = chunk + 19;
+    const int Sstart = j0 - 9 - ((U - (total % U)) % U);
+    MarchPos pm, pf;
+    pm.set(wrap_pos(Sstart, nd), step);
+    pf.set(wrap_pos(Sstart - 7, nd), step);
+    MagBuf<T> buf[PF];
+    T nu[PF][5];
+    auto load_u = [&](T (&dst)[5]) {
+        const unsigned o = gb + pf.off;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) dst[q] = A::ld(in_u[q], o);
+    };
+    in.load(buf[0], pm.off);
+    load_u(nu[0]);
+#pragma unroll
+    for (int b = 1; b < PF; ++b) {
+        pm.next(nd, step);
+        pf.next(nd, step);
+        in.load(buf[b], pm.off);
+        load_u(nu[b]);
+    }
+    // output offsets of the second magnetic (s - 6) and fluid (s - 10) positions
+    unsigned pmo = gb + (unsigned)(Sstart - 6) * step;
+    unsigned pfo = gb + (unsigned)(Sstart - 10) * step;
+    // edge velocities a(s-4) for the second window: the first window's a(L-3)
+    // as it stood before the previous push
+    T a_prev[4] = { T(0), T(0), T(0), T(0) };
+    // new faces of the second operator at its previous output position
+    T pb_t1o = T(0), pb_t1p = T(0), pb_t2o = T(0), pb_t2p = T(0), pb_n = T(0);
+    for (int S0 = Sstart; S0 <= j0 + chunk + 9; S0 += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int s = S0 + k;
+            T v[5], q0[4], bn0, u0[5];
+            buf[k % PF].take(v, q0, bn0);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) u0[q] = nu[k % PF][q];
+            pm.next(nd, step);
+            pf.next(nd, step);
+            in.load(buf[k % PF], pm.off);
+            load_u(nu[k % PF]);
+
+            T a_cur[4];
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) a_cur[ch] = WM1.a3[ch];     // a(s-3)
+            T nb1[5];
+            WM1.push(v, q0, bn0, tau, halftau, nb1);                 // faces at s-3
+            T nb[5];
+            WM2.push_edge(a_prev, nb1, nb1[4], tau, halftau, nb);     // faces at s-6
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) a_prev[ch] = a_cur[ch];
+            const int jmo = s - 6;
+            if (jmo >= j0 && jmo < j0 + chunk) {
+                A::st(P.out[BX + T1], pmo, nb[0]);
+                A::st(P.out[BX + T2], pmo, nb[2]);
+                A::st(P.out[BX + N_], pmo, nb[4]);
+            }
+            pmo += step;
+            // fluid at s-7: Bbar from the new faces of s-7 (and b_n of s-6)
+            T bb0[3];
+            bb0[0] = T(0.5) * (pb_n + nb[4]);
+            bb0[1] = T(0.5) * (pb_t1o + pb_t1p);
+            bb0[2] = T(0.5) * (pb_t2o + pb_t2p);
+            pb_t1o = nb[0]; pb_t1p = nb[1]; pb_t2o = nb[2]; pb_t2p = nb[3]; pb_n = nb[4];
+            T unew[5];
+            WF.push(u0, bb0, gamma, c, c, tau, halftau, unew);
+            if (s - 10 >= j0) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) A::st(out_u[q], pfo, unew[q]);
+            }
+            pfo += step;
+        }
+    }
+}
+
+// three register windows: one wave per SIMD (up to 512 registers, no spills)
+template <typename T, int D, bool W32, int LIM = LIM_VANLEER>
+__global__ void __launch_bounds__(256, 1) magmagfluid_march_kernel(SweepParams<T> P, int chunk)
+{
+    magmagfluid_march_lane<T, D, W32, LIM>(P, (long)xcd_tile(gridDim.x) * blockDim.x + threadIdx.x, chunk);
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
@@ -1275,8 +1441,7 @@ template <typename T>
 inline void row_shape(int nx, int& tpr, int& rows_per_wg, int& threads)
 {
     tpr = nx / 4;
-    rows_per_wg = 256 / tpr;
-    if (rows_per_wg < 1) rows_per_wg = 1;
+    rows_per_wg = x_rows_per_wg(nx);
     threads = rows_per_wg * tpr;
 }
 
@@ -1307,9 +1472,11 @@ hipError_t launch_fluid_lim(const SweepParams<T>& P, int d, const LaunchTuning& 
         const size_t lds = sizeof(T) * 25 * threads;
         if (P.cfl_acc) {
             if (threads % 64) return hipErrorInvalidValue;      // fused CFL needs full waves
-            hipLaunchKernelGGL((fluid_x_kernel<T, true, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((fluid_x_kernel<T, true, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
+                               row_group_tiles(P.ny, rpw, tune.row_group));
         } else {
-            hipLaunchKernelGGL((fluid_x_kernel<T, false, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((fluid_x_kernel<T, false, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
+                               row_group_tiles(P.ny, rpw, tune.row_group));
         }
     } else {
         const int nd = d == 1 ? P.ny : P.nz;
@@ -1340,7 +1507,8 @@ hipError_t launch_magnetic_lim(const SweepParams<T>& P, int d, const LaunchTunin
         const int nrows = P.ny * P.nz;
         const int grid = (nrows + rpw - 1) / rpw;
         const size_t lds = sizeof(T) * 16 * threads;
-        hipLaunchKernelGGL((mag_x_kernel<T, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+        hipLaunchKernelGGL((mag_x_kernel<T, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
+                           row_group_tiles(P.ny, rpw, tune.row_group));
     } else {
         const int nd = d == 1 ? P.ny : P.nz;
         const int npencil = P.nx * (d == 1 ? P.nz : P.ny);
@@ -1404,9 +1572,11 @@ hipError_t launch_magfluid_lim(const SweepParams<T>& P, int d, const LaunchTunin
         const size_t lds = sizeof(T) * 25 * threads;
         if (P.cfl_acc) {
             if (threads % 64) return hipErrorInvalidValue;      // fused CFL needs full waves
-            hipLaunchKernelGGL((magfluid_x_kernel<T, true, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((magfluid_x_kernel<T, true, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
+                               row_group_tiles(P.ny, rpw, tune.row_group));
         } else {
-            hipLaunchKernelGGL((magfluid_x_kernel<T, false, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw);
+            hipLaunchKernelGGL((magfluid_x_kernel<T, false, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
+                               row_group_tiles(P.ny, rpw, tune.row_group));
         }
     } else {
         if (P.cfl_acc) return hipErrorInvalidValue;
@@ -1437,6 +1607,27 @@ hipError_t launch_magfluid(const SweepParams<T>& P, int d, const LaunchTuning& t
     case LIM_SUPERBEE: return launch_magfluid_lim<T, LIM_SUPERBEE>(P, d, tune, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+// M_d M_d F_d in one launch (march axes; van Leer's limiter)
+template <typename T>
+hipError_t launch_magmagfluid(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
+{
+    if (d == 0 || P.cfl_acc || P.limiter != LIM_VANLEER) return hipErrorInvalidValue;
+    const int nd = d == 1 ? P.ny : P.nz;
+    const int npencil = P.nx * (d == 1 ? P.nz : P.ny);
+    int chunk = tune.triple_chunk[d];
+    if (chunk <= 0 || nd % chunk) chunk = nd;
+    const long lanes = (long)npencil * (nd / chunk);
+    const int grid = (int)((lanes + 255) / 256);
+    if (offsets32<T>(P, tune)) {
+        if (d == 1) hipLaunchKernelGGL((magmagfluid_march_kernel<T, 1, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+        else hipLaunchKernelGGL((magmagfluid_march_kernel<T, 2, true>), dim3(grid), dim3(256), 0, s, P, chunk);
+    } else {
+        if (d == 1) hipLaunchKernelGGL((magmagfluid_march_kernel<T, 1, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+        else hipLaunchKernelGGL((magmagfluid_march_kernel<T, 2, false>), dim3(grid), dim3(256), 0, s, P, chunk);
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

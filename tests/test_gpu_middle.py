@@ -1,0 +1,125 @@
+"""The middle of a step, M_z M_z F_z (the last forward operator and the first
+reverse pair of the x, y, z, z, y, x order of section II.B), in one launch:
+the second magnetic window takes the first one's new faces and edge
+velocities from registers, the fluid window the second one's faces.  It
+evaluates the same device functions in the same order as the three
+operators, so steps with it equal steps without it bit for bit: on ragged
+grids, with z pencils down to the minimum length 8 (shorter than the
+19-position warm-up), for several march chunks, and against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import max_family_err
+from paper_1004_1680_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+ONE, TWO = 1, 2
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1004_1680_amd import mhd
+    mhd.load()
+    return mhd
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def steps(M, s, n, mode, nsteps, chunk=0):
+    S = M.Solver(n, prec="f32")
+    S.set_launch(M.MHD_TUNE_MIDDLE, mode)
+    assert S.launch(M.MHD_TUNE_MIDDLE) == mode
+    if chunk:
+        S.set_launch(M.MHD_TUNE_MIDDLE_CHUNK, chunk)
+        assert S.launch(M.MHD_TUNE_MIDDLE_CHUNK) == chunk
+    S.set_state(s)
+    for _ in range(nsteps):
+        S.step_auto(0.7)
+    assert S.status() == nsteps
+    out = S.get_state(), S.time()
+    S.close()
+    return out
+
+
+@pytest.mark.parametrize("n", [(40, 24, 16), (16, 48, 20), (8, 8, 8), (12, 8, 36), (32, 32, 32), (512, 8, 12)])
+def test_middle_in_one_launch_is_the_three_operators(M, n):
+    say(f"case: fused middle n={n}")
+    # the box is n * (1 / nx) long: on the 512-wide grid the y and z extents
+    # are 64 and 43 times shorter, so the field's amplitude is cut to keep
+    # the curl of the potential (and the state) in the physical range
+    s = I.random_smooth(n, seed=41, amp_b=0.15 if n[0] < 512 else 0.002)
+    a, ta = steps(M, s, n, ONE, 3)
+    b, tb = steps(M, s, n, TWO, 3)
+    assert np.array_equal(a, b) and ta == tb
+
+
+def test_middle_chunking(M):
+    n = (24, 16, 48)
+    say(f"case: fused middle chunks {n}")
+    s = I.random_smooth(n, seed=42)
+    ref, _ = steps(M, s, n, TWO, 2)
+    for ch in (8, 16, 24, 48):
+        out, _ = steps(M, s, n, ONE, 2, chunk=ch)
+        assert np.array_equal(out, ref), ch
+
+
+def test_middle_steps_match_the_oracle(M):
+    n = (40, 24, 16)
+    say(f"case: fused middle vs oracle {n}")
+    s = I.random_smooth(n, seed=43).astype(np.float32).astype(np.float64)
+    g, t = steps(M, s, n, ONE, 3)
+    o, to, _ = oracle.run(s, 3)
+    err = max_family_err(g, o)
+    say("err", err)
+    assert err <= 3e-5
+    assert t == pytest.approx(to, rel=1e-6)
+
+
+def test_middle_keeps_a_nonphysical_state(M):
+    n = (32, 32, 32)
+    say("case: fused middle skip path")
+    s = I.random_smooth(n, seed=6)
+    s[4, 3, 5, 7] = -1.0
+    S = M.Solver(n, prec="f32")
+    S.set_launch(M.MHD_TUNE_MIDDLE, ONE)
+    S.set_state(s)
+    before = S.get_state()
+    S.step_auto(0.7)
+    with pytest.raises(M.NonPhysicalState):
+        S.status()
+    assert np.array_equal(S.get_state(), before)
+    S.close()
+
+
+def test_middle_key_rules(M):
+    S = M.Solver((16, 16, 16), prec="f32")
+    assert S.launch(M.MHD_TUNE_MIDDLE) == TWO           # built-in: off below 128^3 cells
+    S.set_launch(M.MHD_TUNE_MIDDLE, ONE)
+    assert S.launch(M.MHD_TUNE_MIDDLE) == ONE
+    S.set_reverse(2)                                     # needs the fused reverse pairs
+    assert S.launch(M.MHD_TUNE_MIDDLE) == TWO
+    S.set_reverse(0)
+    S.set_limiter(M.MHD_LIMITER_MINMOD)                  # and van Leer's limiter
+    assert S.launch(M.MHD_TUNE_MIDDLE) == TWO
+    S.set_limiter(M.MHD_LIMITER_VANLEER)
+    with pytest.raises(M.MHDError):
+        S.set_launch(M.MHD_TUNE_MIDDLE, 3)
+    with pytest.raises(M.MHDError):
+        S.set_launch(M.MHD_TUNE_MIDDLE_CHUNK, 12)
+    S.close()
+    S = M.Solver((16, 16, 16), prec="f64")
+    S.set_launch(M.MHD_TUNE_MIDDLE, ONE)
+    assert S.launch(M.MHD_TUNE_MIDDLE) == TWO           # FP32 only
+    S.close()
+    S = M.Solver((128, 128, 128), prec="f32")
+    assert S.launch(M.MHD_TUNE_MIDDLE) == ONE           # built-in: on from 128^3 cells
+    S.set_launch(M.MHD_TUNE_MIDDLE, TWO)
+    assert S.launch(M.MHD_TUNE_MIDDLE) == TWO
+    S.close()

@@ -470,7 +470,7 @@ def test_invalid_arguments(M):
         with pytest.raises(M.MHDError):
             S.step(bad)
     with pytest.raises(M.MHDError):
-        S.sweep(7, 0.01)
+        S.sweep(8, 0.01)
     with pytest.raises(M.MHDError):
         S.fluid(3, 0.01)
     with pytest.raises(M.MHDError):
