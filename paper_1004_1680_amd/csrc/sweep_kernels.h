@@ -303,16 +303,61 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
             for (int o = 32; o > 0; o >>= 1) wlb = fmaxf(wlb, __shfl_xor(wlb, o, 64));
             thr = fmax(tslot, (double)wlb);
         }
-        if (R.active)
+        if constexpr (sizeof(T) == 4) {
+            // the cells to evaluate are packed over the wave through LDS
+            // (region A, free since the last barrier; 64 x 11 values per
+            // wave) and evaluated 64 at a time, one per lane: the few cells
+            // near a wave's maximum usually sit in one lane (4 consecutive
+            // cells), whose 4 evaluations would otherwise run one after
+            // the other with the rest of the wave idle
+            const int lane = threadIdx.x & 63;
+            const unsigned long long below = (1ull << lane) - 1ull;
+            bool nd[4];
+            int idx[4];
+            int total = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                bool need = true;
-                if constexpr (sizeof(T) == 4) need = !sure[k] || (double)ub[k] >= thr;
-                if (need)
-                    signal_speed64((double)onew[k][0], (double)onew[k][1], (double)onew[k][2], (double)onew[k][3],
-                                   (double)onew[k][4], (double)fb[k][0], (double)fb[k][1], (double)fb[k][2],
-                                   (double)fb[k][3], (double)fb[k][4], (double)fb[k][5], P.gamma64, vmax, bad);
+                nd[k] = R.active && (!sure[k] || (double)ub[k] >= thr);
+                const unsigned long long bal = __ballot(nd[k]);
+                idx[k] = total + __popcll(bal & below);
+                total += __popcll(bal);
             }
+            float* const E = reinterpret_cast<float*>(A) + (threadIdx.x >> 6) * (64 * 11);
+            for (int r = 0; r < total; r += 64) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (nd[k] && idx[k] >= r && idx[k] < r + 64) {
+                        const int e = idx[k] - r;
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) E[q * 64 + e] = onew[k][q];
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) E[(5 + q) * 64 + e] = fb[k][q];
+                    }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane < total - r) {
+                    float c[11];
+#pragma unroll
+                    for (int q = 0; q < 11; ++q) c[q] = E[q * 64 + lane];
+                    signal_speed64((double)c[0], (double)c[1], (double)c[2], (double)c[3], (double)c[4],
+                                   (double)c[5], (double)c[6], (double)c[7], (double)c[8], (double)c[9],
+                                   (double)c[10], P.gamma64, vmax, bad);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            // a persistent caller's next tile writes region A before its
+            // first barrier
+            __syncthreads();
+        } else if (R.active) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                signal_speed64((double)onew[k][0], (double)onew[k][1], (double)onew[k][2], (double)onew[k][3],
+                               (double)onew[k][4], (double)fb[k][0], (double)fb[k][1], (double)fb[k][2],
+                               (double)fb[k][3], (double)fb[k][4], (double)fb[k][5], P.gamma64, vmax, bad);
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
