@@ -3,7 +3,7 @@ states, the launch configuration bench.py times), on sampled outputs.
 
 One step of the whole grid runs on the GPU.  The FP64 oracle cannot step a
 1024^3 grid in test time, but one step only reaches 16 cells along any axis:
-the oracle steps periodic 40^3 windows cut from the same float-rounded
+the oracle steps 32 periodic 40^3 windows cut from the same float-rounded
 initial state with the GPU's dt and relaxation speed (dt scaled by n / 40,
 since the scheme's grid spacing is 1 / nx), and the 8^3 interior of each
 window must equal the full-grid result (checked exactly for the oracle
@@ -63,8 +63,16 @@ def test_full_size_sampled_parity(n, prec):
     d1 = S.diag()
     u1 = S.get_state_tensor()
     say("dt", dt, "c", c)
+    # fixed windows (periodic wraps on every axis), windows across the
+    # launch-shape seams (64-row groups of the x sweeps' tile order; march
+    # chunk boundaries at multiples of 64 along y and z) and seeded random
+    # ones: 32 windows, 16384 sampled cells
     centers = [(n // 2, n // 3, n // 5), (0, 0, 0), (n - 3, 7, n // 2), (n // 4, n - 1, 3),
-               (5 * n // 8, 3 * n // 4, n - 9), (n // 7, n // 2, 2 * n // 3)]
+               (5 * n // 8, 3 * n // 4, n - 9), (n // 7, n // 2, 2 * n // 3),
+               (n // 3, 64, n // 2), (n // 5, 127, 3 * n // 4), (2 * n // 3, n // 2, 256 % n),
+               (n - 1, 191, 255 % n), (17, 320 % n, 64), (n // 2, n // 2 + 1, 128)]
+    rng = np.random.default_rng(2024)
+    centers += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(20)]
     err = np.zeros(4)
     scale = np.zeros(4)
     for ctr in centers:
