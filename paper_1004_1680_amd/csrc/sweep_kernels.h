@@ -21,6 +21,7 @@
 // land on the same XCD (the hardware deals workgroups round-robin over the
 // 8 XCDs, each with its own L2).
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -113,6 +114,29 @@ __device__ __forceinline__ void step_scalars(const SweepParams<T>& P, T& tau, T&
 // values of T (fluid, and the fused magnetic-fluid pair) or 16 * blockDim
 // (magnetic).
 
+// Element offsets of the row kernels.  W32: every field of the grid fits in
+// 4 GiB, offsets are 32-bit and an access is the field's (uniform) base
+// plus one 32-bit byte offset per lane; otherwise 64-bit element offsets.
+template <typename T, bool W32>
+struct RowAddr {
+    using off = std::conditional_t<W32, unsigned, size_t>;
+    static __device__ __forceinline__ const T* at(const T* p, off e)
+    {
+        if constexpr (W32) return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + e * (unsigned)sizeof(T));
+        else return p + e;
+    }
+    static __device__ __forceinline__ T* at(T* p, off e)
+    {
+        if constexpr (W32) return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + e * (unsigned)sizeof(T));
+        else return p + e;
+    }
+    // offset of row (y, z)
+    static __device__ __forceinline__ off row(int nx, int ny, int y, int z)
+    {
+        return (off)nx * ((off)y + (off)ny * (off)z);
+    }
+};
+
 // Row geometry of one thread: row of the grid, position in it, neighbours
 // in the row (for the LDS exchanges).  Idle threads (rloc >= rows_per_wg)
 // exchange with themselves, so every LDS index stays below blockDim.x.
@@ -177,8 +201,9 @@ __device__ __forceinline__ void row_stage_speeds(const T (&w)[4][5], const T (&b
 // CFL = true: the FP64 signal speed of every output cell, maximum per wave,
 // atomic maximum into P.cfl_acc; needs full waves (blockDim.x a multiple of
 // 64).
-template <typename T, bool CFL, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
-__device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowThread& R, size_t base,
+template <typename T, bool CFL, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP, bool W32 = false>
+__device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowThread& R,
+                                             typename RowAddr<T, W32>::off base,
                                              const T (&u)[4][5], const T (&bb)[4][3],
                                              const T (&fb)[CFL ? 4 : 1][6], T* const A)
 {
@@ -266,7 +291,7 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
             T o[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) o[k] = sub_scaled(u[k][q], tau, phi[k][q] - (k > 0 ? phi[k - 1][q] : phiprev));
-            vec4<T>::store(P.out[q] + base + R.i0, o);
+            vec4<T>::store(RowAddr<T, W32>::at(P.out[q], base + R.i0), o);
             if constexpr (CFL)
 #pragma unroll
                 for (int k = 0; k < 4; ++k) onew[k][q] = o[k];
@@ -373,13 +398,14 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
 }
 
 // U of the thread's 4 cells (inactive threads: rho = 1, a harmless state)
-template <typename T>
-__device__ __forceinline__ void load_u4(const SweepParams<T>& P, const RowThread& R, size_t base, T (&u)[4][5])
+template <typename T, bool W32 = false>
+__device__ __forceinline__ void load_u4(const SweepParams<T>& P, const RowThread& R,
+                                        typename RowAddr<T, W32>::off base, T (&u)[4][5])
 {
     T tmp[4];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        if (R.active) vec4<T>::load(P.in[q] + base + R.i0, tmp);
+        if (R.active) vec4<T>::load(RowAddr<T, W32>::at(P.in[q], base + R.i0), tmp);
         else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) u[k][q] = tmp[k];
@@ -387,24 +413,26 @@ __device__ __forceinline__ void load_u4(const SweepParams<T>& P, const RowThread
 }
 
 // One tile of rows_per_wg rows of one grid: fluid operator F_x.
-template <typename T, bool CFL = false, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
+template <typename T, bool CFL = false, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP, bool W32 = false>
 __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
                                              int rows_per_wg, T* const A)
 {
+    using RA = RowAddr<T, W32>;
+    using off = typename RA::off;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const RowThread R(tile, tpr, rows_per_wg, ny, nz);
     const int y = R.y, z = R.z, i0 = R.i0;
     const bool active = R.active;
-    const size_t base = (size_t)nx * ((size_t)y + (size_t)ny * z);
-    const size_t base_yp = (size_t)nx * ((size_t)(y + 1 == ny ? 0 : y + 1) + (size_t)ny * z);
-    const size_t base_zp = (size_t)nx * ((size_t)y + (size_t)ny * (z + 1 == nz ? 0 : z + 1));
+    const off base = RA::row(nx, ny, y, z);
+    const off base_yp = RA::row(nx, ny, y + 1 == ny ? 0 : y + 1, z);
+    const off base_zp = RA::row(nx, ny, y, z + 1 == nz ? 0 : z + 1);
 
     if (P.flag && *P.flag) {      // non-physical state recorded: keep the state
         if (active)
             for (int f = 0; f < 5; ++f) {
                 T v[4];
-                vec4<T>::load(P.in[f] + base + i0, v);
-                vec4<T>::store(P.out[f] + base + i0, v);
+                vec4<T>::load(RA::at(P.in[f], base + i0), v);
+                vec4<T>::store(RA::at(P.out[f], base + i0), v);
             }
         // the record (1 non-physical, 2 zero signal speed) carries over to
         // the CFL that follows, as the separate reduction would find it
@@ -415,14 +443,14 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
 
     T u[4][5], bb[4][3];
     T fb[CFL ? 4 : 1][6];         // fused CFL: raw face values (own, next) of b_x, b_y, b_z
-    load_u4(P, R, base, u);
+    load_u4<T, W32>(P, R, base, u);
     {
         T tmp[4], tmp2[4];
         // Bbar_x: faces i and i+1 along the row
         T bxn = T(0);
         if (active) {
-            vec4<T>::load(P.in[BX] + base + i0, tmp);
-            bxn = P.in[BX][base + (i0 + 4 == nx ? 0 : i0 + 4)];
+            vec4<T>::load(RA::at(P.in[BX], base + i0), tmp);
+            bxn = *RA::at(P.in[BX], base + (i0 + 4 == nx ? 0 : i0 + 4));
         } else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) bb[k][0] = T(0.5) * (tmp[k] + (k < 3 ? tmp[k + 1] : bxn));
@@ -430,14 +458,14 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
 #pragma unroll
             for (int k = 0; k < 4; ++k) { fb[k][0] = tmp[k]; fb[k][1] = k < 3 ? tmp[k + 1] : bxn; }
         // Bbar_y: faces at y and y+1; Bbar_z: faces at z and z+1
-        if (active) { vec4<T>::load(P.in[BY] + base + i0, tmp); vec4<T>::load(P.in[BY] + base_yp + i0, tmp2); }
+        if (active) { vec4<T>::load(RA::at(P.in[BY], base + i0), tmp); vec4<T>::load(RA::at(P.in[BY], base_yp + i0), tmp2); }
         else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) bb[k][1] = T(0.5) * (tmp[k] + tmp2[k]);
         if constexpr (CFL)
 #pragma unroll
             for (int k = 0; k < 4; ++k) { fb[k][2] = tmp[k]; fb[k][3] = tmp2[k]; }
-        if (active) { vec4<T>::load(P.in[BZ] + base + i0, tmp); vec4<T>::load(P.in[BZ] + base_zp + i0, tmp2); }
+        if (active) { vec4<T>::load(RA::at(P.in[BZ], base + i0), tmp); vec4<T>::load(RA::at(P.in[BZ], base_zp + i0), tmp2); }
         else tmp[0] = tmp[1] = tmp[2] = tmp[3] = tmp2[0] = tmp2[1] = tmp2[2] = tmp2[3] = T(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) bb[k][2] = T(0.5) * (tmp[k] + tmp2[k]);
@@ -445,15 +473,15 @@ __device__ __forceinline__ void fluid_x_tile(const SweepParams<T>& P, int tile, 
 #pragma unroll
             for (int k = 0; k < 4; ++k) { fb[k][4] = tmp[k]; fb[k][5] = tmp2[k]; }
     }
-    fluid_x_core<T, CFL, LIM, FRZ>(P, R, base, u, bb, fb, A);
+    fluid_x_core<T, CFL, LIM, FRZ, W32>(P, R, base, u, bb, fb, A);
 }
 
-template <typename T, bool CFL, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP>
+template <typename T, bool CFL, int LIM = LIM_VANLEER, int FRZ = FRZ_STEP, bool W32 = false>
 __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg, int st)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tile = row_tile(xcd_tile(gridDim.x), st, P.ny / rows_per_wg, P.nz);
-    fluid_x_tile<T, CFL, LIM, FRZ>(P, tile, tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    fluid_x_tile<T, CFL, LIM, FRZ, W32>(P, tile, tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // Magnetic operator along x (e = y then z) of the thread's 4 cells.  For
@@ -464,21 +492,22 @@ __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr,
 // Gives the new faces nb = (b_y of P, b_y of P+y, b_z of P, b_z of P+z, b_x
 // of P) of the 4 cells; stores nothing.  A: LDS of 16 values per thread.
 // Every thread of the workgroup calls it (it holds barriers).
-template <typename T, int LIM = LIM_VANLEER>
+template <typename T, int LIM = LIM_VANLEER, bool W32 = false>
 __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThread& R, T (&nb)[5][4],
                                            T* const A)
 {
+    using RA = RowAddr<T, W32>;
+    using off = typename RA::off;
     T* const B = A + 12 * blockDim.x;                       // A: 12, B: 4 values / thread
     const int nt = blockDim.x;
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int t = R.t, tprev = R.tprev, tnext = R.tnext, i0 = R.i0, y = R.y, z = R.z;
     const bool active = R.active;
     const int inext = (i0 + 4 == nx) ? 0 : i0 + 4;
-    auto rbase = [&](int yy, int zz) -> size_t {
-        yy = wrapi(yy, ny); zz = wrapi(zz, nz);
-        return (size_t)nx * ((size_t)yy + (size_t)ny * zz);
+    auto rbase = [&](int yy, int zz) -> off {
+        return RA::row(nx, ny, wrapi(yy, ny), wrapi(zz, nz));
     };
-    const size_t b0 = rbase(y, z);
+    const off b0 = rbase(y, z);
     T tau, halftau, cdummy;
     step_scalars(P, tau, halftau, cdummy);
 
@@ -486,16 +515,16 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
     // rows index: 0 P, 1 P-y, 2 P+y, 3 P-z, 4 P+z
     T v[5][5];
     {
-        const size_t rb[5] = { b0, rbase(y - 1, z), rbase(y + 1, z), rbase(y, z - 1), rbase(y, z + 1) };
+        const off rb[5] = { b0, rbase(y - 1, z), rbase(y + 1, z), rbase(y, z - 1), rbase(y, z + 1) };
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
             T rho[4], m[4];
             T rhon = T(1), mn = T(0);
             if (active) {
-                vec4<T>::load(P.in[RHO] + rb[r] + i0, rho);
-                vec4<T>::load(P.in[MX] + rb[r] + i0, m);
-                rhon = P.in[RHO][rb[r] + inext];
-                mn = P.in[MX][rb[r] + inext];
+                vec4<T>::load(RA::at(P.in[RHO], rb[r] + i0), rho);
+                vec4<T>::load(RA::at(P.in[MX], rb[r] + i0), m);
+                rhon = *RA::at(P.in[RHO], rb[r] + inext);
+                mn = *RA::at(P.in[MX], rb[r] + inext);
             } else {
                 rho[0] = rho[1] = rho[2] = rho[3] = T(1);
                 m[0] = m[1] = m[2] = m[3] = T(0);
@@ -511,14 +540,14 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
     const int vr1[4] = { 1, 0, 3, 0 };
     T q[4][5];
     {
-        const size_t qb[4] = { b0, rbase(y + 1, z), b0, rbase(y, z + 1) };
+        const off qb[4] = { b0, rbase(y + 1, z), b0, rbase(y, z + 1) };
         const int qf[4] = { BY, BY, BZ, BZ };
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) {
             T tmp[4];
             if (active) {
-                vec4<T>::load(P.in[qf[ch]] + qb[ch] + i0, tmp);
-                q[ch][4] = P.in[qf[ch]][qb[ch] + inext];
+                vec4<T>::load(RA::at(P.in[qf[ch]], qb[ch] + i0), tmp);
+                q[ch][4] = *RA::at(P.in[qf[ch]], qb[ch] + inext);
             } else {
                 tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(0);
                 q[ch][4] = T(0);
@@ -582,7 +611,7 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) fprev[ch] = B[ch * nt + tprev];
     T bx[4];
-    if (active) vec4<T>::load(P.in[BX] + b0 + i0, bx);
+    if (active) vec4<T>::load(RA::at(P.in[BX], b0 + i0), bx);
     else bx[0] = bx[1] = bx[2] = bx[3] = T(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -601,36 +630,37 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
 }
 
 // One tile of rows_per_wg rows of one grid: magnetic operator M_x.
-template <typename T, int LIM = LIM_VANLEER>
+template <typename T, int LIM = LIM_VANLEER, bool W32 = false>
 __device__ __forceinline__ void mag_x_tile(const SweepParams<T>& P, int tile, int tpr,
                                            int rows_per_wg, T* const A)
 {
+    using RA = RowAddr<T, W32>;
     const int nx = P.nx, ny = P.ny;
     const RowThread R(tile, tpr, rows_per_wg, ny, P.nz);
-    const size_t b0 = (size_t)nx * ((size_t)R.y + (size_t)ny * R.z);
+    const typename RA::off b0 = RA::row(nx, ny, R.y, R.z);
     if (P.flag && *P.flag) {
         if (R.active)
             for (int f = BX; f <= BZ; ++f) {
                 T v[4];
-                vec4<T>::load(P.in[f] + b0 + R.i0, v);
-                vec4<T>::store(P.out[f] + b0 + R.i0, v);
+                vec4<T>::load(RA::at(P.in[f], b0 + R.i0), v);
+                vec4<T>::store(RA::at(P.out[f], b0 + R.i0), v);
             }
         return;
     }
     T nb[5][4];
-    mag_x_core<T, LIM>(P, R, nb, A);
+    mag_x_core<T, LIM, W32>(P, R, nb, A);
     if (!R.active) return;
-    vec4<T>::store(P.out[BY] + b0 + R.i0, nb[0]);
-    vec4<T>::store(P.out[BZ] + b0 + R.i0, nb[2]);
-    vec4<T>::store(P.out[BX] + b0 + R.i0, nb[4]);
+    vec4<T>::store(RA::at(P.out[BY], b0 + R.i0), nb[0]);
+    vec4<T>::store(RA::at(P.out[BZ], b0 + R.i0), nb[2]);
+    vec4<T>::store(RA::at(P.out[BX], b0 + R.i0), nb[4]);
 }
 
-template <typename T, int LIM = LIM_VANLEER>
+template <typename T, int LIM = LIM_VANLEER, bool W32 = false>
 __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg, int st)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tile = row_tile(xcd_tile(gridDim.x), st, P.ny / rows_per_wg, P.nz);
-    mag_x_tile<T, LIM>(P, tile, tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    mag_x_tile<T, LIM, W32>(P, tile, tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // One tile of rows: the reverse-half pair M_x then F_x in one pass.  The new
@@ -641,19 +671,20 @@ __global__ void __launch_bounds__(256) mag_x_kernel(SweepParams<T> P, int tpr, i
 // of 25 values per thread (the magnetic part uses the first 16; the b_x
 // exchange uses values 20..21, which the fluid part first writes after a
 // barrier that follows its last read).
-template <typename T, bool CFL = false, int LIM = LIM_VANLEER>
+template <typename T, bool CFL = false, int LIM = LIM_VANLEER, bool W32 = false>
 __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int tile, int tpr,
                                                 int rows_per_wg, T* const A)
 {
+    using RA = RowAddr<T, W32>;
     const int nx = P.nx, ny = P.ny;
     const RowThread R(tile, tpr, rows_per_wg, ny, P.nz);
-    const size_t base = (size_t)nx * ((size_t)R.y + (size_t)ny * R.z);
+    const typename RA::off base = RA::row(nx, ny, R.y, R.z);
     if (P.flag && *P.flag) {
         if (R.active)
             for (int f = 0; f < NFIELD; ++f) {
                 T v[4];
-                vec4<T>::load(P.in[f] + base + R.i0, v);
-                vec4<T>::store(P.out[f] + base + R.i0, v);
+                vec4<T>::load(RA::at(P.in[f], base + R.i0), v);
+                vec4<T>::store(RA::at(P.out[f], base + R.i0), v);
             }
         // the record (1 non-physical, 2 zero signal speed) carries over to
         // the CFL that follows, as the separate reduction would find it
@@ -662,16 +693,16 @@ __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int til
         return;
     }
     T nb[5][4];
-    mag_x_core<T, LIM>(P, R, nb, A);
+    mag_x_core<T, LIM, W32>(P, R, nb, A);
     // new b_x of the first cell -> previous thread
     T* const X = A + 20 * blockDim.x;
     X[R.t] = nb[4][0];
     __syncthreads();
     const T bxn = X[R.tnext];
     if (R.active) {
-        vec4<T>::store(P.out[BY] + base + R.i0, nb[0]);
-        vec4<T>::store(P.out[BZ] + base + R.i0, nb[2]);
-        vec4<T>::store(P.out[BX] + base + R.i0, nb[4]);
+        vec4<T>::store(RA::at(P.out[BY], base + R.i0), nb[0]);
+        vec4<T>::store(RA::at(P.out[BZ], base + R.i0), nb[2]);
+        vec4<T>::store(RA::at(P.out[BX], base + R.i0), nb[4]);
     }
     T u[4][5], bb[4][3];
     T fb[CFL ? 4 : 1][6];
@@ -687,16 +718,16 @@ __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int til
             fb[k][4] = nb[2][k]; fb[k][5] = nb[3][k];
         }
     }
-    load_u4(P, R, base, u);
-    fluid_x_core<T, CFL, LIM>(P, R, base, u, bb, fb, A);
+    load_u4<T, W32>(P, R, base, u);
+    fluid_x_core<T, CFL, LIM, FRZ_STEP, W32>(P, R, base, u, bb, fb, A);
 }
 
-template <typename T, bool CFL, int LIM = LIM_VANLEER>
+template <typename T, bool CFL, int LIM = LIM_VANLEER, bool W32 = false>
 __global__ void __launch_bounds__(256) magfluid_x_kernel(SweepParams<T> P, int tpr, int rows_per_wg, int st)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int tile = row_tile(xcd_tile(gridDim.x), st, P.ny / rows_per_wg, P.nz);
-    magfluid_x_tile<T, CFL, LIM>(P, tile, tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
+    magfluid_x_tile<T, CFL, LIM, W32>(P, tile, tpr, rows_per_wg, reinterpret_cast<T*>(smem_raw));
 }
 
 // ---------------------------------------------------------------------------
@@ -1506,6 +1537,7 @@ inline bool offsets32(const SweepParams<T>& P, const LaunchTuning& tune)
     return !tune.wide && (unsigned long long)P.nx * P.ny * P.nz * sizeof(T) <= (1ull << 32);
 }
 
+
 template <typename T, int LIM, int FRZ = FRZ_STEP>
 hipError_t launch_fluid_lim(const SweepParams<T>& P, int d, const LaunchTuning& tune, hipStream_t s)
 {
@@ -1515,13 +1547,21 @@ hipError_t launch_fluid_lim(const SweepParams<T>& P, int d, const LaunchTuning& 
         const int nrows = P.ny * P.nz;
         const int grid = (nrows + rpw - 1) / rpw;
         const size_t lds = sizeof(T) * 25 * threads;
+        const int st = row_group_tiles(P.ny, rpw, tune.row_group);
+        const bool fast = offsets32<T>(P, tune);
         if (P.cfl_acc) {
             if (threads % 64) return hipErrorInvalidValue;      // fused CFL needs full waves
-            hipLaunchKernelGGL((fluid_x_kernel<T, true, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
-                               row_group_tiles(P.ny, rpw, tune.row_group));
+            if (fast)
+                hipLaunchKernelGGL((fluid_x_kernel<T, true, LIM, FRZ, true>), dim3(grid), dim3(threads), lds, s, P,
+                                   tpr, rpw, st);
+            else
+                hipLaunchKernelGGL((fluid_x_kernel<T, true, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw, st);
         } else {
-            hipLaunchKernelGGL((fluid_x_kernel<T, false, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
-                               row_group_tiles(P.ny, rpw, tune.row_group));
+            if (fast)
+                hipLaunchKernelGGL((fluid_x_kernel<T, false, LIM, FRZ, true>), dim3(grid), dim3(threads), lds, s, P,
+                                   tpr, rpw, st);
+            else
+                hipLaunchKernelGGL((fluid_x_kernel<T, false, LIM, FRZ>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw, st);
         }
     } else {
         const int nd = d == 1 ? P.ny : P.nz;
@@ -1552,8 +1592,11 @@ hipError_t launch_magnetic_lim(const SweepParams<T>& P, int d, const LaunchTunin
         const int nrows = P.ny * P.nz;
         const int grid = (nrows + rpw - 1) / rpw;
         const size_t lds = sizeof(T) * 16 * threads;
-        hipLaunchKernelGGL((mag_x_kernel<T, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
-                           row_group_tiles(P.ny, rpw, tune.row_group));
+        const int st = row_group_tiles(P.ny, rpw, tune.row_group);
+        if (offsets32<T>(P, tune))
+            hipLaunchKernelGGL((mag_x_kernel<T, LIM, true>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw, st);
+        else
+            hipLaunchKernelGGL((mag_x_kernel<T, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw, st);
     } else {
         const int nd = d == 1 ? P.ny : P.nz;
         const int npencil = P.nx * (d == 1 ? P.nz : P.ny);
@@ -1615,13 +1658,21 @@ hipError_t launch_magfluid_lim(const SweepParams<T>& P, int d, const LaunchTunin
         const int nrows = P.ny * P.nz;
         const int grid = (nrows + rpw - 1) / rpw;
         const size_t lds = sizeof(T) * 25 * threads;
+        const int st = row_group_tiles(P.ny, rpw, tune.row_group);
+        const bool fast = offsets32<T>(P, tune);
         if (P.cfl_acc) {
             if (threads % 64) return hipErrorInvalidValue;      // fused CFL needs full waves
-            hipLaunchKernelGGL((magfluid_x_kernel<T, true, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
-                               row_group_tiles(P.ny, rpw, tune.row_group));
+            if (fast)
+                hipLaunchKernelGGL((magfluid_x_kernel<T, true, LIM, true>), dim3(grid), dim3(threads), lds, s, P,
+                                   tpr, rpw, st);
+            else
+                hipLaunchKernelGGL((magfluid_x_kernel<T, true, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw, st);
         } else {
-            hipLaunchKernelGGL((magfluid_x_kernel<T, false, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw,
-                               row_group_tiles(P.ny, rpw, tune.row_group));
+            if (fast)
+                hipLaunchKernelGGL((magfluid_x_kernel<T, false, LIM, true>), dim3(grid), dim3(threads), lds, s, P,
+                                   tpr, rpw, st);
+            else
+                hipLaunchKernelGGL((magfluid_x_kernel<T, false, LIM>), dim3(grid), dim3(threads), lds, s, P, tpr, rpw, st);
         }
     } else {
         if (P.cfl_acc) return hipErrorInvalidValue;
