@@ -295,17 +295,24 @@ __device__ __forceinline__ void signal_speed64(double rho, double mx, double my,
 // FP32 screen of one cell for the fused CFL of the FP32 tier: bounds
 // lb <= speed <= ub of the FP64 signal speed that signal_speed64 finds for
 // the same (float) inputs, and whether the cell is surely physical there
-// (rho > 0, p > 0, everything finite; lb is meaningful only then).  Margins: the pressure of the cell may differ
-// from its FP64 value by dp = 1e-4 (gamma - 1)(|e| + m^2/(2 rho) + |B|^2/2),
-// about 100 times what the FP32 rounding of this expression can do (a few
-// units of 2^-24 of the largest term it cancels), and the other factors
-// by 1e-5 relative (each FP32 operation, the hardware reciprocal included,
-// is within 2^-23).  A cell that is surely physical and whose upper bound is
-// below a speed already found, or below the lower bound of another such
-// cell, cannot be the maximum.
-__device__ __forceinline__ void screen_speed32(float rho, float mx, float my, float mz, float e,
+// (rho > 0, p > 0, everything finite; the bounds are meaningful only then).
+// Margins: the pressure of the cell may differ from its FP64 value by
+// dp = 1e-4 (gamma - 1)(|e| + m^2/(2 rho) + |B|^2/2), about 100 times what
+// the FP32 rounding of this expression can do (a few units of 2^-24 of the
+// largest term it cancels), and the other factors by 1e-5 relative (each
+// FP32 operation, the hardware reciprocal included, is within 2^-23).  A
+// cell that is surely physical and whose upper bound is below a speed
+// already found, or below the lower bound of another such cell, cannot be
+// the maximum.  A non-finite e, m^2 or |B|^2 makes p > dp fail (an infinite
+// or undefined p or dp), so the test p > dp with a finite ub covers every
+// way signal_speed64 can flag the cell.  The upper bound and the two terms
+// of the lower one (am = max |m_d| / rho, xl = the lower speed^2 bound) come
+// from screen_upper32; screen_lower32 finishes the lower bound, which is
+// needed for one cell per lane only.
+__device__ __forceinline__ void screen_upper32(float rho, float mx, float my, float mz, float e,
                                                float bx0, float bx1, float by0, float by1, float bz0,
-                                               float bz1, float gamma, float& lb, float& ub, bool& sure)
+                                               float bz1, float gamma, float& ub, float& am, float& xl,
+                                               bool& sure)
 {
     const float bx = 0.5f * (bx0 + bx1);
     const float by = 0.5f * (by0 + by1);
@@ -316,12 +323,17 @@ __device__ __forceinline__ void screen_speed32(float rho, float mx, float my, fl
     const float ke = 0.5f * mm * inv, me = 0.5f * b2;
     const float p = (gamma - 1.0f) * (e - ke - me);
     const float dp = 1e-4f * (gamma - 1.0f) * (fabsf(e) + ke + me);
-    const float am = fmaxf(fabsf(mx), fmaxf(fabsf(my), fabsf(mz)));
-    const float x = gamma * (fmaxf(p, 0.0f) + dp) + b2;
-    const float xl = fmaxf(gamma * (p - dp) + b2, 0.0f);
-    ub = (am * inv + sqrtf(x * inv)) * 1.00001f;
-    lb = (am * inv + sqrtf(xl * inv)) * 0.99999f;
-    sure = rho > 0.0f && p > dp && isfinite(ub) && isfinite(e) && isfinite(mm) && isfinite(b2);
+    am = fmaxf(fabsf(mx), fmaxf(fabsf(my), fabsf(mz))) * inv;
+    // p > dp for a surely physical cell: no clamping at zero needed
+    const float x = gamma * (p + dp) + b2;
+    xl = (gamma * (p - dp) + b2) * inv;
+    ub = (am + sqrtf(x * inv)) * 1.00001f;
+    sure = rho > 0.0f && p > dp && isfinite(ub);
+}
+
+__device__ __forceinline__ float screen_lower32(float am, float xl)
+{
+    return (am + sqrtf(xl)) * 0.99999f;
 }
 
 }  // namespace mhd

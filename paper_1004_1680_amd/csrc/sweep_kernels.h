@@ -314,16 +314,20 @@ __device__ __forceinline__ void fluid_x_core(const SweepParams<T>& P, const RowT
         if constexpr (sizeof(T) == 4) {
             tslot = __longlong_as_double((long long)__hip_atomic_load(P.cfl_acc + slot, __ATOMIC_RELAXED,
                                                                       __HIP_MEMORY_SCOPE_AGENT));
-            // and the largest lower bound of a surely physical cell of the wave
-            float wlb = 0.0f;
+            // and a lower bound of a surely physical cell of the wave: the
+            // largest over the wave of the lower bound of each lane's cell
+            // with the largest upper bound (any cell's lower bound is a
+            // speed the state reaches)
+            float bub = -1.0f, bam = 0.0f, bxl = 0.0f;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                float lb;
-                screen_speed32(onew[k][0], onew[k][1], onew[k][2], onew[k][3], onew[k][4], fb[k][0], fb[k][1],
-                               fb[k][2], fb[k][3], fb[k][4], fb[k][5], (float)P.gamma, lb, ub[k], sure[k]);
+                float am, xl;
+                screen_upper32(onew[k][0], onew[k][1], onew[k][2], onew[k][3], onew[k][4], fb[k][0], fb[k][1],
+                               fb[k][2], fb[k][3], fb[k][4], fb[k][5], (float)P.gamma, ub[k], am, xl, sure[k]);
                 sure[k] = sure[k] && R.active;
-                if (sure[k]) wlb = fmaxf(wlb, lb);
+                if (sure[k] && ub[k] > bub) { bub = ub[k]; bam = am; bxl = xl; }
             }
+            float wlb = bub >= 0.0f ? screen_lower32(bam, bxl) : 0.0f;
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) wlb = fmaxf(wlb, __shfl_xor(wlb, o, 64));
             thr = fmax(tslot, (double)wlb);
@@ -490,11 +494,12 @@ __global__ void __launch_bounds__(256) fluid_x_kernel(SweepParams<T> P, int tpr,
 // rows P+e and P), the latter for the constraint update of b_x; a plus
 // chain is the own chain of the neighbour row, evaluated identically.
 // Gives the new faces nb = (b_y of P, b_y of P+y, b_z of P, b_z of P+z, b_x
-// of P) of the 4 cells; stores nothing.  A: LDS of 16 values per thread.
+// of P) of the 4 cells; stores nothing.  own (optional): rho and m_x of
+// the thread's 4 cells as loaded.  A: LDS of 16 values per thread.
 // Every thread of the workgroup calls it (it holds barriers).
 template <typename T, int LIM = LIM_VANLEER, bool W32 = false>
 __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThread& R, T (&nb)[5][4],
-                                           T* const A)
+                                           T* const A, T (*own)[4] = nullptr)
 {
     using RA = RowAddr<T, W32>;
     using off = typename RA::off;
@@ -532,6 +537,10 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[r][k] = velocity(m[k], rho[k]);
             v[r][4] = velocity(mn, rhon);
+            if (r == 0 && own) {                  // rho and m_x of the thread's own cells
+#pragma unroll
+                for (int k = 0; k < 4; ++k) { own[0][k] = rho[k]; own[1][k] = m[k]; }
+            }
         }
     }
     // chains: 0 own-y, 1 plus-y, 2 own-z, 3 plus-z
@@ -693,7 +702,8 @@ __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int til
         return;
     }
     T nb[5][4];
-    mag_x_core<T, LIM, W32>(P, R, nb, A);
+    T own[2][4];
+    mag_x_core<T, LIM, W32>(P, R, nb, A, own);
     // new b_x of the first cell -> previous thread
     T* const X = A + 20 * blockDim.x;
     X[R.t] = nb[4][0];
@@ -718,7 +728,20 @@ __device__ __forceinline__ void magfluid_x_tile(const SweepParams<T>& P, int til
             fb[k][4] = nb[2][k]; fb[k][5] = nb[3][k];
         }
     }
-    load_u4<T, W32>(P, R, base, u);
+    // U: rho and m_x as the magnetic part loaded them (the same values; the
+    // reciprocal of rho is then shared), m_y, m_z, e loaded here
+    {
+        T tmp[4];
+#pragma unroll
+        for (int q = 2; q < 5; ++q) {
+            if (R.active) vec4<T>::load(RA::at(P.in[q], base + R.i0), tmp);
+            else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(1);     // as load_u4
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u[k][q] = tmp[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { u[k][0] = own[0][k]; u[k][1] = own[1][k]; }
+    }
     fluid_x_core<T, CFL, LIM, FRZ_STEP, W32>(P, R, base, u, bb, fb, A);
 }
 
