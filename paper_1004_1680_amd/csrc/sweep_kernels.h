@@ -508,7 +508,6 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
     const int nx = P.nx, ny = P.ny, nz = P.nz;
     const int t = R.t, tprev = R.tprev, tnext = R.tnext, i0 = R.i0, y = R.y, z = R.z;
     const bool active = R.active;
-    const int inext = (i0 + 4 == nx) ? 0 : i0 + 4;
     auto rbase = [&](int yy, int zz) -> off {
         return RA::row(nx, ny, wrapi(yy, ny), wrapi(zz, nz));
     };
@@ -524,19 +523,15 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
 #pragma unroll
         for (int r = 0; r < 5; ++r) {
             T rho[4], m[4];
-            T rhon = T(1), mn = T(0);
             if (active) {
                 vec4<T>::load(RA::at(P.in[RHO], rb[r] + i0), rho);
                 vec4<T>::load(RA::at(P.in[MX], rb[r] + i0), m);
-                rhon = *RA::at(P.in[RHO], rb[r] + inext);
-                mn = *RA::at(P.in[MX], rb[r] + inext);
             } else {
                 rho[0] = rho[1] = rho[2] = rho[3] = T(1);
                 m[0] = m[1] = m[2] = m[3] = T(0);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[r][k] = velocity(m[k], rho[k]);
-            v[r][4] = velocity(mn, rhon);
             if (r == 0 && own) {                  // rho and m_x of the thread's own cells
 #pragma unroll
                 for (int k = 0; k < 4; ++k) { own[0][k] = rho[k]; own[1][k] = m[k]; }
@@ -554,17 +549,23 @@ __device__ __forceinline__ void mag_x_core(const SweepParams<T>& P, const RowThr
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) {
             T tmp[4];
-            if (active) {
-                vec4<T>::load(RA::at(P.in[qf[ch]], qb[ch] + i0), tmp);
-                q[ch][4] = *RA::at(P.in[qf[ch]], qb[ch] + inext);
-            } else {
-                tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(0);
-                q[ch][4] = T(0);
-            }
+            if (active) vec4<T>::load(RA::at(P.in[qf[ch]], qb[ch] + i0), tmp);
+            else tmp[0] = tmp[1] = tmp[2] = tmp[3] = T(0);
 #pragma unroll
             for (int k = 0; k < 4; ++k) q[ch][k] = tmp[k];
         }
     }
+    // exchange 0: the next cell's velocities and q (the next thread's first
+    // cell; the row wraps) through LDS rather than loaded and divided again
+#pragma unroll
+    for (int r = 0; r < 5; ++r) A[r * nt + t] = v[r][0];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) A[(5 + ch) * nt + t] = q[ch][0];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 5; ++r) v[r][4] = A[r * nt + tnext];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) q[ch][4] = A[(5 + ch) * nt + tnext];
     T a[4][4], g[4][4];
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
