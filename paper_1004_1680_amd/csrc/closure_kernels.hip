@@ -290,139 +290,169 @@ __device__ __forceinline__ uint4 shift_left1(uint4 p, uint4 c)     // elements p
 }
 
 // Tile of wgrad: 32 (x) x 4 (y) x 2 (z) cells = 8 K steps of 32 cells (one
-// row segment each).  Its input halo is staged channel-major in LDS,
-// x from x0 - 8 to x0 + 40 (aligned groups of 8, so the dx = -1, 0, +1
-// fragments of a group come from three aligned 16-byte reads), y and z one
-// cell each side; the tile's dy rows are staged beside it (channel stride
-// padded by 8 bf16 so the 16 channels of a fragment read spread over the
-// banks).
+// row segment each).
 constexpr int WT_X = 32, WT_Y = 4, WT_Z = 2;
 constexpr int WL_X = WT_X + 16, WL_Y = WT_Y + 2, WL_Z = WT_Z + 2;
 
-// dW[o][ci][co] = sum_cell x[cell + d(o)][ci] dy[cell][co] as MFMA with
-// M = co (A = dy, channel-major), N = ci (B = shifted x), K = cells.  Nine
-// waves: wave w owns the offsets with (dy, dz) = (w % 3 - 1, w / 3 - 1) and
-// all three dx.  Persistent over tiles; each workgroup writes its partial
-// sums, wgrad_reduce adds them in a fixed order.
+// wgrad: dW[o][ci][co] = sum_c x[c + d(o)][ci] dy[c][co]
+//                     = sum_c dy[c - dx][co] x[c + (0, dy, dz)][ci]
+// (the x offset moved onto dy), with M = co (A = dy shifted along x), N = ci
+// (B = x rows, aligned: no shifting), K = cells.  Three waves per
+// workgroup; wave w owns the offsets with dz = w - 1 and all nine (dx, dy),
+// so an A fragment feeds 3 x NBI and a B fragment 3 x MB products.  LDS:
+// x without an x halo, [ci][hz][hy][32], and dy with one, [co][ks][48],
+// channel strides padded by 16 bf16 (75 KB for 32 -> 32 channels).  The
+// elements one before and after a lane's 8 dy values come from the lanes
+// 16 below and above (ds_bpermute) or, at the segment's ends, from the
+// halo.  Persistent over tiles; each workgroup writes its partial sums,
+// wgrad_reduce adds them in a fixed order.  (A first form shifted x and ran
+// nine waves of three offsets each: it read x with halo in all three axes
+// and the dword reads of each shifted fragment's edge elements conflicted
+// in the LDS banks; 315, 271 and 130 us against 238, 123 and 106 us for
+// 32 -> 32, 32 -> 8 and 8 -> 32 channels at 128^3.)
+constexpr int WG_WAVES = 3;
+
 template <int CI, int CO>
-__global__ void __launch_bounds__(576) conv3d_wgrad_kernel(WgradArgs A)
+__global__ void __launch_bounds__(64 * WG_WAVES, (CI * CO > 256 ? 1 : 2)) conv3d_wgrad_kernel(WgradArgs A)
 {
     constexpr int MB = (CO + 15) / 16, NBI = (CI + 15) / 16;
-    // channel strides of the dy rows and of the x tile padded to an odd
-    // multiple of 32 bytes modulo 256: the 16 channels of a fragment read
-    // are then conflict-free (measured; an unpadded 2304-byte stride costs
-    // 8 passes, a 16-byte pad 2)
-    constexpr int KSTEPS = WT_Y * WT_Z, DYS = KSTEPS * WT_X + 16;
-    constexpr int XCS = WL_Z * WL_Y * WL_X + 16;
+    constexpr int KSTEPS = WT_Y * WT_Z;
+    constexpr int XROWS = WL_Z * WL_Y;                       // 4 x 6 rows of x per tile
+    constexpr int XCS = XROWS * WT_X + 16;                   // channel strides, padded as above
+    constexpr int DX = WT_X + 16;                            // dy row with 8 halo cells each side
+    constexpr int DYS = KSTEPS * DX + 16;
+    constexpr int NT = 64 * WG_WAVES;
     __shared__ __align__(16) uint16_t xs[CI * XCS];
     __shared__ __align__(16) uint16_t dys[CO * DYS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
-    const int ddy = wave % 3 - 1, ddz = wave / 3 - 1;
+    const int ddz = wave - 1;
     const int nx = A.n[0], ny = A.n[1], nz = A.n[2];
     const size_t N = (size_t)nx * ny * nz;
     const int tx = nx / WT_X, ty = ny / WT_Y, ntiles = tx * ty * (nz / WT_Z);
 
-    f4 acc[3][MB][NBI];
+    f4 acc[3][3][MB][NBI];                                  // [dx + 1][dy + 1]
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int m = 0; m < MB; ++m)
+        for (int b = 0; b < 3; ++b)
 #pragma unroll
-            for (int q = 0; q < NBI; ++q) acc[d][m][q] = f4{ 0.f, 0.f, 0.f, 0.f };
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int q = 0; q < NBI; ++q) acc[a][b][m][q] = f4{ 0.f, 0.f, 0.f, 0.f };
 
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int x0 = (t % tx) * WT_X, y0 = ((t / tx) % ty) * WT_Y, z0 = (t / (tx * ty)) * WT_Z;
-        // fill x (with halo) and dy of the tile in batches of FB loads per
-        // thread, each batch in flight at once; x item it < XI, dy items after
-        constexpr int XI = CI * WL_Z * WL_Y * (WL_X / 8), DI = CO * KSTEPS * (WT_X / 8), ITEMS = XI + DI;
-        constexpr int FILL = (ITEMS + 575) / 576, FB = FILL < 4 ? FILL : 4;
+        // fill: x rows (ci, hz, hy) of 32 cells = 4 loads of 16 bytes, dy rows
+        // (co, ks) of 48 cells (x0 - 8 .. x0 + 40, periodic) = 6 loads
+        constexpr int XI = CI * XROWS * (WT_X / 8), DI = CO * KSTEPS * (DX / 8), ITEMS = XI + DI;
+        // as many of a thread's loads in flight at once as the registers
+        // allow (the fill waits for one round trip per batch): 24 (all) with
+        // 32 -> 32 channels at one wave per SIMD, 12 at two
+        constexpr int FMAX = CI * CO > 256 ? 24 : 12;
+        constexpr int FILL = (ITEMS + NT - 1) / NT, FB = FILL < FMAX ? FILL : FMAX;
         __syncthreads();                                   // previous tile's reads are done
 #pragma unroll
         for (int f0 = 0; f0 < FILL; f0 += FB) {
             uint4 fv[FB];
 #pragma unroll
             for (int f = 0; f < FB; ++f) {
-                const int it = threadIdx.x + 576 * (f0 + f);
+                const int it = threadIdx.x + NT * (f0 + f);
                 fv[f] = make_uint4(0, 0, 0, 0);
                 if (f0 + f < FILL && it < XI) {
-                    const int gx = it % (WL_X / 8), hy = (it / (WL_X / 8)) % WL_Y;
-                    const int hz = (it / (WL_X / 8 * WL_Y)) % WL_Z, ci = it / (WL_X / 8 * WL_Y * WL_Z);
-                    const int sx = x0 - 8 + 8 * gx, gxs = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
-                    const size_t src = (size_t)ci * N + (size_t)gxs +
+                    const int gx = it % (WT_X / 8), row = (it / (WT_X / 8)) % XROWS, ci = it / (WT_X / 8 * XROWS);
+                    const int hy = row % WL_Y, hz = row / WL_Y;
+                    const size_t src = (size_t)ci * N + (size_t)(x0 + 8 * gx) +
                                        (size_t)nx * ((size_t)wrap1(y0 - 1 + hy, ny) + (size_t)ny * wrap1(z0 - 1 + hz, nz));
                     fv[f] = ld16(A.xT + src);
                 } else if (f0 + f < FILL && it < ITEMS) {
-                    const int d = it - XI, gg = d % (WT_X / 8), ks = (d / (WT_X / 8)) % KSTEPS;
-                    const int co = d / (WT_X / 8 * KSTEPS);
-                    const size_t src = (size_t)co * N + (size_t)(x0 + 8 * gg) +
+                    const int d = it - XI, gx = d % (DX / 8), ks = (d / (DX / 8)) % KSTEPS;
+                    const int co = d / (DX / 8 * KSTEPS);
+                    const int sx = x0 - 8 + 8 * gx, gxs = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+                    const size_t src = (size_t)co * N + (size_t)gxs +
                                        (size_t)nx * ((size_t)(y0 + ks % WT_Y) + (size_t)ny * (z0 + ks / WT_Y));
                     fv[f] = ld16(A.dyT + src);
                 }
             }
 #pragma unroll
             for (int f = 0; f < FB; ++f) {
-                const int it = threadIdx.x + 576 * (f0 + f);
+                const int it = threadIdx.x + NT * (f0 + f);
                 if (f0 + f < FILL && it < XI) {
-                    const int gx = it % (WL_X / 8), hy = (it / (WL_X / 8)) % WL_Y;
-                    const int hz = (it / (WL_X / 8 * WL_Y)) % WL_Z, ci = it / (WL_X / 8 * WL_Y * WL_Z);
-                    *reinterpret_cast<uint4*>(xs + ci * XCS + (hz * WL_Y + hy) * WL_X + 8 * gx) = fv[f];
+                    const int gx = it % (WT_X / 8), row = (it / (WT_X / 8)) % XROWS, ci = it / (WT_X / 8 * XROWS);
+                    *reinterpret_cast<uint4*>(xs + ci * XCS + row * WT_X + 8 * gx) = fv[f];
                 } else if (f0 + f < FILL && it < ITEMS) {
-                    const int d = it - XI, gg = d % (WT_X / 8), ks = (d / (WT_X / 8)) % KSTEPS;
-                    const int co = d / (WT_X / 8 * KSTEPS);
-                    *reinterpret_cast<uint4*>(dys + co * DYS + ks * WT_X + 8 * gg) = fv[f];
+                    const int d = it - XI, gx = d % (DX / 8), ks = (d / (DX / 8)) % KSTEPS;
+                    const int co = d / (DX / 8 * KSTEPS);
+                    *reinterpret_cast<uint4*>(dys + co * DYS + ks * DX + 8 * gx) = fv[f];
                 }
             }
         }
         __syncthreads();
-#pragma unroll 2
+#pragma unroll 1
         for (int ks = 0; ks < KSTEPS; ++ks) {
             const int ky = ks % WT_Y, kz = ks / WT_Y;
-            bf16x8 af[MB];                                 // dy: 8 cells of one row segment per lane
+            // A: dy of channel co = 16 m + r, cells 8 g .. 8 g + 7 of the row,
+            // shifted by -dx
+            bf16x8 af[3][MB];
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
                 const int co = 16 * m + r;
-                af[m] = as_bf8(co < CO ? *reinterpret_cast<const uint4*>(dys + co * DYS + ks * WT_X + 8 * g)
-                                       : make_uint4(0, 0, 0, 0));
+                const uint16_t* row = dys + (co < CO ? co : 0) * DYS + ks * DX;
+                uint4 mid = *reinterpret_cast<const uint4*>(row + 8 + 8 * g);
+                // the row's halo element before (g = 0: cell -1) or after
+                // (g = 3: cell 32) the lane's segment
+                const uint32_t halo = *reinterpret_cast<const uint32_t*>(row + (g == 3 ? 40 : 6));
+                const uint32_t pw = (uint32_t)__shfl((int)mid.w, lane - 16, 64);
+                const uint32_t nw = (uint32_t)__shfl((int)mid.x, lane + 16, 64);
+                const uint32_t prev = g == 0 ? halo : pw;       // its high half: cell 8 g - 1
+                const uint32_t next = g == 3 ? halo : nw;       // its low half: cell 8 g + 8
+                if (co >= CO) mid = make_uint4(0, 0, 0, 0);
+                const uint32_t prevv = co < CO ? prev : 0u, nextv = co < CO ? next : 0u;
+                af[0][m] = as_bf8(shift_right1(mid, make_uint4(nextv, 0, 0, 0)));   // dx = -1: dy at c + 1
+                af[1][m] = as_bf8(mid);                                             // dx = 0
+                af[2][m] = as_bf8(shift_left1(make_uint4(0, 0, 0, prevv), mid));    // dx = +1: dy at c - 1
             }
 #pragma unroll
-            for (int q = 0; q < NBI; ++q) {
-                const int ci = 16 * q + r;
-                uint4 lo = make_uint4(0, 0, 0, 0), mid = lo, hi = lo;
-                if (ci < CI) {
-                    const uint16_t* row = xs + ci * XCS + ((kz + 1 + ddz) * WL_Y + ky + 1 + ddy) * WL_X + 8 * g;
-                    lo = *reinterpret_cast<const uint4*>(row);
-                    mid = *reinterpret_cast<const uint4*>(row + 8);
-                    hi = *reinterpret_cast<const uint4*>(row + 16);
-                }
-                const bf16x8 bm = as_bf8(shift_left1(lo, mid)), b0 = as_bf8(mid), bp = as_bf8(shift_right1(mid, hi));
+            for (int b = 0; b < 3; ++b) {                  // dy = b - 1
+                bf16x8 bf[NBI];
 #pragma unroll
-                for (int m = 0; m < MB; ++m) {
-                    acc[0][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bm, acc[0][m][q], 0, 0, 0);
-                    acc[1][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], b0, acc[1][m][q], 0, 0, 0);
-                    acc[2][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[m], bp, acc[2][m][q], 0, 0, 0);
+                for (int q = 0; q < NBI; ++q) {
+                    const int ci = 16 * q + r;
+                    bf[q] = as_bf8(ci < CI ? *reinterpret_cast<const uint4*>(
+                                                 xs + ci * XCS + ((kz + 1 + ddz) * WL_Y + ky + b) * WT_X + 8 * g)
+                                           : make_uint4(0, 0, 0, 0));
                 }
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int m = 0; m < MB; ++m)
+#pragma unroll
+                        for (int q = 0; q < NBI; ++q)
+                            acc[a][b][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a][m], bf[q], acc[a][b][m][q],
+                                                                                      0, 0, 0);
             }
         }
     }
     // D[co][ci] of offset o: lane holds co = 16 m + 4 g + e, ci = 16 q + r
     float* out = A.partial + (size_t)blockIdx.x * 27 * CI * CO;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int o = (ddz + 1) * 9 + (ddy + 1) * 3 + d;
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int m = 0; m < MB; ++m)
+        for (int b = 0; b < 3; ++b) {
+            const int o = (ddz + 1) * 9 + b * 3 + a;
 #pragma unroll
-            for (int q = 0; q < NBI; ++q) {
-                const int ci = 16 * q + r;
-                if (ci >= CI) continue;
+            for (int m = 0; m < MB; ++m)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int co = 16 * m + 4 * g + e;
-                    if (co < CO) out[((size_t)o * CI + ci) * CO + co] = acc[d][m][q][e];
+                for (int q = 0; q < NBI; ++q) {
+                    const int ci = 16 * q + r;
+                    if (ci >= CI) continue;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int co = 16 * m + 4 * g + e;
+                        if (co < CO) out[((size_t)o * CI + ci) * CO + co] = acc[a][b][m][q][e];
+                    }
                 }
-            }
-    }
+        }
 }
 
 // dw[i] = sum over workgroups of partial[wg][i] in workgroup order: pass 1
@@ -498,14 +528,15 @@ hipError_t launch_conv3d_wgrad(const WgradArgs& A, int cin, int cout, float* dw,
 {
     int tpw = 0;
     const int nwg = wgrad_blocks(A.n, tpw);
+    constexpr int T2 = 64 * WG_WAVES;
     if (cin == 8 && cout == 32)
-        hipLaunchKernelGGL((conv3d_wgrad_kernel<8, 32>), dim3(nwg), dim3(576), 0, s, A);
+        hipLaunchKernelGGL((conv3d_wgrad_kernel<8, 32>), dim3(nwg), dim3(T2), 0, s, A);
     else if (cin == 32 && cout == 32)
-        hipLaunchKernelGGL((conv3d_wgrad_kernel<32, 32>), dim3(nwg), dim3(576), 0, s, A);
+        hipLaunchKernelGGL((conv3d_wgrad_kernel<32, 32>), dim3(nwg), dim3(T2), 0, s, A);
     else if (cin == 32 && cout == 8)
-        hipLaunchKernelGGL((conv3d_wgrad_kernel<32, 8>), dim3(nwg), dim3(576), 0, s, A);
+        hipLaunchKernelGGL((conv3d_wgrad_kernel<32, 8>), dim3(nwg), dim3(T2), 0, s, A);
     else if (cin == 8 && cout == 8)
-        hipLaunchKernelGGL((conv3d_wgrad_kernel<8, 8>), dim3(nwg), dim3(576), 0, s, A);
+        hipLaunchKernelGGL((conv3d_wgrad_kernel<8, 8>), dim3(nwg), dim3(T2), 0, s, A);
     else
         return hipErrorInvalidValue;
     const int count = 27 * cin * cout;

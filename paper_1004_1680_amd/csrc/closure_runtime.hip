@@ -328,6 +328,7 @@ extern "C" int mhd_closure_step(mhd_closure* c, mhd_ctx* coarse, double cfl)
     if (mhd_internal_stream(coarse) != c->stream)
         return mhd_fail(MHD_EINVAL, "closure and coarse handle must share a stream");
     if ((r = mhd_step_auto(coarse, cfl))) return r;
+    if ((r = mhd_internal_gather_first(coarse))) return r;
     int all0 = 0;
     float* u = (float*)mhd_internal_state(coarse, &all0);
     if (!all0) return mhd_fail(MHD_ESTATE, "coarse state not in its first buffer");

@@ -960,6 +960,22 @@ void* mhd_internal_state(mhd_ctx* h, int* all_in_first_buffer)
     *all_in_first_buffer = all;
     return h->buf[0];
 }
+
+// Bring every field into the first buffer (a device copy on the handle's
+// stream for each field held in the second), so that the state is one
+// contiguous array.  After a step the fields need not share a buffer: the
+// fused middle of a step writes b once for two magnetic operators.
+int mhd_internal_gather_first(mhd_ctx* h)
+{
+    for (int q = 0; q < 8; ++q) {
+        if (h->cur[q] == 0) continue;
+        HIP_TRY(h, hipMemcpyAsync((char*)h->buf[0] + (size_t)q * h->N * h->esize,
+                                  (const char*)h->buf[1] + (size_t)q * h->N * h->esize, h->N * h->esize,
+                                  hipMemcpyDeviceToDevice, h->stream));
+        h->cur[q] = 0;
+    }
+    return MHD_OK;
+}
 int mhd_internal_prec(const mhd_ctx* h) { return h->prec; }
 void mhd_internal_dims(const mhd_ctx* h, int n[3]) { n[0] = h->n[0]; n[1] = h->n[1]; n[2] = h->n[2]; }
 hipStream_t mhd_internal_stream(const mhd_ctx* h) { return h->stream; }

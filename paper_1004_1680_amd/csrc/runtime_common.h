@@ -18,6 +18,7 @@ int mhd_fail(int code, const char* fmt, ...);
 // Internal accessors of a single-grid handle (used by the closure runtime).
 struct mhd_ctx;
 void* mhd_internal_state(mhd_ctx* h, int* all_in_first_buffer);  // buffer 0 base
+int mhd_internal_gather_first(mhd_ctx* h);     // every field into buffer 0 (stream-ordered copies)
 int mhd_internal_prec(const mhd_ctx* h);
 void mhd_internal_dims(const mhd_ctx* h, int n[3]);
 hipStream_t mhd_internal_stream(const mhd_ctx* h);
