@@ -331,11 +331,16 @@ __global__ void __launch_bounds__(64 * WG_WAVES, (CI * CO > 256 ? 1 : 2)) conv3d
     const size_t N = (size_t)nx * ny * nz;
     const int tx = nx / WT_X, ty = ny / WT_Y, ntiles = tx * ty * (nz / WT_Z);
 
-    f4 acc[3][3][MB][NBI];                                  // [dx + 1][dy + 1]
+    // 8 channels of dy (x) fill only half of an MFMA block's rows (columns):
+    // there the rows (columns) carry (channel, dx) ((channel, dy)) pairs,
+    // 8 channels x 2 offsets per block, two blocks for the three offsets
+    constexpr bool FM = CO == 8 && CI > 8, FN = CI == 8 && CO > 8;
+    constexpr int AN = FM ? 2 : 3, BN = FN ? 2 : 3;
+    f4 acc[AN][BN][MB][NBI];                                // [dx + 1][dy + 1], or the folded blocks
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < AN; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
+        for (int b = 0; b < BN; ++b)
 #pragma unroll
             for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -391,12 +396,12 @@ __global__ void __launch_bounds__(64 * WG_WAVES, (CI * CO > 256 ? 1 : 2)) conv3d
 #pragma unroll 1
         for (int ks = 0; ks < KSTEPS; ++ks) {
             const int ky = ks % WT_Y, kz = ks / WT_Y;
-            // A: dy of channel co = 16 m + r, cells 8 g .. 8 g + 7 of the row,
-            // shifted by -dx
-            bf16x8 af[3][MB];
+            // A: dy of channel co = 16 m + r (FM: r mod 8), cells 8 g .. 8 g + 7
+            // of the row, shifted by -dx
+            bf16x8 af[AN][MB];
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
-                const int co = 16 * m + r;
+                const int co = FM ? (r & 7) : 16 * m + r;
                 const uint16_t* row = dys + (co < CO ? co : 0) * DYS + ks * DX;
                 uint4 mid = *reinterpret_cast<const uint4*>(row + 8 + 8 * g);
                 // the row's halo element before (g = 0: cell -1) or after
@@ -408,51 +413,81 @@ __global__ void __launch_bounds__(64 * WG_WAVES, (CI * CO > 256 ? 1 : 2)) conv3d
                 const uint32_t next = g == 3 ? halo : nw;       // its low half: cell 8 g + 8
                 if (co >= CO) mid = make_uint4(0, 0, 0, 0);
                 const uint32_t prevv = co < CO ? prev : 0u, nextv = co < CO ? next : 0u;
-                af[0][m] = as_bf8(shift_right1(mid, make_uint4(nextv, 0, 0, 0)));   // dx = -1: dy at c + 1
-                af[1][m] = as_bf8(mid);                                             // dx = 0
-                af[2][m] = as_bf8(shift_left1(make_uint4(0, 0, 0, prevv), mid));    // dx = +1: dy at c - 1
+                const uint4 sm1 = shift_right1(mid, make_uint4(nextv, 0, 0, 0));   // dx = -1: dy at c + 1
+                const uint4 sp1 = shift_left1(make_uint4(0, 0, 0, prevv), mid);    // dx = +1: dy at c - 1
+                if constexpr (FM) {
+                    // rows r < 8: dx = -1 | +1, rows r >= 8: dx = 0 | none
+                    af[0][m] = as_bf8(r < 8 ? sm1 : mid);
+                    af[1][m] = as_bf8(r < 8 ? sp1 : make_uint4(0, 0, 0, 0));
+                } else {
+                    af[0][m] = as_bf8(sm1);
+                    af[1][m] = as_bf8(mid);
+                    af[2][m] = as_bf8(sp1);
+                }
             }
+            if constexpr (FN) {
+                // columns r < 8: dy = -1 | +1, columns r >= 8: dy = 0 | none
+                bf16x8 bf[2];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {                  // dy = b - 1
-                bf16x8 bf[NBI];
-#pragma unroll
-                for (int q = 0; q < NBI; ++q) {
-                    const int ci = 16 * q + r;
-                    bf[q] = as_bf8(ci < CI ? *reinterpret_cast<const uint4*>(
-                                                 xs + ci * XCS + ((kz + 1 + ddz) * WL_Y + ky + b) * WT_X + 8 * g)
-                                           : make_uint4(0, 0, 0, 0));
+                for (int j = 0; j < 2; ++j) {
+                    const int b = 2 * j + (r >> 3), ci = r & 7;
+                    bf[j] = as_bf8(b < 3 ? *reinterpret_cast<const uint4*>(
+                                               xs + ci * XCS + ((kz + 1 + ddz) * WL_Y + ky + b) * WT_X + 8 * g)
+                                         : make_uint4(0, 0, 0, 0));
                 }
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
+                for (int a = 0; a < AN; ++a)
 #pragma unroll
-                    for (int m = 0; m < MB; ++m)
+                    for (int j = 0; j < 2; ++j)
 #pragma unroll
-                        for (int q = 0; q < NBI; ++q)
-                            acc[a][b][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a][m], bf[q], acc[a][b][m][q],
+                        for (int m = 0; m < MB; ++m)
+                            acc[a][j][m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a][m], bf[j], acc[a][j][m][0],
                                                                                       0, 0, 0);
+            } else {
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {              // dy = b - 1
+                    bf16x8 bf[NBI];
+#pragma unroll
+                    for (int q = 0; q < NBI; ++q) {
+                        const int ci = 16 * q + r;
+                        bf[q] = as_bf8(ci < CI ? *reinterpret_cast<const uint4*>(
+                                                     xs + ci * XCS + ((kz + 1 + ddz) * WL_Y + ky + b) * WT_X + 8 * g)
+                                               : make_uint4(0, 0, 0, 0));
+                    }
+#pragma unroll
+                    for (int a = 0; a < AN; ++a)
+#pragma unroll
+                        for (int m = 0; m < MB; ++m)
+#pragma unroll
+                            for (int q = 0; q < NBI; ++q)
+                                acc[a][b][m][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a][m], bf[q],
+                                                                                          acc[a][b][m][q], 0, 0, 0);
+                }
             }
         }
     }
-    // D[co][ci] of offset o: lane holds co = 16 m + 4 g + e, ci = 16 q + r
+    // D of an MFMA block: lane holds rows 4 g + e (e = 0..3), column r;
+    // unfolded, row = co - 16 m and column = ci - 16 q
     float* out = A.partial + (size_t)blockIdx.x * 27 * CI * CO;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < AN; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const int o = (ddz + 1) * 9 + b * 3 + a;
+        for (int b = 0; b < BN; ++b)
 #pragma unroll
             for (int m = 0; m < MB; ++m)
 #pragma unroll
-                for (int q = 0; q < NBI; ++q) {
-                    const int ci = 16 * q + r;
-                    if (ci >= CI) continue;
+                for (int q = 0; q < NBI; ++q)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const int co = 16 * m + 4 * g + e;
-                        if (co < CO) out[((size_t)o * CI + ci) * CO + co] = acc[a][b][m][q][e];
+                        const int row = 4 * g + e;
+                        const int co = FM ? (row & 7) : 16 * m + row;
+                        const int dxi = FM ? 2 * a + (row >> 3) : a;            // dx + 1
+                        const int ci = FN ? (r & 7) : 16 * q + r;
+                        const int dyi = FN ? 2 * b + (r >> 3) : b;              // dy + 1
+                        if (co >= CO || ci >= CI || dxi > 2 || dyi > 2) continue;
+                        const int o = (ddz + 1) * 9 + dyi * 3 + dxi;
+                        out[((size_t)o * CI + ci) * CO + co] = acc[a][b][m][q][e];
                     }
-                }
-        }
 }
 
 // dw[i] = sum over workgroups of partial[wg][i] in workgroup order: pass 1

@@ -71,7 +71,7 @@ def test_conv_dgrad_parity(env, cin, cout):
     assert err < 1e-5
 
 
-@pytest.mark.parametrize("cin,cout", [(8, 32), (32, 32), (32, 8)])
+@pytest.mark.parametrize("cin,cout", [(8, 32), (32, 32), (32, 8), (8, 8)])
 def test_conv_wgrad_parity(env, cin, cout):
     torch, mhd = env
     say(f"case: conv wgrad {cin}->{cout}")
