@@ -103,10 +103,14 @@ class PairSet:
         self.items.extend(other.items)
 
 
-def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print, rollout=False):
+def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print, rollout=False, deadline=None):
     """training pairs from fine trajectories of the Orszag-Tang family (one
     per seed), as a PairSet; cl: the Closure of the coarse grid, whose
-    residual kernel forms the targets.
+    residual kernel forms the targets.  Within a trajectory the restricted
+    state that ends one pair starts the next and is stored once.
+
+    deadline: a time.perf_counter() value after which no further pair is
+    generated (the pairs so far are returned).
 
     rollout: also pairs whose input is the state of a plain coarse run
     started from the restricted initial state and stepped with the same
@@ -120,13 +124,20 @@ def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print,
     Rr = mhd.Solver((nc,) * 3, prec="f32", stream=stream) if rollout else None
     pairs = PairSet(cl, nc, stream)
     for sd in seeds:
+        if deadline is not None and time.perf_counter() > deadline:
+            log(f"[closure] time budget reached before seed {sd}: {len(pairs)} pairs")
+            break
         F.set_state_tensor(I.orszag_tang_torch((nf,) * 3, seed=sd))
         t = 0.0
         roll_alive = rollout
+        u_ref = None
         for k in range(steps_per_traj):
+            if deadline is not None and time.perf_counter() > deadline:
+                log(f"[closure] time budget reached at seed {sd}, coarse step {k}: {len(pairs)} pairs")
+                break
             try:
                 F.restrict_to(C)
-                u_c = C.get_state_tensor().clone()
+                u_c = C.get_state_tensor().clone() if u_ref is None else u_ref
                 dtc = C.cfl_dt(cfl)
                 c = C.relaxation_speed()
                 nfine = advance_to(F, t + 2.0 * dtc, cfl, t0=t)
@@ -474,24 +485,45 @@ def load(path, n, stream=None):
 
 def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, steps_per_traj=24,
                   val_steps=None, epochs=10, lr=1e-3, cfl=0.7, scale_mode="family", log=print,
-                  weighting="global", gate=False, short_seeds=(), short_steps=0, rollout=False):
+                  weighting="global", gate=False, short_seeds=(), short_steps=0, rollout=False,
+                  init=None, budget_s=None):
     """data generation and training; returns (closure, scales, info).
     short_seeds / short_steps: further trajectories of short_steps pairs
-    each, which weight the early, smooth part of the flow more."""
+    each, which weight the early, smooth part of the flow more.
+
+    init: a closure saved by save() to continue from: its parameters,
+      scales and gate are kept (not fitted again) and training goes on over
+      the new pairs (Adam's moments start from zero); its metadata's pair
+      count is carried into pairs_total, so a training set larger than one
+      run can generate is covered in several runs over disjoint seeds.
+    budget_s: seconds from the start after which no further training pair
+      is generated (the validation pairs come first)."""
     import torch
     stream = torch.cuda.current_stream()
     nc = nf // r
     cl = mhd.Closure((nc,) * 3, stream=stream)
     t0 = time.perf_counter()
-    pairs = generate_pairs(cl, nf, r, train_seeds, steps_per_traj, stream, cfl, log, rollout)
-    if short_seeds and short_steps:
-        pairs.extend(generate_pairs(cl, nf, r, short_seeds, short_steps, stream, cfl, log))
+    deadline = None if budget_s is None else t0 + budget_s
     val = generate_pairs(cl, nf, r, (val_seed,), val_steps or steps_per_traj, stream, cfl, log)
+    pairs = generate_pairs(cl, nf, r, train_seeds, steps_per_traj, stream, cfl, log, rollout, deadline)
+    if short_seeds and short_steps:
+        pairs.extend(generate_pairs(cl, nf, r, short_seeds, short_steps, stream, cfl, log, deadline=deadline))
     _sync(torch)
     t_data = time.perf_counter() - t0
-    scales = fit_scales(cl, pairs, scale_mode)
-    R = fit_gate(cl, pairs) if gate else None
-    cl.set_params(init_params(0))
+    log(f"[closure] {len(pairs)} training and {len(val)} validation pairs in {t_data:.1f} s")
+    before = {}
+    if init is not None:
+        z = np.load(init, allow_pickle=False)
+        before = json.loads(str(z["meta"]))
+        if (before.get("nf"), before.get("ratio")) != (nf, r):
+            raise ValueError(f"{init} was trained for nf={before.get('nf')}, ratio={before.get('ratio')}")
+        scales = (z["in_mean"], z["in_std"], z["out_scale"], z["target_scale"])
+        R = z["gate"] if z["gate"].size == 8 else None
+        cl.set_params(z["params"])
+    else:
+        scales = fit_scales(cl, pairs, scale_mode)
+        R = fit_gate(cl, pairs) if gate else None
+        cl.set_params(init_params(0))
     cl.set_scales(*scales)
     cl.set_gate(R)
     val_loss0 = float(np.mean([cl.grad(u, t)[0] for u, t in val]))
@@ -506,7 +538,10 @@ def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, st
             "pairs": len(pairs), "data_s": t_data, "train_s": t_train, "epochs": epochs, "lr": lr,
             "train_steps": epochs * len(pairs), "val_loss_untrained": val_loss0, "history": hist,
             "val_field_residual": fe.tolist(), "scale_mode": scale_mode, "weighting": weighting,
-            "gate": None if R is None else R.tolist(), "rollout": rollout}
+            "gate": None if R is None else np.asarray(R).tolist(), "rollout": rollout,
+            "pairs_total": before.get("pairs_total", before.get("pairs", 0)) + len(pairs),
+            "runs": before.get("runs", []) + [{"seeds": list(train_seeds) + list(short_seeds), "pairs": len(pairs),
+                                               "epochs": epochs, "lr": lr}]}
     del pairs, val
     return cl, scales, info
 
@@ -543,6 +578,9 @@ if __name__ == "__main__":
     t.add_argument("--short-steps", type=int, default=0)
     t.add_argument("--rollout", action="store_true",
                    help="also pairs from plain coarse rollouts (the states a rollout visits)")
+    t.add_argument("--seed-start", type=int, default=1, help="first training seed")
+    t.add_argument("--init", default=None, help="continue from this saved closure (its scales and gate kept)")
+    t.add_argument("--budget-s", type=float, default=None, help="stop generating training pairs after this")
     t.add_argument("--out", required=True, help=".npz file for the trained closure")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
@@ -554,12 +592,14 @@ if __name__ == "__main__":
     import torch
     stream = torch.cuda.current_stream()
     if args.cmd == "train":
-        cl, scales, info = train_closure(args.nf, args.ratio, tuple(range(1, args.seeds + 1)),
+        s0 = args.seed_start
+        cl, scales, info = train_closure(args.nf, args.ratio, tuple(range(s0, s0 + args.seeds)),
                                          steps_per_traj=args.steps, val_steps=args.val_steps,
                                          epochs=args.epochs, lr=args.lr, log=say,
                                          weighting=args.weighting, gate=args.gate,
-                                         short_seeds=tuple(range(args.seeds + 1, args.seeds + 1 + args.short_seeds)),
-                                         short_steps=args.short_steps, rollout=args.rollout)
+                                         short_seeds=tuple(range(s0 + args.seeds, s0 + args.seeds + args.short_seeds)),
+                                         short_steps=args.short_steps, rollout=args.rollout,
+                                         init=args.init, budget_s=args.budget_s)
         save(args.out, cl, scales, info, info["gate"])
         print(json.dumps(info))
     else:
@@ -569,6 +609,6 @@ if __name__ == "__main__":
         cl, scales, meta = load(args.weights, (nf // r,) * 3, stream)
         cks = [int(v) for v in args.checkpoints.split(",") if v] or None
         res = evaluate(cl, nf, r, args.seed, args.steps, torch, stream, log=say, checkpoints=cks)
-        res["training"] = {k: meta[k] for k in ("pairs", "epochs", "train_steps", "data_s", "train_s")
-                           if k in meta}
+        res["training"] = {k: meta[k] for k in ("pairs", "pairs_total", "runs", "epochs", "train_steps",
+                                                "data_s", "train_s") if k in meta}
         print(json.dumps(res))
