@@ -300,7 +300,9 @@ __device__ __forceinline__ void signal_speed64(double rho, double mx, double my,
 // dp = 1e-4 (gamma - 1)(|e| + m^2/(2 rho) + |B|^2/2), about 100 times what
 // the FP32 rounding of this expression can do (a few units of 2^-24 of the
 // largest term it cancels), and the other factors by 1e-5 relative (each
-// FP32 operation, the hardware reciprocal included, is within 2^-23).  A
+// FP32 operation, the hardware reciprocal and square root included, is
+// within 2^-23; square roots of arguments below 2^-96 are not taken, the
+// bounds use 2^-48 above and 0 below instead).  A
 // cell that is surely physical and whose upper bound is below a speed
 // already found, or below the lower bound of another such cell, cannot be
 // the maximum.  A non-finite e, m^2 or |B|^2 makes p > dp fail (an infinite
@@ -309,6 +311,15 @@ __device__ __forceinline__ void signal_speed64(double rho, double mx, double my,
 // of the lower one (am = max |m_d| / rho, xl = the lower speed^2 bound) come
 // from screen_upper32; screen_lower32 finishes the lower bound, which is
 // needed for one cell per lane only.
+__device__ __forceinline__ float sqrt_above32(float y)
+{
+    return y < 0x1p-96f ? 0x1p-48f : __builtin_amdgcn_sqrtf(y);
+}
+__device__ __forceinline__ float sqrt_below32(float y)
+{
+    return y < 0x1p-96f ? 0.0f : __builtin_amdgcn_sqrtf(y);
+}
+
 __device__ __forceinline__ void screen_upper32(float rho, float mx, float my, float mz, float e,
                                                float bx0, float bx1, float by0, float by1, float bz0,
                                                float bz1, float gamma, float& ub, float& am, float& xl,
@@ -327,13 +338,13 @@ __device__ __forceinline__ void screen_upper32(float rho, float mx, float my, fl
     // p > dp for a surely physical cell: no clamping at zero needed
     const float x = gamma * (p + dp) + b2;
     xl = (gamma * (p - dp) + b2) * inv;
-    ub = (am + sqrtf(x * inv)) * 1.00001f;
+    ub = (am + sqrt_above32(x * inv)) * 1.00001f;
     sure = rho > 0.0f && p > dp && isfinite(ub);
 }
 
 __device__ __forceinline__ float screen_lower32(float am, float xl)
 {
-    return (am + sqrtf(xl)) * 0.99999f;
+    return (am + sqrt_below32(xl)) * 0.99999f;
 }
 
 }  // namespace mhd
