@@ -75,6 +75,7 @@ class PairSet:
         self.cl = cl
         self.C = mhd.Solver((nc,) * 3, prec="f32", stream=stream)
         self.items = []
+        self.seeds = []          # trajectories that gave at least one pair
 
     def add(self, u_c, u_ref, dt, c):
         self.items.append((u_c, u_ref, dt, c))
@@ -101,6 +102,7 @@ class PairSet:
 
     def extend(self, other):
         self.items.extend(other.items)
+        self.seeds.extend(other.seeds)
 
 
 def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print, rollout=False, deadline=None):
@@ -150,6 +152,8 @@ def generate_pairs(cl, nf, r, seeds, steps_per_traj, stream, cfl=0.7, log=print,
             F.restrict_to(C)
             u_ref = C.get_state_tensor().clone()
             pairs.add(u_c, u_ref, dtc, c)
+            if not pairs.seeds or pairs.seeds[-1] != sd:
+                pairs.seeds.append(sd)
             if roll_alive:
                 if k == 0:
                     Rr.set_state_tensor(u_c)
@@ -511,6 +515,8 @@ def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, st
     _sync(torch)
     t_data = time.perf_counter() - t0
     log(f"[closure] {len(pairs)} training and {len(val)} validation pairs in {t_data:.1f} s")
+    if len(pairs) == 0:
+        raise ValueError("no training pairs were generated (time budget or trajectories too short)")
     before = {}
     if init is not None:
         z = np.load(init, allow_pickle=False)
@@ -533,14 +539,19 @@ def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, st
     t_train = time.perf_counter() - t0
     fe = field_errors(cl, val)
     log("[closure] validation one-step residual ratio per field: " + " ".join(f"{v:.3f}" for v in fe))
+    # the same on up to 32 training pairs spread over the set (below 1 there
+    # but not on the validation pairs: the fit does not carry over)
+    idx = np.unique(np.linspace(0, len(pairs) - 1, min(32, len(pairs))).astype(int))
+    fe_tr = field_errors(cl, (pairs[int(i)] for i in idx))
+    log("[closure] training-pair one-step residual ratio per field: " + " ".join(f"{v:.3f}" for v in fe_tr))
     info = {"nf": nf, "ratio": r, "train_seeds": list(train_seeds), "steps_per_traj": steps_per_traj,
             "short_seeds": list(short_seeds), "short_steps": short_steps,
             "pairs": len(pairs), "data_s": t_data, "train_s": t_train, "epochs": epochs, "lr": lr,
             "train_steps": epochs * len(pairs), "val_loss_untrained": val_loss0, "history": hist,
-            "val_field_residual": fe.tolist(), "scale_mode": scale_mode, "weighting": weighting,
+            "val_field_residual": fe.tolist(), "train_field_residual": fe_tr.tolist(), "scale_mode": scale_mode, "weighting": weighting,
             "gate": None if R is None else np.asarray(R).tolist(), "rollout": rollout,
             "pairs_total": before.get("pairs_total", before.get("pairs", 0)) + len(pairs),
-            "runs": before.get("runs", []) + [{"seeds": list(train_seeds) + list(short_seeds), "pairs": len(pairs),
+            "runs": before.get("runs", []) + [{"seeds": list(pairs.seeds), "pairs": len(pairs),
                                                "epochs": epochs, "lr": lr}]}
     del pairs, val
     return cl, scales, info
