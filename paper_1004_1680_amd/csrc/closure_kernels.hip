@@ -292,7 +292,7 @@ __device__ __forceinline__ uint4 shift_left1(uint4 p, uint4 c)     // elements p
 // Tile of wgrad: 32 (x) x 4 (y) x 2 (z) cells = 8 K steps of 32 cells (one
 // row segment each).
 constexpr int WT_X = 32, WT_Y = 4, WT_Z = 2;
-constexpr int WL_X = WT_X + 16, WL_Y = WT_Y + 2, WL_Z = WT_Z + 2;
+constexpr int WL_Y = WT_Y + 2, WL_Z = WT_Z + 2;          // x rows with their y / z halo
 
 // wgrad: dW[o][ci][co] = sum_c x[c + d(o)][ci] dy[c][co]
 //                     = sum_c dy[c - dx][co] x[c + (0, dy, dz)][ci]
@@ -304,11 +304,12 @@ constexpr int WL_X = WT_X + 16, WL_Y = WT_Y + 2, WL_Z = WT_Z + 2;
 // channel strides padded by 16 bf16 (75 KB for 32 -> 32 channels).  The
 // elements one before and after a lane's 8 dy values come from the lanes
 // 16 below and above (ds_bpermute) or, at the segment's ends, from the
-// halo.  Persistent over tiles; each workgroup writes its partial sums,
+// halo.  With 8 channels on one side a 16-row (16-column) block carries two
+// offsets.  Persistent over tiles; each workgroup writes its partial sums,
 // wgrad_reduce adds them in a fixed order.  (A first form shifted x and ran
 // nine waves of three offsets each: it read x with halo in all three axes
 // and the dword reads of each shifted fragment's edge elements conflicted
-// in the LDS banks; 315, 271 and 130 us against 238, 123 and 106 us for
+// in the LDS banks; 315, 271 and 130 us against 236, 110 and 100 us for
 // 32 -> 32, 32 -> 8 and 8 -> 32 channels at 128^3.)
 constexpr int WG_WAVES = 3;
 
