@@ -496,10 +496,12 @@ def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, st
     each, which weight the early, smooth part of the flow more.
 
     init: a closure saved by save() to continue from: its parameters,
-      scales and gate are kept (not fitted again) and training goes on over
-      the new pairs (Adam's moments start from zero); its metadata's pair
-      count is carried into pairs_total, so a training set larger than one
-      run can generate is covered in several runs over disjoint seeds.
+      scales and gate are kept (not fitted again; scale_mode and gate are
+      then those it was saved with) and training goes on over the new pairs
+      (Adam's moments start from zero); its metadata's pair count is carried
+      into pairs_total, so a training set larger than one run can generate
+      is covered in several runs over disjoint seeds.  val_loss_untrained
+      is then the validation loss of the loaded parameters.
     budget_s: seconds from the start after which no further training pair
       is generated (the validation pairs come first)."""
     import torch
@@ -525,6 +527,7 @@ def train_closure(nf=256, r=8, train_seeds=tuple(range(1, 13)), val_seed=100, st
             raise ValueError(f"{init} was trained for nf={before.get('nf')}, ratio={before.get('ratio')}")
         scales = (z["in_mean"], z["in_std"], z["out_scale"], z["target_scale"])
         R = z["gate"] if z["gate"].size == 8 else None
+        scale_mode = before.get("scale_mode", scale_mode)
         cl.set_params(z["params"])
     else:
         scales = fit_scales(cl, pairs, scale_mode)
