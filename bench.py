@@ -414,6 +414,9 @@ def run_ensemble(args, wl, torch, mhd):
         log(f"[bench] box {i} ({n}^3, Mach {m:.2f}, beta {b:.2f}) resident")
     log("[bench] autotune")
     shape = autotune.tune_batch(B, args.cfl, use_cache=False)
+    if args.middle:
+        B.set_launch(mhd.MHD_BATCH_MIDDLE, args.middle)
+    shape["middle"] = B.launch(mhd.MHD_BATCH_MIDDLE)
     log(f"[bench] launch shape {shape}; warm-up")
     B.run(args.warmup, args.cfl, graph=True)
     B.status(raise_on_nonphysical=False)
@@ -429,10 +432,13 @@ def run_ensemble(args, wl, torch, mhd):
     value = ncell * args.steps / el / 1e6
     step_alg = STEP_WORDS * 4 * ncell / (ms_per_step * 1e-3) / 1e9
     fused = shape["reverse"] == 1
+    middle = fused and shape["middle"] == 1
     # bytes of the launches a step runs: 6 or 3 split operator pairs, 0 or 3
-    # fused reverse pairs (each box's CFL maximum is found by the last launch)
+    # fused reverse pairs (each box's CFL maximum is found by the last launch);
+    # the middle M_z M_z F_z in one launch drops the forward M_z's bytes
     nsplit = 3 if fused else 6
-    split = (nsplit * (ALG_WORDS["fluid"] + ALG_WORDS["magnetic"]) + (6 - nsplit) * ALG_WORDS["pair"]) * 4 * ncell
+    split = (nsplit * (ALG_WORDS["fluid"] + ALG_WORDS["magnetic"]) + (6 - nsplit) * ALG_WORDS["pair"]
+             - (ALG_WORDS["magnetic"] if middle else 0)) * 4 * ncell
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "Mcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -441,7 +447,8 @@ def run_ensemble(args, wl, torch, mhd):
         "config": {"workload": wl["desc"], "boxes": len(dims), "cells": ncell, "cfl": args.cfl,
                    "limiter": args.limiter, "launch": shape, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm",
-                     "kernel": "whole step (" + ("3 split pairs, 3 fused reverse pairs" if fused
+                     "kernel": "whole step (" + ("5 forward operators, M_z M_z F_z in one launch, 2 fused reverse pairs"
+                                                 if middle else "3 split pairs, 3 fused reverse pairs" if fused
                                                  else "12 split operators") + ", per-box CFL in the last launch)",
                      "achieved": round(split / (ms_per_step * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",

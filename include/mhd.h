@@ -292,12 +292,15 @@ int mhd_batch_time(mhd_batch *b, double *times);
  * reverse-half pair M_d F_d in one launch, 2: the two operators in turn,
  * 0: built-in, 1 in FP32 with the van Leer or minmod limiter, 2 otherwise),
  * the target march chunk of the
- * fused pairs (MHD_BATCH_PAIR_CHUNK, default 128), and MHD_BATCH_WIDE_OFFSETS
- * as MHD_TUNE_WIDE_OFFSETS.
+ * fused pairs (MHD_BATCH_PAIR_CHUNK, default 128), MHD_BATCH_WIDE_OFFSETS
+ * as MHD_TUNE_WIDE_OFFSETS, and MHD_BATCH_MIDDLE as MHD_TUNE_MIDDLE (1: M_z
+ * M_z F_z in one launch, on the fused pairs' work list; 2: M_z and the z
+ * pair; 0: built-in, 1 where the boxes hold 128^3 cells or more on average,
+ * in FP32 with fused pairs and van Leer's limiter).
  * Launch-shape parameters, not part of the method. */
 enum { MHD_BATCH_GRID_X = 10, MHD_BATCH_GRID_Y = 11, MHD_BATCH_GRID_Z = 12,
        MHD_BATCH_CHUNK = 13, MHD_BATCH_REVERSE = 14, MHD_BATCH_WIDE_OFFSETS = 15,
-       MHD_BATCH_PAIR_CHUNK = 16 };
+       MHD_BATCH_PAIR_CHUNK = 16, MHD_BATCH_MIDDLE = 17 };
 int mhd_batch_set_launch(mhd_batch *b, int key, int value);
 int mhd_batch_get_launch(const mhd_batch *b, int key, int *value);
 

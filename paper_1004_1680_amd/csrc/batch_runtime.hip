@@ -6,8 +6,10 @@
 // the 12 operators, each ONE persistent launch over the (box, tile) work
 // items of its direction, and the per-box time advance.  Every field is
 // written 6 times per step, so after a full step the state is back in the
-// first buffer: the captured HIP graph of one step can be replayed for any
-// number of steps.
+// buffer it started in, and the captured HIP graph of one step can be
+// replayed for any number of steps.  With the middle M_z M_z F_z in one
+// launch the face fields are written 5 times per step: they alternate
+// between the buffers (cur), and the captured graph holds two steps.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -51,6 +53,7 @@ struct mhd_batch {
     int chunk_target;
     int pair_chunk_target;
     int rev_mode;           // reverse-half pairs M_d F_d: 0 built-in, 1 one launch each, 2 two
+    int mid_mode;           // M_z M_z F_z: 0 built-in, 1 one launch, 2 M_z and the z pair
     int limiter;            // slope limiter of the operators (MHD_LIMITER_*)
     // fused CFL: the last launch of a step leaves each box's FP64 maximum
     // signal speed in cfl_acc (CFL_ACC_SLOTS + 1 words per box); acc_valid
@@ -62,6 +65,8 @@ struct mhd_batch {
     hipGraphExec_t exec;
     double graph_cfl;
     bool graph_valid;
+    int graph_steps;        // steps in the captured graph (1, or 2 with the fused middle)
+    int graph_bpar;         // buffer of the face fields when the graph starts
     bool failed;
 };
 
@@ -190,6 +195,7 @@ extern "C" mhd_batch* mhd_batch_create(int nbox, const int* dims, double gamma, 
     b->chunk_target = 64;
     b->pair_chunk_target = 128;
     b->rev_mode = 0;
+    b->mid_mode = 0;
     b->limiter = MHD_LIMITER_VANLEER;
     b->wide = false;
     b->d_boxes = nullptr;
@@ -203,6 +209,7 @@ extern "C" mhd_batch* mhd_batch_create(int nbox, const int* dims, double gamma, 
     b->d_cfl_items = nullptr; b->d_item_first = nullptr;
     b->partial = nullptr; b->partial_bad = nullptr;
     b->graph = nullptr; b->exec = nullptr; b->graph_valid = false;
+    b->graph_steps = 1; b->graph_bpar = 0;
     b->failed = false;
     for (int q = 0; q < 8; ++q) b->cur[q] = 0;
     if (hipGetDevice(&b->device) != hipSuccess) {
@@ -307,8 +314,13 @@ extern "C" int mhd_batch_set_state(mhd_batch* b, int box, const double* host, si
     HIP_TRY(b, hipSetDevice(b->device));
     b->acc_valid = false;         // the fused CFL maxima describe the old state
     const size_t N = bd.ncell;
+    // the fluid fields (0-4) and the face fields (5-7) each lie contiguously
+    // in the buffer that holds them now
+    const int bu = b->cur[0], bf = b->cur[5];
     if (b->prec == MHD_F64) {
-        HIP_TRY(b, hipMemcpyAsync(box_field<double>(b, box, 0, 0), host, 8 * N * sizeof(double),
+        HIP_TRY(b, hipMemcpyAsync(box_field<double>(b, box, 0, bu), host, 5 * N * sizeof(double),
+                                  hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(b, hipMemcpyAsync(box_field<double>(b, box, 5, bf), host + 5 * N, 3 * N * sizeof(double),
                                   hipMemcpyHostToDevice, b->stream));
     } else {
         double* stage = nullptr;
@@ -318,7 +330,9 @@ extern "C" int mhd_batch_set_state(mhd_batch* b, int box, const double* host, si
         }
         hipError_t e = hipMemcpyAsync(stage, host, 8 * N * sizeof(double), hipMemcpyHostToDevice, b->stream);
         if (e == hipSuccess)
-            e = launch_convert_in<float>(stage, box_field<float>(b, box, 0, 0), 8 * N, b->stream);
+            e = launch_convert_in<float>(stage, box_field<float>(b, box, 0, bu), 5 * N, b->stream);
+        if (e == hipSuccess)
+            e = launch_convert_in<float>(stage + 5 * N, box_field<float>(b, box, 5, bf), 3 * N, b->stream);
         const hipError_t e2 = hipStreamSynchronize(b->stream);
         (void)hipFree(stage);
         HIP_TRY(b, e);
@@ -341,8 +355,11 @@ extern "C" int mhd_batch_get_state(mhd_batch* b, int box, double* host, size_t n
     if (n != 8 * (size_t)bd.ncell) return mhd_fail(MHD_EINVAL, "state size %zu != 8 * cells of box", n);
     HIP_TRY(b, hipSetDevice(b->device));
     const size_t N = bd.ncell;
+    const int bu = b->cur[0], bf = b->cur[5];
     if (b->prec == MHD_F64) {
-        HIP_TRY(b, hipMemcpyAsync(host, box_field<double>(b, box, 0, 0), 8 * N * sizeof(double),
+        HIP_TRY(b, hipMemcpyAsync(host, box_field<double>(b, box, 0, bu), 5 * N * sizeof(double),
+                                  hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(b, hipMemcpyAsync(host + 5 * N, box_field<double>(b, box, 5, bf), 3 * N * sizeof(double),
                                   hipMemcpyDeviceToHost, b->stream));
         HIP_TRY(b, hipStreamSynchronize(b->stream));
         return MHD_OK;
@@ -352,7 +369,8 @@ extern "C" int mhd_batch_get_state(mhd_batch* b, int box, double* host, size_t n
         (void)hipGetLastError();
         return mhd_fail(MHD_ENOMEM, "staging allocation failed");
     }
-    hipError_t e = launch_convert_out<float>(box_field<float>(b, box, 0, 0), stage, 8 * N, b->stream);
+    hipError_t e = launch_convert_out<float>(box_field<float>(b, box, 0, bu), stage, 5 * N, b->stream);
+    if (e == hipSuccess) e = launch_convert_out<float>(box_field<float>(b, box, 5, bf), stage + 5 * N, 3 * N, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host, stage, 8 * N * sizeof(double), hipMemcpyDeviceToHost, b->stream);
     const hipError_t e2 = hipStreamSynchronize(b->stream);
@@ -369,6 +387,20 @@ static bool batch_pairs_fused(const mhd_batch* b)
     return b->rev_mode == 1 ||
            (b->rev_mode == 0 && b->prec == MHD_F32 &&
             (b->limiter == MHD_LIMITER_VANLEER || b->limiter == MHD_LIMITER_MINMOD));
+}
+
+// the middle of a step M_z M_z F_z in one launch: with fused pairs, FP32 and
+// van Leer's limiter, as for a single grid; built in from 128^3 cells per box
+// on average
+static bool batch_mid_fused(const mhd_batch* b)
+{
+    if (!batch_pairs_fused(b) || b->prec != MHD_F32 || b->limiter != MHD_LIMITER_VANLEER) return false;
+    if (b->mid_mode == 0) {
+        unsigned long long cells = 0;
+        for (const BoxDesc& bd : b->boxes) cells += bd.ncell;
+        return cells >= (unsigned long long)b->boxes.size() * 128ull * 128 * 128;
+    }
+    return b->mid_mode == 1;
 }
 
 template <typename T>
@@ -392,19 +424,22 @@ static int enqueue_batch_step(mhd_batch* b, double cfl)
                                          { 1, 2 }, { 0, 2 }, { 1, 1 }, { 0, 1 }, { 1, 0 }, { 0, 0 } };
     static const int fused[9][2] = { { 0, 0 }, { 1, 0 }, { 0, 1 }, { 1, 1 }, { 0, 2 }, { 1, 2 },
                                      { 2, 2 }, { 2, 1 }, { 2, 0 } };
-    const bool fz = batch_pairs_fused(b);
-    const int nops = fz ? 9 : 12;
+    // op 3: the middle M_z M_z F_z in one launch
+    static const int middle[8][2] = { { 0, 0 }, { 1, 0 }, { 0, 1 }, { 1, 1 }, { 0, 2 }, { 3, 2 }, { 2, 1 }, { 2, 0 } };
+    const bool fz = batch_pairs_fused(b), mid = fz && batch_mid_fused(b);
+    const int nops = mid ? 8 : fz ? 9 : 12;
     for (int k = 0; k < nops; ++k) {
-        const int op = fz ? fused[k][0] : separate[k][0];
-        const int d = fz ? fused[k][1] : separate[k][1];
+        const int op = mid ? middle[k][0] : fz ? fused[k][0] : separate[k][0];
+        const int d = mid ? middle[k][1] : fz ? fused[k][1] : separate[k][1];
         BatchParams<T> P;
         for (int q = 0; q < 8; ++q) {
             P.in_base[q] = reinterpret_cast<const T*>(b->buf[b->cur[q]]);
             P.out_base[q] = reinterpret_cast<T*>(b->buf[1 - b->cur[q]]);
         }
         P.boxes = b->d_boxes;
-        // the fused pairs along y and z have work lists of their own chunks
-        const bool pl = op == 2 && d > 0;
+        // the fused pairs along y and z (and the middle) have work lists of
+        // their own chunks
+        const bool pl = (op == 2 || op == 3) && d > 0;
         P.items = pl ? b->d_pitems[d] : b->d_items[d];
         P.nitems = pl ? b->npitems[d] : b->nitems[d];
         P.gamma = (T)b->gamma;
@@ -462,10 +497,19 @@ extern "C" int mhd_batch_run(mhd_batch* b, double cfl, int nsteps, int use_graph
         --nsteps;
     }
     if (nsteps == 0) return MHD_OK;
-    if (!b->graph_valid || b->graph_cfl != cfl) {
-        drop_graph(b);
+    // with the fused middle a step moves the face fields to the other
+    // buffer: the graph holds two steps and starts from one buffer of them
+    const int gs = batch_mid_fused(b) ? 2 : 1;
+    if (b->graph_valid && (b->graph_cfl != cfl || b->graph_steps != gs)) drop_graph(b);
+    if (gs == 2 && b->graph_valid && b->cur[5] != b->graph_bpar) {
+        if ((r = enqueue_step(b, cfl))) return r;
+        if (--nsteps == 0) return MHD_OK;
+    }
+    if (!b->graph_valid) {
+        const int bpar = b->cur[5];
         HIP_TRY(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         r = enqueue_step(b, cfl);
+        if (!r && gs == 2) r = enqueue_step(b, cfl);
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(b->stream, &g);
         if (r) {
@@ -476,9 +520,12 @@ extern "C" int mhd_batch_run(mhd_batch* b, double cfl, int nsteps, int use_graph
         b->graph = g;
         HIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         b->graph_cfl = cfl;
+        b->graph_steps = gs;
+        b->graph_bpar = bpar;
         b->graph_valid = true;
     }
-    for (int s = 0; s < nsteps; ++s) HIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+    for (; nsteps >= gs; nsteps -= gs) HIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+    if (nsteps > 0 && (r = enqueue_step(b, cfl))) return r;       // the odd last step
     return MHD_OK;
 }
 
@@ -551,6 +598,13 @@ extern "C" int mhd_batch_set_launch(mhd_batch* b, int key, int value)
         drop_graph(b);
         return MHD_OK;
     }
+    if (key == MHD_BATCH_MIDDLE) {
+        if (value < 0 || value > 2)
+            return mhd_fail(MHD_EINVAL, "middle-of-step choice must be 0, 1 or 2 (got %d)", value);
+        b->mid_mode = value;
+        drop_graph(b);
+        return MHD_OK;
+    }
     return mhd_fail(MHD_EINVAL, "unknown launch key %d", key);
 }
 
@@ -587,6 +641,8 @@ extern "C" int mhd_batch_get_launch(const mhd_batch* b, int key, int* value)
         *value = batch_pairs_fused(b) ? 1 : 2;
     else if (key == MHD_BATCH_WIDE_OFFSETS)
         *value = b->wide ? 1 : 0;
+    else if (key == MHD_BATCH_MIDDLE)
+        *value = batch_mid_fused(b) ? 1 : 2;
     else
         return mhd_fail(MHD_EINVAL, "unknown launch key %d", key);
     return MHD_OK;

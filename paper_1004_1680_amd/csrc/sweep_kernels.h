@@ -1787,11 +1787,12 @@ __device__ __forceinline__ SweepParams<T> box_params(const BatchParams<T>& B, in
     return P;
 }
 
-// op 0 fluid, 1 magnetic, 2 the fused reverse-half pair (magnetic then fluid)
+// op 0 fluid, 1 magnetic, 2 the fused reverse-half pair (magnetic then
+// fluid), 3 the middle of a step M_z M_z F_z (z only, one wave per SIMD)
 template <typename T, int OP>
 constexpr int batch_waves(int d)
 {
-    return d == 0 ? 1 : (OP == 2 ? magfluid_waves<T>() : march_waves<T>());
+    return d == 0 ? 1 : (OP == 3 ? 1 : OP == 2 ? magfluid_waves<T>() : march_waves<T>());
 }
 
 // W32: every box's fields have 32-bit byte offsets (see Addr)
@@ -1823,8 +1824,10 @@ __global__ void __launch_bounds__(256, (batch_waves<T, OP>(D))) batch_sweep_kern
                 fluid_march_lane<T, D, W32, LIM>(P, gid, bd.chunk[D]);
             else if constexpr (OP == 1)
                 mag_march_lane<T, D, W32, LIM>(P, gid, bd.chunk[D]);
-            else
+            else if constexpr (OP == 2)
                 magfluid_march_lane<T, D, W32, LIM>(P, gid, bd.pchunk[D]);
+            else
+                magmagfluid_march_lane<T, D, W32, LIM>(P, gid, bd.pchunk[D]);   // the pairs' work list
         }
     }
 }
@@ -1856,13 +1859,19 @@ static void launch_batch_op_lim(const BatchParams<T>& B, int op, int d, int grid
 {
     if (op == 0) launch_batch_op_dir<T, 0, LIM>(B, d, grid, lds, s);
     else if (op == 1) launch_batch_op_dir<T, 1, LIM>(B, d, grid, lds, s);
-    else launch_batch_op_dir<T, 2, LIM>(B, d, grid, lds, s);
+    else if (op == 2) launch_batch_op_dir<T, 2, LIM>(B, d, grid, lds, s);
+    else if constexpr (sizeof(T) == 4 && LIM == LIM_VANLEER) {
+        // the middle: z only, FP32, van Leer's limiter (the single grid's rules)
+        if (B.offsets32) hipLaunchKernelGGL((batch_sweep_kernel<T, 3, 2, true, LIM>), dim3(grid), dim3(256), 0, s, B);
+        else hipLaunchKernelGGL((batch_sweep_kernel<T, 3, 2, false, LIM>), dim3(grid), dim3(256), 0, s, B);
+    }
 }
 
 template <typename T>
 hipError_t launch_batch_op(const BatchParams<T>& B, int op, int d, int grid, hipStream_t s)
 {
     if (B.cfl_acc && (d != 0 || op == 1)) return hipErrorInvalidValue;   // only x fluid / x pair
+    if (op == 3 && (d != 2 || sizeof(T) != 4 || B.limiter != LIM_VANLEER)) return hipErrorInvalidValue;
     const size_t lds = d == 0 ? sizeof(T) * (op == 1 ? 16 : 25) * 256 : 0;
     switch (B.limiter) {
     case LIM_VANLEER: launch_batch_op_lim<T, LIM_VANLEER>(B, op, d, grid, lds, s); break;

@@ -22,7 +22,7 @@ MHD_TUNE_CHUNK_Y, MHD_TUNE_CHUNK_Z, MHD_TUNE_REVERSE = 1, 2, 3
 MHD_TUNE_PAIR_CHUNK_Y, MHD_TUNE_PAIR_CHUNK_Z, MHD_TUNE_WIDE_OFFSETS = 4, 5, 6
 MHD_TUNE_MIDDLE, MHD_TUNE_MIDDLE_CHUNK, MHD_TUNE_ROW_GROUP = 7, 8, 9
 MHD_BATCH_GRID_X, MHD_BATCH_GRID_Y, MHD_BATCH_GRID_Z, MHD_BATCH_CHUNK = 10, 11, 12, 13
-MHD_BATCH_REVERSE, MHD_BATCH_WIDE_OFFSETS, MHD_BATCH_PAIR_CHUNK = 14, 15, 16
+MHD_BATCH_REVERSE, MHD_BATCH_WIDE_OFFSETS, MHD_BATCH_PAIR_CHUNK, MHD_BATCH_MIDDLE = 14, 15, 16, 17
 MHD_LIMITER_VANLEER, MHD_LIMITER_MINMOD, MHD_LIMITER_MC, MHD_LIMITER_SUPERBEE = 0, 1, 2, 3
 MHD_FREEZE_STEP, MHD_FREEZE_CELL, MHD_FREEZE_PENCIL = 0, 1, 2
 

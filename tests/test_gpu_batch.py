@@ -85,6 +85,64 @@ def test_batch_reverse_pairs_fused_or_separate(M, prec):
     B.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_middle_in_one_launch(M, graph):
+    """the middle of a step M_z M_z F_z as one launch over the pairs' work
+    list: every box equals its single-grid run (which at these sizes runs M_z
+    and the z pair), with the shortest and a longer pair chunk"""
+    say(f"case: batch middle in one launch, graph={graph}")
+    ss = states(DIMS)
+    ref, rtimes = single_runs(M, DIMS, ss, "f32", 3)
+    for pchunk in (8, 32):
+        B = M.Batch(DIMS, prec="f32")
+        assert B.launch(M.MHD_BATCH_MIDDLE) == 2          # built in: boxes below 128^3 on average
+        B.set_launch(M.MHD_BATCH_MIDDLE, 1)
+        assert B.launch(M.MHD_BATCH_MIDDLE) == 1
+        B.set_launch(M.MHD_BATCH_PAIR_CHUNK, pchunk)
+        for i, s in enumerate(ss):
+            B.set_state(i, s)
+        B.run(3, graph=graph)
+        steps, nonphys = B.status()
+        assert list(steps) == [3] * len(DIMS) and not nonphys.any()
+        for i in range(len(DIMS)):
+            assert np.array_equal(B.get_state(i), ref[i]), (pchunk, i)
+        assert np.array_equal(B.times(), np.array(rtimes))
+        B.close()
+    T = M.Batch(DIMS, prec="f64")
+    T.set_launch(M.MHD_BATCH_MIDDLE, 1)
+    assert T.launch(M.MHD_BATCH_MIDDLE) == 2              # FP32 only
+    T.close()
+
+
+def test_batch_middle_odd_step_counts(M):
+    """with the fused middle the face fields change buffer every step and the
+    captured graph holds two steps: runs of 1, 2 and 3 steps in turn (eager
+    steps realign the buffers around graph replays) and a state set between
+    them all match single grids"""
+    say("case: batch middle, odd step counts")
+    ss = states(DIMS)
+    ref, rtimes = single_runs(M, DIMS, ss, "f32", 6)
+    B = M.Batch(DIMS, prec="f32")
+    B.set_launch(M.MHD_BATCH_MIDDLE, 1)
+    for i, s in enumerate(ss):
+        B.set_state(i, s)
+    B.run(1, graph=True)
+    B.run(2, graph=True)
+    B.run(3, graph=True)
+    steps, nonphys = B.status()
+    assert list(steps) == [6] * len(DIMS) and not nonphys.any()
+    for i in range(len(DIMS)):
+        assert np.array_equal(B.get_state(i), ref[i]), i
+    assert np.array_equal(B.times(), np.array(rtimes))
+    # a box set afresh at an odd buffer phase starts from its new state
+    ref1, _ = single_runs(M, DIMS[:1], ss[:1], "f32", 1)
+    B.run(1, graph=True)
+    B.set_state(0, ss[0])
+    B.run(1, graph=True)
+    assert np.array_equal(B.get_state(0), ref1[0])
+    B.close()
+
+
 @pytest.mark.parametrize("grid,chunk,pchunk", [(8, 8, 256), (64, 16, 8), (1024, 64, 128), (2048, 256, 32)])
 def test_batch_launch_shape_invariance(M, grid, chunk, pchunk):
     say(f"case: batch launch grid={grid} chunk={chunk} pair chunk={pchunk}")
