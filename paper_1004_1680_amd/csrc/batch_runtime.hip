@@ -119,7 +119,13 @@ static int build_lists(mhd_batch* b)
             const long lanes = (long)bd.n[0] * (d == 1 ? bd.n[2] : bd.n[1]) * (bd.n[d] / bd.chunk[d]);
             bd.ntile[d] = (int)((lanes + 255) / 256);
         }
-        for (int d = 0; d < 3; ++d)
+        // x tiles in the single-grid visit order (groups of rows along y, one
+        // group per z in turn), so the rows z +- 1 a tile reads were read a
+        // few items earlier on the same XCD
+        const int st = row_group_tiles(bd.n[1], bd.rpw, 0);
+        const int ty = bd.n[1] / bd.rpw;
+        for (int t = 0; t < bd.ntile[0]; ++t) items[0].push_back(make_int2(i, row_tile(t, st, ty, bd.n[2])));
+        for (int d = 1; d < 3; ++d)
             for (int t = 0; t < bd.ntile[d]; ++t) items[d].push_back(make_int2(i, t));
         for (int d = 1; d < 3; ++d) {
             const long lanes = (long)bd.n[0] * (d == 1 ? bd.n[2] : bd.n[1]) * (bd.n[d] / bd.pchunk[d]);

@@ -66,6 +66,28 @@ inline int row_group_tiles(int ny, int rows_per_wg, int max_rows)
     return st;
 }
 
+// Visit order of the row tiles of an x sweep (the single-grid kernels and
+// the ensembles' work lists).  A tile holds rows_per_wg
+// consecutive rows along y at one z; tile L covers rows L * rows_per_wg ..
+// of the flattened (z, y) index, ty = ny / rows_per_wg tiles per y line.
+// Visit o goes to groups of st tiles along y, one group per z in turn, so
+// the rows z - 1 and z + 1 that a tile reads belong to tiles st positions
+// before and after it, which the same XCD (consecutive visits share one,
+// see xcd_tile) holds in its L2; in the linear order they are a whole y
+// line of tiles away.  Rows y +- 1 at a group's edge are read twice.  A
+// bijection of [0, ty * nz) when st divides ty; st <= 0 or st >= ty keeps
+// the linear order.
+__host__ __device__ inline int row_tile(int o, int st, int ty, int nz)
+{
+    if (st <= 0 || st >= ty) return o;
+    const int per_col = st * nz;
+    const int c = o / per_col;
+    const int rem = o - c * per_col;
+    const int z = rem / st;
+    return z * ty + c * st + (rem - z * st);
+}
+
+
 // ---------------------------------------------------------------------------
 // Batched ensembles: boxes of different sizes in one pair of buffers.  Box b
 // holds its 8 fields contiguously (field-major, x fastest) at element
