@@ -11,8 +11,9 @@ device, problem and precision.
   middle of a step (M_z M_z F_z) when it is on (the x sweeps hold whole
   rows and have no shape to choose);
 * batched ensemble: the persistent grid of the operator launches, the
-  target march chunk and whether the reverse-half pairs run fused (fused
-  pairs pay a 13-cell warm-up per chunk, heavy for small boxes).
+  target march chunk, whether the reverse-half pairs run fused (fused
+  pairs pay a 13-cell warm-up per chunk, heavy for small boxes) and, fused,
+  their chunk and whether the middle M_z M_z F_z runs as one launch.
 
 The state is saved before tuning and restored afterwards, so tuning does not
 advance the simulation.
