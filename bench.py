@@ -312,8 +312,9 @@ def time_components(S, n, prec, stream, reps, torch, mhd):
 
 def step_launches(S, n, esize, fused, w32, lim=0, middle=False):
     """(kernel name, grid threads) of every sweep launch of one step of an
-    n^3 grid, in the profiler's naming (the sweep kernels carry the slope
-    limiter as their last template argument)"""
+    n^3 grid, in the profiler's naming: the template arguments as the
+    demangled names print them (the slope limiter; the fluid kernels' freezing
+    speed, 0 for the step's; the 32-bit offsets flag of the x kernels last)"""
     t = "double" if esize == 8 else "float"
     tpr = n // 4
     rpw = max(1, 256 // tpr)
@@ -323,24 +324,24 @@ def step_launches(S, n, esize, fused, w32, lim=0, middle=False):
         lanes = n * n * (n // chunk)
         return -(-lanes // 256) * 256
 
-    fx = (f"fluid_x_kernel<{t}, false, {lim}>", xgrid)
-    mx = (f"mag_x_kernel<{t}, {lim}>", xgrid)
-    fy = (f"fluid_march_kernel<{t}, 1, {w32}, {lim}>", march(S.chunk(1)))
+    fx = (f"fluid_x_kernel<{t}, false, {lim}, 0, {w32}>", xgrid)
+    mx = (f"mag_x_kernel<{t}, {lim}, {w32}>", xgrid)
+    fy = (f"fluid_march_kernel<{t}, 1, {w32}, {lim}, 0>", march(S.chunk(1)))
     my = (f"mag_march_kernel<{t}, 1, {w32}, {lim}>", march(S.chunk(1)))
-    fz = (f"fluid_march_kernel<{t}, 2, {w32}, {lim}>", march(S.chunk(2)))
+    fz = (f"fluid_march_kernel<{t}, 2, {w32}, {lim}, 0>", march(S.chunk(2)))
     mz = (f"mag_march_kernel<{t}, 2, {w32}, {lim}>", march(S.chunk(2)))
     if middle:
         from paper_1004_1680_amd import mhd
         return [fx, mx, fy, my, fz,
                 (f"magmagfluid_march_kernel<{t}, 2, {w32}, {lim}>", march(S.launch(mhd.MHD_TUNE_MIDDLE_CHUNK))),
                 (f"magfluid_march_kernel<{t}, 1, {w32}, {lim}>", march(S.pair_chunk(1))),
-                (f"magfluid_x_kernel<{t}, true, {lim}>", xgrid)]
+                (f"magfluid_x_kernel<{t}, true, {lim}, {w32}>", xgrid)]
     if fused:
         return [fx, mx, fy, my, fz, mz,
                 (f"magfluid_march_kernel<{t}, 2, {w32}, {lim}>", march(S.pair_chunk(2))),
                 (f"magfluid_march_kernel<{t}, 1, {w32}, {lim}>", march(S.pair_chunk(1))),
-                (f"magfluid_x_kernel<{t}, true, {lim}>", xgrid)]
-    return [fx, mx, fy, my, fz, mz, mz, fz, my, fy, mx, (f"fluid_x_kernel<{t}, true, {lim}>", xgrid)]
+                (f"magfluid_x_kernel<{t}, true, {lim}, {w32}>", xgrid)]
+    return [fx, mx, fy, my, fz, mz, mz, fz, my, fy, mx, (f"fluid_x_kernel<{t}, true, {lim}, 0, {w32}>", xgrid)]
 
 
 def cpu_baseline(wl, reps=3):
@@ -1010,12 +1011,17 @@ def main():
     w32 = "true" if ncell * esize <= 2 ** 32 else "false"
     axis = dom.split("_")[1][0]
     cfl_x = dom.endswith("+cfl")
-    # the sweep kernels carry the slope limiter as a last template argument
-    lt = f", {lim}"
-    tname = {"x": ("{op}_x_kernel<{t}, " + ("true" if cfl_x else "false") + "{lt}>") if op != "magnetic"
-             else "mag_x_kernel<{t}{lt}>",
-             "y": "{op}_march_kernel<{t}, 1, {w}{lt}>", "z": "{op}_march_kernel<{t}, 2, {w}{lt}>"}[axis].format(
-        op=kname, t="double" if esize == 8 else "float", w=w32, lt=lt)
+    # the profiler's names (as in step_launches): the slope limiter, the
+    # fluid kernels' freezing speed (0), the x kernels' 32-bit offsets flag
+    t = "double" if esize == 8 else "float"
+    cf = "true" if cfl_x else "false"
+    if axis == "x":
+        tname = {"fluid": f"fluid_x_kernel<{t}, {cf}, {lim}, 0, {w32}>",
+                 "magnetic": f"mag_x_kernel<{t}, {lim}, {w32}>",
+                 "pair": f"magfluid_x_kernel<{t}, {cf}, {lim}, {w32}>"}[op]
+    else:
+        dd = 1 if axis == "y" else 2
+        tname = f"{kname}_march_kernel<{t}, {dd}, {w32}, {lim}" + (", 0>" if op == "fluid" else ">")
     if tname in tmap:
         traffic = tmap[tname]
     step_alg = STEP_WORDS * esize * ncell / (ms_per_step * 1e-3) / 1e9

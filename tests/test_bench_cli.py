@@ -41,3 +41,23 @@ def test_cpu_baseline_reports_median_model_and_threads():
     model, threads, avail = bench.cpu_info()
     assert out["cores"] == threads >= 1 and out["cpu_model"] == model
     assert out["single_thread"]["cores"] == 1
+
+
+def test_step_launch_names_are_the_profilers():
+    """the kernel names bench.py looks up in a traffic summary (every launch
+    of a step, each workload's launch mix) are those the profiler printed in
+    the committed 512^3 summary"""
+    import re
+    sys.path.insert(0, ROOT)
+    import bench
+    text = open(os.path.join(ROOT, "profiles", "sweeps_ot512_fp32_hbm_traffic.md")).read()
+    names = set(re.findall(r"^traffic_bytes\[([^\]@]+?)\]", text, re.M))
+
+    class S:
+        def chunk(self, d): return 256
+        def pair_chunk(self, d): return 256
+        def launch(self, k): return 512
+
+    for fused, middle in ((True, True), (True, False)):
+        for name, _ in bench.step_launches(S(), 512, 4, fused, "true", 0, middle):
+            assert name in names, name
